@@ -1,0 +1,218 @@
+/*
+ * ooc.h -- C ABI of the out-of-core tiled stencil loop-chain library (gfx950).
+ *
+ * The interface follows the structured-mesh abstraction of the paper's
+ * Section 3: a block (the grid, ooc_create), datasets on it (ooc_decl_field),
+ * stencils (per-argument offset lists) and parallel loops over an iteration
+ * range with read / write / read-write access (ooc_par_loop).  Data is only
+ * reachable through opaque handles, and only calls that return data to the
+ * caller (ooc_reduce, ooc_fetch_field, ooc_execute) end the lazily queued
+ * loop chain (Section 3).  Execution of a chain follows the explicitly managed
+ * tiling of Section 4 (Algorithm 1, with the optimisations of Section 4.1).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns int: OOC_OK (0) or a negative OOC_E_* code.  No
+ *    C++ exception crosses this boundary.  The message of the last failure is
+ *    available from ooc_last_error().
+ *  - After an OOC_E_DEVICE failure the context is failed: every later call
+ *    except ooc_destroy / ooc_last_error returns OOC_E_FAILED.
+ *  - Pointers passed in (names, offsets, initial data) are copied before the
+ *    call returns; the caller keeps ownership.
+ *  - Grid indices are logical: an axis of n interior cells with halo depth h
+ *    has valid indices [-h, n + h + delta) where delta (0 or 1) is the field's
+ *    size increment on that axis (nodes and faces have one more point).
+ *  - The tiled axis is the last grid axis (y in 2D, z in 3D).
+ *  - Host field data is row-major with x fastest, laid out over the field's
+ *    full logical extent (halo included), as float64.
+ */
+#ifndef OOC_H
+#define OOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ooc_ctx ooc_ctx;
+typedef int32_t ooc_field;
+typedef int32_t ooc_red;
+
+/* return codes */
+enum {
+  OOC_OK = 0,
+  OOC_E_ARG = -1,     /* invalid argument: bad handle, range, stencil or kernel signature */
+  OOC_E_BUDGET = -2,  /* no tile schedule fits the device byte budget */
+  OOC_E_DEVICE = -3,  /* a HIP runtime call failed; the context is now failed */
+  OOC_E_STATE = -4,   /* call not valid in the current state (e.g. before bind) */
+  OOC_E_FAILED = -5,  /* the context failed earlier */
+  OOC_E_STALE = -6,   /* fetch of a temporary whose host copy was skipped (Cyclic) */
+  OOC_E_NOMEM = -7    /* host allocation (pinned memory) failed */
+};
+
+/* dataset access modes (Section 3: read / write / both; INC is a point-wise
+ * read-modify-write, analysed as read-write) */
+enum { OOC_READ = 1, OOC_WRITE = 2, OOC_RW = 3, OOC_INC = 4 };
+
+/* reduction operators */
+enum { OOC_RED_MIN = 1, OOC_RED_MAX = 2, OOC_RED_SUM = 3 };
+
+/* kinds of loop argument */
+enum {
+  OOC_ARG_DAT = 0,       /* a field accessed through a stencil */
+  OOC_ARG_RED = 1,       /* a reduction the loop contributes to */
+  OOC_ARG_CONST = 2,     /* a double passed by value */
+  OOC_ARG_DEVSCALAR = 3  /* the last committed value of a reduction, read on the device */
+};
+
+/* context flags */
+enum {
+  OOC_FLAG_CYCLIC = 1,        /* Section 4.1 opt (2): do not download write-first datasets */
+  OOC_FLAG_PREFETCH = 2,      /* Section 4.1 opt (3): start the next chain's first tile early */
+  OOC_FLAG_FP32_STREAM = 4,   /* store streamed fields on the host as float32 (transfers halved) */
+  OOC_FLAG_INCORE = 8,        /* keep every field resident on the device (no streaming) */
+  OOC_FLAG_GRAPH = 16,        /* replay each chain's tile pipeline from a captured hipGraph */
+  OOC_FLAG_DEBUG_POISON = 64, /* fill every slot with NaN before use (finds missing uploads) */
+  OOC_FLAG_DEBUG_SYNC = 128   /* serialise the three streams (separates races from plan bugs) */
+};
+
+/* per-field flags for ooc_decl_field */
+enum {
+  OOC_FIELD_RESIDENT = 1  /* keep this field on the device for the context's lifetime */
+};
+
+typedef struct {
+  int32_t kind;            /* OOC_ARG_* */
+  int32_t handle;          /* field (DAT) or reduction (RED, DEVSCALAR) handle */
+  int32_t access;          /* DAT only: OOC_READ / OOC_WRITE / OOC_RW / OOC_INC */
+  int32_t npts;            /* DAT only: number of stencil points (>= 1) */
+  const int32_t *offsets;  /* DAT only: npts * ndim offsets, point-major */
+  double value;            /* CONST only */
+} ooc_arg;
+
+typedef struct {
+  uint64_t chains, tiles, launches;
+  uint64_t bytes_h2d, bytes_d2h, bytes_edge;   /* cumulative transfer bytes */
+  uint64_t bytes_hbm_alg;                      /* cumulative algorithmic loop bytes (Section 5.1 rule) */
+  uint64_t last_bytes_h2d, last_bytes_d2h;     /* of the last flush */
+  int64_t tile_rows;                           /* tile height of the last planned chain */
+  int32_t ntiles_last;                         /* tiles of the last planned chain */
+  int32_t slots;                               /* buffer depth in use */
+  uint64_t slot_bytes;                         /* bytes of one slot of the last plan */
+  double last_flush_ms;                        /* device time of the last flush */
+  double last_kernel_ms;                       /* summed kernel time of the last flush (if timed) */
+} ooc_stats;
+
+/* Create a context for a grid of ndim (2 or 3) axes with dims[a] interior cells
+ * per axis and halo depth `halo` (Section 3: a block).  device_budget_bytes
+ * caps the device memory the context may use (tile slots, resident fields and
+ * reduction buffers).  Nothing is allocated on the device here. */
+int ooc_create(ooc_ctx **out, int ndim, const int64_t dims[3], int halo,
+               size_t device_budget_bytes, uint32_t flags);
+
+/* Hand the context its device arena (at least the budget, 256-byte aligned)
+ * and its three streams: host-to-device, compute, device-to-host (Section 4:
+ * streams 1, 0 and 2 of Algorithm 1).  Streams are hipStream_t values; the
+ * arena and the streams stay owned by the caller and must outlive the
+ * context.  If never called, the first flush allocates its own. */
+int ooc_bind_device(ooc_ctx *ctx, void *arena, size_t arena_bytes,
+                    void *stream_h2d, void *stream_compute, void *stream_d2h);
+
+/* Declare a float64 field (Section 3: a dataset).  size_delta[a] in {0,1}
+ * adds one point on axis a (node / face centring).  init_host, if not NULL,
+ * holds the full logical extent (halo included, x fastest); NULL means zeros.
+ * The library keeps the field in pinned host memory it owns. */
+int ooc_decl_field(ooc_ctx *ctx, const char *name, const int32_t size_delta[3],
+                   const double *init_host, uint32_t field_flags, ooc_field *out);
+
+/* Declare a reduction (MIN / MAX / SUM).  A SUM is order-fixed: per-row
+ * partials in x order, combined in a fixed order, so its value does not
+ * depend on the tiling. */
+int ooc_decl_reduction(ooc_ctx *ctx, int op, ooc_red *out);
+
+/* Set the committed value of a reduction (what DEVSCALAR arguments read). */
+int ooc_set_reduction(ooc_ctx *ctx, ooc_red red, double value);
+
+/* Queue a parallel loop (Section 3; Figure 1): kernel_id from ooc_kernels.h,
+ * range[2a], range[2a+1] the half-open iteration range on axis a.  Nothing
+ * executes (lazy execution, Section 3).  Checked at the call:
+ *  - the kernel's signature (argument kinds and counts);
+ *  - every DAT access stays inside its field's extent;
+ *  - WRITE / RW / INC arguments access only offset 0 (points are order-free);
+ *  - a loop that writes a field reads it at non-zero offsets only where the
+ *    shifted range is disjoint from the written range. */
+int ooc_par_loop(ooc_ctx *ctx, int kernel_id, const int64_t range[6], int nargs,
+                 const ooc_arg *args);
+
+/* Mark a step boundary in the queue; with ooc_set_schedule(chain_steps = k)
+ * a chain ends after every k marks. */
+int ooc_mark_step(ooc_ctx *ctx);
+
+/* Flush: analyse and execute everything queued, then wait for the device. */
+int ooc_execute(ooc_ctx *ctx);
+
+/* Flush, then return the committed value of a reduction (Section 3: getting
+ * the result of a reduction ends the chain). */
+int ooc_reduce(ooc_ctx *ctx, ooc_red red, double *out);
+
+/* Flush, then copy the field's full logical extent (float64, x fastest) into
+ * dst (bytes must equal the extent size).  OOC_E_STALE if the field is a
+ * temporary whose download was skipped under OOC_FLAG_CYCLIC. */
+int ooc_fetch_field(ooc_ctx *ctx, ooc_field f, double *dst, size_t bytes);
+
+/* Replace a field's host data (full logical extent, float64). */
+int ooc_set_field(ooc_ctx *ctx, ooc_field f, const double *src, size_t bytes);
+
+/* Set / clear context flags, e.g. OOC_FLAG_CYCLIC once the cyclic part of an
+ * application begins (Section 4.1). */
+int ooc_set_flags(ooc_ctx *ctx, uint32_t set, uint32_t clear);
+
+/* Schedule: tile height in rows of the tiled axis (0 = largest that fits the
+ * budget), chain length in step marks (0 = whole flush), slot count (0 = 3,
+ * the paper's three slots; 2..8 allowed). */
+int ooc_set_schedule(ooc_ctx *ctx, int64_t tile_rows, int chain_steps, int slots);
+
+int ooc_get_stats(ooc_ctx *ctx, ooc_stats *out);
+
+/* Enable per-launch timing with hipEvents (adds a little overhead); read the
+ * summed kernel time of the last flush from ooc_stats.last_kernel_ms. */
+int ooc_set_timing(ooc_ctx *ctx, int on);
+
+/* Accumulated timing of one kernel id over the flushes since timing was
+ * enabled: summed launch time (ms, hipEvents on the compute stream), launch
+ * count and algorithmic bytes (Section 5.1 rule: 1x per read or written
+ * dataset point, 2x for read-write). */
+int ooc_kernel_stats(ooc_ctx *ctx, int kernel_id, double *ms, uint64_t *launches, uint64_t *bytes);
+
+const char *ooc_last_error(ooc_ctx *ctx);
+
+int ooc_destroy(ooc_ctx *ctx);
+
+/* ------------------------------------------------------------ inspection */
+/* Plan the chain that the next flush would execute first, without running it,
+ * and expose the plan (owned by the context, valid until the next call that
+ * plans or flushes).  Used by host-side tests of the tiling analysis. */
+typedef struct {
+  int32_t ntiles, nloops, nfields, slots;
+  int64_t tile_rows;
+  uint64_t slot_bytes;
+  const int64_t *loop_rows;   /* [nloops][ntiles][2]: tiled-axis rows of loop i in tile t */
+  const int64_t *resident;    /* [nfields][ntiles][2]: rows held in the slot during tile t */
+  int32_t nup, ndown, nedge;  /* counts of transfer runs */
+  const int64_t *up;          /* [nup][4]: field, tile, row_lo, row_hi (uploaded before tile) */
+  const int64_t *down;        /* [ndown][4]: field, tile, row_lo, row_hi (downloaded after tile) */
+  const int64_t *edge;        /* [nedge][4]: field, tile, row_lo, row_hi (copied tile-1 -> tile) */
+  const int32_t *temporary;   /* [nfields]: 1 if no element is read before written in the chain */
+} ooc_plan_info;
+
+int ooc_debug_plan(ooc_ctx *ctx, ooc_plan_info *out);
+
+/* Field geometry: logical lower bound, extent per axis and the row pitch (in
+ * elements) of the library's layout. */
+int ooc_field_shape(ooc_ctx *ctx, ooc_field f, int64_t lo[3], int64_t n[3]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OOC_H */

@@ -1,0 +1,77 @@
+/*
+ * ooc_kernels.h -- kernel ids accepted by ooc_par_loop, with the argument list
+ * each expects (DAT arguments first, in this order; then CONST, DEVSCALAR and
+ * RED arguments).  "R", "W", "RW" give the access mode; stencils are the
+ * caller's, but must cover what the kernel reads (listed here).
+ *
+ * Offsets are (dx, dy[, dz]).  "4n" = the four nodes of a cell
+ * {(0,0),(1,0),(0,1),(1,1)}; "4c" = the four cells of a node
+ * {(-1,-1),(0,-1),(-1,0),(0,0)}.
+ */
+#ifndef OOC_KERNELS_H
+#define OOC_KERNELS_H
+
+enum {
+  /* ---- generic ---- */
+  /* n pairs (W dst_k @0, R src_k @o_k), n CONST sign_k: dst_k = sign_k * src_k(p + o_k).
+   * Used for reflective-wall strips and field copies.  1 <= n <= 6. */
+  OOC_K_MIRROR = 1,
+  /* W dst @0, CONST value: dst = value */
+  OOC_K_FILL = 2,
+  /* R a_1..a_m @0 (1 <= m <= 3), RED(SUM): red += prod_k a_k */
+  OOC_K_SUM_PROD = 3,
+  /* W out @0, R in @{o_1..o_n}, CONST c0, CONST c1: out = c0 * mean_k in(p+o_k) + c1 */
+  OOC_K_AVG = 4,
+  /* INC out @0, R in @0, CONST c: out += c * in */
+  OOC_K_INC_ADD = 5,
+  /* R a @0, RED(MIN), RED(MAX): min / max of a */
+  OOC_K_MINMAX = 6,
+
+  /* ---- 2D hydro proxy (x = axis 0, y = axis 1; tiled along y) ---- */
+  /* R rho, R e, W p, W cs: p = (g-1) rho e; cs = sqrt(g p / rho) */
+  OOC_K_H2D_EOS = 100,
+  /* R rho, R e, W p */
+  OOC_K_H2D_EOS_P = 101,
+  /* R rho0, R cs, R u0 4n, R v0 4n, W q */
+  OOC_K_H2D_VISC = 102,
+  /* R rho0, R e0, R p, R q, R vol, R xarea {(0,0),(1,0)}, R yarea {(0,0),(0,1)},
+   * R u0 4n, R v0 4n, W rho1, W e1; DEVSCALAR dt */
+  OOC_K_H2D_PDV_PRED = 103,
+  /* as PDV_PRED plus R u1 4n, R v1 4n after v0 */
+  OOC_K_H2D_PDV_CORR = 104,
+  /* R rho0 4c, R vol 4c, R p 4c, R q 4c, R xarea {(0,-1),(0,0)}, R yarea {(-1,0),(0,0)},
+   * R u0, R v0, W u1, W v1; CONST nx, CONST ny; DEVSCALAR dt */
+  OOC_K_H2D_ACCEL = 105,
+  /* R xarea, R u0 {(0,0),(0,1)}, R u1 {(0,0),(0,1)}, W vfx; DEVSCALAR dt */
+  OOC_K_H2D_FLUX_X = 106,
+  /* R yarea, R v0 {(0,0),(1,0)}, R v1 {(0,0),(1,0)}, W vfy; DEVSCALAR dt */
+  OOC_K_H2D_FLUX_Y = 107,
+  /* R vol, R vfx {(0,0),(1,0)}, R vfy {(0,0),(0,1)}, W pre, W post */
+  OOC_K_H2D_ADV_VOL_X = 108,
+  /* R vol, R vfy {(0,0),(0,1)}, W pre, W post */
+  OOC_K_H2D_ADV_VOL_Y = 109,
+  /* R vf, R rho1 {-e,0}, R e1 {-e,0}, W mf, W ef  (e = unit vector of the sweep) */
+  OOC_K_H2D_ADV_FLUX_X = 110,
+  OOC_K_H2D_ADV_FLUX_Y = 111,
+  /* RW rho1, RW e1, R pre, R post, R mf {0,+e}, R ef {0,+e} */
+  OOC_K_H2D_ADV_CELL_X = 112,
+  OOC_K_H2D_ADV_CELL_Y = 113,
+  /* R mf (x: {(0,-1),(0,0),(1,-1),(1,0)}; y: {(-1,0),(0,0),(-1,1),(0,1)}), W nf */
+  OOC_K_H2D_NFLUX_X = 114,
+  OOC_K_H2D_NFLUX_Y = 115,
+  /* R rho1 4c, R post 4c, R nf {-e,0}, W nmpost, W nmpre */
+  OOC_K_H2D_NMASS_X = 116,
+  OOC_K_H2D_NMASS_Y = 117,
+  /* R nf, R vel {0,+e}, W mflux */
+  OOC_K_H2D_MFLUX_X = 118,
+  OOC_K_H2D_MFLUX_Y = 119,
+  /* RW vel, R nmpre, R nmpost, R mflux {-e,0} */
+  OOC_K_H2D_VEL_X = 120,
+  OOC_K_H2D_VEL_Y = 121,
+  /* R e0, R u0 4n, R v0 4n; CONST dx, CONST dy; RED(MIN) dt */
+  OOC_K_H2D_DT = 122,
+
+  OOC_K_MAX_ID = 512
+};
+
+#endif /* OOC_KERNELS_H */

@@ -1,0 +1,206 @@
+// Generic kernels of the loop-chain library for gfx950: mirror / copy strips,
+// fills, order-fixed sums, min/max reductions, the batched slot-to-slot edge
+// copy, and float32 <-> float64 conversion of streamed rows.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels_device.h"
+#include "ooc_internal.h"
+
+namespace ooc {
+
+KernelInfo *kernel_table() {
+  static KernelInfo t[OOC_K_MAX_ID];
+  return t;
+}
+
+// ---------------------------------------------------------------- generic
+// dst_q(p) = sign_q * src_q(p + o_q) for each of the n pairs.
+__global__ void __launch_bounds__(256) k_mirror(KArgs a) {
+  POINT_INDEX_OR_RETURN;
+  const int n = a.ndat / 2;
+  for (int q = 0; q < n; q++) {
+    const int32_t *o = a.off[2 * q + 1];
+    AT(2 * q, 0, 0, 0) = a.c[q] * AT(2 * q + 1, o[0], o[1], o[2]);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_fill_pt(KArgs a) {
+  POINT_INDEX_OR_RETURN;
+  AT(0, 0, 0, 0) = a.c[0];
+}
+
+// out = c0 * (sum over the stencil of in) / npts + c1, stencil summed in order
+__global__ void __launch_bounds__(256) k_avg(KArgs a) {
+  POINT_INDEX_OR_RETURN;
+  double s = 0.0;
+  for (int q = 0; q < a.nst; q++) s += AT(1, a.st[q][0], a.st[q][1], a.st[q][2]);
+  AT(0, 0, 0, 0) = a.c[0] * (s / (double)a.nst) + a.c[1];
+}
+
+__global__ void __launch_bounds__(256) k_inc_add(KArgs a) {
+  POINT_INDEX_OR_RETURN;
+  AT(0, 0, 0, 0) = AT(0, 0, 0, 0) + a.c[0] * AT(1, 0, 0, 0);
+}
+
+__global__ void __launch_bounds__(256) k_minmax(KArgs a) {
+  POINT_INDEX_ACTIVE;
+  double v = active ? AT(0, 0, 0, 0) : INFINITY;
+  double w = active ? AT(0, 0, 0, 0) : -INFINITY;
+  block_min_to(v, a.red[0]);
+  block_max_to(w, a.red[1]);
+}
+
+// One block per row (y, z): the row's product sum in a fixed order, written to
+// the row's partial slot.  Independent of tiling because a row is always
+// summed by one block in the same order.
+__global__ void __launch_bounds__(256) k_sum_prod(KArgs a) {
+  const int j = a.lo[1] + blockIdx.y;
+  const int k = a.lo[2] + blockIdx.z;
+  double s = 0.0;
+  for (int i = a.lo[0] + threadIdx.x; i < a.hi[0]; i += 256) {
+    double v = AT(0, 0, 0, 0);
+    if (a.ndat > 1) v *= AT(1, 0, 0, 0);
+    if (a.ndat > 2) v *= AT(2, 0, 0, 0);
+    s += v;
+  }
+  s = block_sum_fixed(s);
+  if (threadIdx.x == 0) {
+    const int64_t row = (int64_t)(k + a.halo) * a.red_rows + (j + a.halo);
+    a.red[0][a.plane ? row : (j + a.halo)] = s;
+  }
+}
+
+void launch_point(void (*k)(KArgs), const KArgs &a, int ndim, void *s) {
+  dim3 grid = point_grid(a, ndim);
+  if (grid.x && grid.y && grid.z) hipLaunchKernelGGL(k, grid, dim3(64, 4, 1), 0, (hipStream_t)s, a);
+}
+
+void launch_rows(void (*k)(KArgs), const KArgs &a, int ndim, void *s) {
+  dim3 grid(1, a.hi[1] - a.lo[1], ndim == 3 ? a.hi[2] - a.lo[2] : 1);
+  if (grid.y && grid.z && a.hi[0] > a.lo[0]) hipLaunchKernelGGL(k, grid, dim3(256, 1, 1), 0, (hipStream_t)s, a);
+}
+
+#define POINT_LAUNCHER(name, kern) \
+  static void name(const KArgs &a, int nd, void *s) { launch_point(kern, a, nd, s); }
+POINT_LAUNCHER(l_mirror, k_mirror)
+POINT_LAUNCHER(l_fill, k_fill_pt)
+POINT_LAUNCHER(l_avg, k_avg)
+POINT_LAUNCHER(l_inc_add, k_inc_add)
+POINT_LAUNCHER(l_minmax, k_minmax)
+static void l_sum_prod(const KArgs &a, int nd, void *s) { launch_rows(k_sum_prod, a, nd, s); }
+
+void register_common_kernels(KernelInfo *t) {
+  t[OOC_K_MIRROR] = {"mirror", 2, 12, -1, 0, 0, kPointGrid, l_mirror};
+  t[OOC_K_FILL] = {"fill", 1, 1, 1, 0, 0, kPointGrid, l_fill};
+  t[OOC_K_SUM_PROD] = {"sum_prod", 1, 3, 0, 0, 1, kRowReduce, l_sum_prod};
+  t[OOC_K_AVG] = {"avg", 2, 2, 2, 0, 0, kPointGrid, l_avg};
+  t[OOC_K_INC_ADD] = {"inc_add", 2, 2, 1, 0, 0, kPointGrid, l_inc_add};
+  t[OOC_K_MINMAX] = {"minmax", 1, 1, 0, 0, 2, kPointGrid, l_minmax};
+}
+
+// --------------------------------------------------------- runtime helpers
+// Batched copy of up to 32 contiguous segments (the slot-to-slot edge copy),
+// each a multiple of 2 doubles and 16-byte aligned (rows are 256-byte multiples).
+struct SegTable {
+  const double *src[32];
+  double *dst[32];
+  int64_t n[32];
+  int64_t blk0[33];
+  int nseg;
+};
+constexpr int64_t kSegChunk = 4096;  // doubles per block
+
+__global__ void __launch_bounds__(256) k_copy_segs(SegTable t) {
+  const int64_t b = blockIdx.x;
+  int s = 0;
+  while (s + 1 < t.nseg && b >= t.blk0[s + 1]) s++;
+  const int64_t base = (b - t.blk0[s]) * kSegChunk;
+  const int64_t end = base + kSegChunk < t.n[s] ? base + kSegChunk : t.n[s];
+  const double2 *src = (const double2 *)t.src[s];
+  double2 *dst = (double2 *)t.dst[s];
+  for (int64_t e = base / 2 + threadIdx.x; e < end / 2; e += 256) dst[e] = src[e];
+}
+
+void launch_copy_segments(const CopySeg *segs, int nseg, void *stream) {
+  for (int s0 = 0; s0 < nseg; s0 += 32) {
+    SegTable t{};
+    t.nseg = nseg - s0 < 32 ? nseg - s0 : 32;
+    int64_t blocks = 0;
+    for (int q = 0; q < t.nseg; q++) {
+      t.src[q] = segs[s0 + q].src;
+      t.dst[q] = segs[s0 + q].dst;
+      t.n[q] = segs[s0 + q].n;
+      t.blk0[q] = blocks;
+      blocks += (t.n[q] + kSegChunk - 1) / kSegChunk;
+    }
+    t.blk0[t.nseg] = blocks;
+    if (blocks) hipLaunchKernelGGL(k_copy_segs, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, t);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_fill(double *d, int64_t n, double v) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) d[e] = v;
+}
+
+void launch_fill(double *dst, int64_t n, double value, void *stream) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, dst, n, value);
+}
+
+__global__ void k_set1(double *d, double v) {
+  if (threadIdx.x == 0) d[0] = v;
+}
+__global__ void k_copy1(const double *s, double *d) {
+  if (threadIdx.x == 0) d[0] = s[0];
+}
+
+void launch_red_init(double *acc, double value, void *stream) {
+  hipLaunchKernelGGL(k_set1, dim3(1), dim3(64), 0, (hipStream_t)stream, acc, value);
+}
+
+void launch_red_commit(const double *acc, double *committed, void *stream) {
+  hipLaunchKernelGGL(k_copy1, dim3(1), dim3(64), 0, (hipStream_t)stream, acc, committed);
+}
+
+// Fixed-order combination of the per-row partials: thread t sums rows
+// t, t+256, ... in order, then a fixed tree.
+__global__ void __launch_bounds__(256) k_sum_finalize(const double *p, int64_t n, double *out) {
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += 256) s += p[e];
+  s = block_sum_fixed(s);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+void launch_sum_finalize(const double *partials, int64_t n, double *committed, void *stream) {
+  hipLaunchKernelGGL(k_sum_finalize, dim3(1), dim3(256), 0, (hipStream_t)stream, partials, n, committed);
+}
+
+__global__ void __launch_bounds__(256) k_f32_to_f64(const float *s, double *d, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    d[e] = (double)s[e];
+}
+
+__global__ void __launch_bounds__(256) k_f64_to_f32(const double *s, float *d, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    d[e] = (float)s[e];  // round to nearest even
+}
+
+void launch_f32_to_f64(const float *src, double *dst, int64_t n, void *stream) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, src, dst, n);
+}
+
+void launch_f64_to_f32(const double *src, float *dst, int64_t n, void *stream) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, src, dst, n);
+}
+
+}  // namespace ooc

@@ -1,0 +1,157 @@
+// Internal types of the out-of-core loop-chain runtime.  Host-only parts (queue,
+// planner) use no HIP; the device parts include hip_runtime.h themselves.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ooc.h"
+#include "../../include/ooc_kernels.h"
+
+namespace ooc {
+
+constexpr int kMaxDat = 24;
+constexpr int kMaxConst = 12;
+constexpr int kMaxDev = 2;
+constexpr int kMaxRed = 2;
+constexpr int kMaxStencil = 32;
+
+// Argument block handed by value to every kernel.  Field pointers are rebased
+// so that logical index (i, j[, k]) of a field is p[k*plane + j*pitch + i]
+// whether the field lives in a tile slot or is resident (the "adjust base
+// pointers for virtual position" step of Algorithm 1).
+struct KArgs {
+  double *p[kMaxDat];
+  int32_t off[kMaxDat][3];         // first stencil point of each DAT argument
+  double c[kMaxConst];             // CONST arguments in order
+  const double *ds[kMaxDev];       // DEVSCALAR arguments: committed reduction values
+  double *red[kMaxRed];            // MIN/MAX: accumulator; SUM: per-row partial array
+  int32_t st[kMaxStencil][3];      // full stencil of the second DAT argument
+  int32_t nst;
+  int32_t ndat;
+  int32_t lo[3], hi[3];            // launch range (tiled axis already cut to the tile)
+  int64_t pitch, plane;            // elements between y rows / z planes
+  int64_t red_rows;                // SUM partials: rows per z plane (3D) ; row index base
+  int32_t halo;
+};
+
+// Kernel launch shapes.
+enum Shape { kPointGrid = 0, kRowReduce = 1 };
+
+struct KernelInfo {
+  const char *name = nullptr;
+  int ndat_min = 0, ndat_max = 0;  // DAT arguments
+  int nconst = 0;                  // -1: equals ndat / 2 (MIRROR)
+  int ndev = 0, nred = 0;
+  int shape = kPointGrid;
+  void (*launch)(const KArgs &, int ndim, void *stream) = nullptr;
+};
+
+// Registry filled by the kernel translation units.
+KernelInfo *kernel_table();
+void register_common_kernels(KernelInfo *t);
+void register_hydro2d_kernels(KernelInfo *t);
+
+// Device helpers implemented in kernels_common.hip.
+struct CopySeg {
+  const double *src;
+  double *dst;
+  int64_t n;  // doubles
+};
+void launch_copy_segments(const CopySeg *segs, int nseg, void *stream);
+void launch_fill(double *dst, int64_t n, double value, void *stream);
+void launch_red_init(double *acc, double value, void *stream);
+void launch_red_commit(const double *acc, double *committed, void *stream);
+void launch_sum_finalize(const double *partials, int64_t n, double *committed, void *stream);
+void launch_f32_to_f64(const float *src, double *dst, int64_t n, void *stream);
+void launch_f64_to_f32(const double *src, float *dst, int64_t n, void *stream);
+
+// ------------------------------------------------------------------ queue
+struct ArgRec {
+  int kind = 0, handle = -1, access = 0;
+  std::vector<int32_t> offs;  // npts * 3
+  double value = 0.0;
+  int npts() const { return (int)offs.size() / 3; }
+};
+
+struct LoopRec {
+  int kid = 0;
+  int64_t lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
+  std::vector<ArgRec> args;
+  int marks_before = 0;  // step marks queued before this loop (cumulative)
+};
+
+struct Field {
+  std::string name;
+  int32_t delta[3] = {0, 0, 0};
+  int64_t lo[3] = {0, 0, 0}, n[3] = {1, 1, 1};  // logical lower bound and extent
+  int64_t nrows = 0;                             // extent along the tiled axis
+  int64_t row_elems = 0;                         // elements per stored row
+  bool resident = false;
+  bool fp32 = false;        // host storage in float32
+  void *host = nullptr;     // pinned host array (nrows * row_elems elements)
+  double *dev_res = nullptr;
+  bool dev_valid = false;   // resident: device copy initialised
+  bool host_valid = true;   // resident: host copy up to date
+  bool stale = false;       // temporary whose download was skipped (Cyclic)
+  std::vector<int64_t> last_down;  // per stored row: tile id of its last download (-1: none)
+  int64_t host_bytes() const { return nrows * row_elems * (fp32 ? 4 : 8); }
+  int64_t row_bytes_dev() const { return row_elems * 8; }
+  int64_t row_bytes_host() const { return row_elems * (fp32 ? 4 : 8); }
+};
+
+struct Reduction {
+  int op = OOC_RED_MIN;
+  double *acc = nullptr;        // device accumulator (MIN/MAX)
+  double *partials = nullptr;   // device per-row partials (SUM)
+  int64_t npartials = 0;
+  double *committed = nullptr;  // device committed value
+  double host_value = 0.0;      // value set from the host before the first bind
+  bool host_set = false;
+};
+
+// --------------------------------------------------------------- planning
+struct Run {
+  int f, t;
+  int64_t lo, hi;  // stored rows
+};
+
+struct Plan {
+  int T = 1, S = 3;
+  int64_t h = 0;
+  int nloops = 0;
+  std::vector<int64_t> lo, hi;    // per loop, tiled-axis logical range
+  std::vector<int64_t> e;         // [nloops][T] exclusive end row of loop i in tile t
+  std::vector<int> slot_fields;   // fields stored in the slots
+  std::vector<int64_t> resA, resB;  // [nfields][T] stored-row residency
+  std::vector<int64_t> cap;         // [nfields] slab rows
+  std::vector<uint64_t> slab_off;   // [nfields] byte offset of the slab inside a slot
+  uint64_t slot_bytes = 0;
+  std::vector<Run> up, down, edge;
+  std::vector<int> temporary;       // [nfields]
+  std::vector<int> written;         // [nfields] written anywhere in the chain
+  uint64_t alg_bytes = 0;           // Section 5.1 byte count of the chain
+  std::vector<uint64_t> loop_alg_bytes;
+  int64_t s(int i, int t) const { return t == 0 ? lo[i] : e[i * T + t - 1]; }
+  int64_t en(int i, int t) const { return e[i * T + t]; }
+};
+
+struct PlanInput {
+  int ndim = 2, tax = 1, halo = 2;
+  const std::vector<Field> *fields = nullptr;
+  const LoopRec *loops = nullptr;
+  int nloops = 0;
+  bool cyclic = false;
+  int S = 3;
+  int64_t forced_h = 0;
+  uint64_t slot_capacity = 0;  // bytes available to one slot
+};
+
+inline bool writes_access(int a) { return a == OOC_WRITE || a == OOC_RW || a == OOC_INC; }
+inline bool reads_access(int a) { return a == OOC_READ || a == OOC_RW || a == OOC_INC; }
+
+// Returns OOC_OK or OOC_E_BUDGET; fills plan.
+int make_plan(const PlanInput &in, Plan &plan, std::string &err);
+
+}  // namespace ooc

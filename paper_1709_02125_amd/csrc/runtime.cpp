@@ -1,0 +1,1026 @@
+// C ABI of the out-of-core stencil loop-chain library: context, validation,
+// lazy loop queue, chain splitting, device memory manager and the three-stream
+// tile pipeline (the paper's Algorithm 1 with the optimisations of Section 4.1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <thread>
+
+#include "ooc_internal.h"
+
+using namespace ooc;
+
+namespace {
+
+struct DeviceError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct ArgError : std::runtime_error {
+  int code;
+  ArgError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                  \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess)                                                          \
+      throw DeviceError(std::string(#x) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+uint64_t align256(uint64_t x) { return (x + 255) / 256 * 256; }
+
+struct KStat {
+  double ms = 0;
+  uint64_t launches = 0, bytes = 0;
+};
+
+struct TimedLaunch {
+  int kid;
+  uint64_t bytes;
+  hipEvent_t a, b;
+};
+
+// parallel fill / copy of large host buffers
+void par_memcpy(void *dst, const void *src, size_t n) {
+  const size_t chunk = 256ull << 20;
+  if (n < 2 * chunk) {
+    if (src) std::memcpy(dst, src, n);
+    else std::memset(dst, 0, n);
+    return;
+  }
+  int nt = (int)std::min<size_t>(16, (n + chunk - 1) / chunk);
+  std::vector<std::thread> th;
+  size_t per = (n + nt - 1) / nt;
+  for (int k = 0; k < nt; k++) {
+    size_t o = k * per, m = std::min(per, n - std::min(n, o));
+    if (!m) continue;
+    th.emplace_back([=] {
+      if (src) std::memcpy((char *)dst + o, (const char *)src + o, m);
+      else std::memset((char *)dst + o, 0, m);
+    });
+  }
+  for (auto &t : th) t.join();
+}
+
+}  // namespace
+
+struct ooc_ctx {
+  int ndim = 2, tax = 1, halo = 2;
+  int64_t dims[3] = {1, 1, 1};
+  size_t budget = 0;
+  uint32_t flags = 0;
+  int64_t pitch = 0, plane = 0;
+  std::vector<Field> fields;
+  std::vector<char> pinned;  // per field: host array is pinned
+  std::vector<Reduction> reds;
+  std::vector<LoopRec> queue;
+  int marks = 0;
+  int64_t tile_rows = 0;
+  int chain_steps = 0;
+  int slots = 3;
+  // device
+  bool bound = false, own_arena = false, own_streams = false, ready = false, failed = false;
+  char *arena = nullptr;
+  size_t arena_bytes = 0;
+  hipStream_t s_up = nullptr, s_comp = nullptr, s_down = nullptr;
+  char *slot_base = nullptr;
+  uint64_t slot_stride = 0;
+  // tiles and events
+  int64_t gtile = 0, gbase = 0, gsynced = -1;
+  std::vector<hipEvent_t> ev_up, ev_comp, ev_down;  // indexed by g - gbase
+  std::map<std::string, Plan> plans;
+  Plan dbg;
+  std::vector<int64_t> dbg_loop_rows, dbg_res, dbg_up, dbg_down, dbg_edge;
+  ooc_stats st{};
+  bool timing = false;
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> tev_pool;
+  size_t tev_next = 0;
+  std::map<int, KStat> kstats;
+  std::string err;
+};
+
+namespace {
+
+KernelInfo *g_table = nullptr;
+
+KernelInfo *table() {
+  if (!g_table) {
+    g_table = kernel_table();
+    register_common_kernels(g_table);
+    register_hydro2d_kernels(g_table);
+  }
+  return g_table;
+}
+
+hipEvent_t &evref(std::vector<hipEvent_t> &v, ooc_ctx *c, int64_t g) {
+  size_t k = (size_t)(g - c->gbase);
+  while (v.size() <= k) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    v.push_back(e);
+  }
+  return v[k];
+}
+
+void wait_tile(ooc_ctx *c, hipStream_t s, std::vector<hipEvent_t> &v, int64_t g) {
+  if (g <= c->gsynced || g < c->gbase) return;
+  HIPCHK(hipStreamWaitEvent(s, evref(v, c, g), 0));
+}
+
+hipEvent_t timing_event(ooc_ctx *c) {
+  if (c->tev_next == c->tev_pool.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    c->tev_pool.push_back(e);
+  }
+  return c->tev_pool[c->tev_next++];
+}
+
+void *alloc_host(ooc_ctx *c, size_t bytes, bool &pinned) {
+  void *p = nullptr;
+  pinned = false;
+  if (c->bound && bytes) {
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) == hipSuccess) {
+      pinned = true;
+      return p;
+    }
+    (void)hipGetLastError();
+  }
+  p = std::aligned_alloc(4096, std::max<size_t>(4096, (bytes + 4095) / 4096 * 4096));
+  return p;
+}
+
+void free_host(void *p, bool pinned) {
+  if (!p) return;
+  if (pinned) (void)hipHostFree(p);
+  else std::free(p);
+}
+
+// Storage layout of a field: every field shares the row pitch (x) and, in 3D,
+// the plane size (x * y), so kernels index all fields alike.
+void layout_field(ooc_ctx *c, Field &f) {
+  for (int a = 0; a < 3; a++) {
+    if (a < c->ndim) {
+      f.lo[a] = -c->halo;
+      f.n[a] = c->dims[a] + 2 * c->halo + f.delta[a];
+    } else {
+      f.lo[a] = 0;
+      f.n[a] = 1;
+    }
+  }
+  f.nrows = f.n[c->tax];
+  f.row_elems = c->ndim == 2 ? c->pitch : c->plane;
+}
+
+// host <-> logical extent copy (field storage is padded to the shared pitch)
+void copy_extent(ooc_ctx *c, Field &f, double *dst, const double *src, bool to_user) {
+  const int64_t nx = f.n[0];
+  const int64_t ny = c->ndim == 3 ? f.n[1] : f.n[1];
+  const int64_t nz = c->ndim == 3 ? f.n[2] : 1;
+  for (int64_t k = 0; k < nz; k++)
+    for (int64_t j = 0; j < ny; j++) {
+      int64_t so = c->ndim == 3 ? k * c->plane + j * c->pitch : j * c->pitch;
+      int64_t uo = (k * ny + j) * nx;
+      if (f.fp32) {
+        float *h = (float *)f.host + so;
+        if (to_user) for (int64_t i = 0; i < nx; i++) dst[uo + i] = (double)h[i];
+        else for (int64_t i = 0; i < nx; i++) h[i] = (float)src[uo + i];
+      } else {
+        double *h = (double *)f.host + so;
+        if (to_user) std::memcpy(dst + uo, h, nx * 8);
+        else std::memcpy(h, src + uo, nx * 8);
+      }
+    }
+}
+
+int fail(ooc_ctx *c, int code, const std::string &m) {
+  c->err = m;
+  return code;
+}
+
+#define GUARD(c)                                                   \
+  if (!(c)) return OOC_E_ARG;                                      \
+  if ((c)->failed) return OOC_E_FAILED;
+
+template <class Fn>
+int guarded(ooc_ctx *c, Fn fn) {
+  try {
+    return fn();
+  } catch (const DeviceError &e) {
+    c->failed = true;
+    c->err = e.what();
+    return OOC_E_DEVICE;
+  } catch (const ArgError &e) {
+    c->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    c->err = "host allocation failed";
+    return OOC_E_NOMEM;
+  }
+}
+
+// ------------------------------------------------------------- device setup
+int64_t sum_partials(const ooc_ctx *c) {
+  return c->ndim == 2 ? c->dims[1] + 2 * c->halo + 1
+                      : (c->dims[2] + 2 * c->halo + 1) * (c->dims[1] + 2 * c->halo + 1);
+}
+
+// Device bytes taken ahead of the slots: reduction buffers and resident fields.
+uint64_t reserved_bytes(const ooc_ctx *c) {
+  uint64_t used = 0;
+  for (const Reduction &r : c->reds) used += 256 + (r.op == OOC_RED_SUM ? align256(sum_partials(c) * 8) : 0);
+  for (const Field &f : c->fields)
+    if (f.resident) used += align256((uint64_t)f.nrows * f.row_elems * 8);
+  return used;
+}
+
+void setup_device(ooc_ctx *c) {
+  if (c->ready) return;
+  if (!c->bound) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) throw DeviceError("no HIP device available");
+    HIPCHK(hipMalloc((void **)&c->arena, c->budget));
+    c->arena_bytes = c->budget;
+    c->own_arena = true;
+    HIPCHK(hipStreamCreateWithFlags(&c->s_up, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&c->s_comp, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&c->s_down, hipStreamNonBlocking));
+    c->own_streams = true;
+    c->bound = true;
+  }
+  // pin host arrays declared before the device was bound
+  for (size_t k = 0; k < c->fields.size(); k++) {
+    Field &f = c->fields[k];
+    if (c->pinned[k]) continue;
+    bool pin = false;
+    void *p = alloc_host(c, f.host_bytes(), pin);
+    par_memcpy(p, f.host, f.host_bytes());
+    free_host(f.host, false);
+    f.host = p;
+    c->pinned[k] = pin;
+  }
+  const size_t budget = std::min(c->budget, c->arena_bytes);
+  uint64_t off = 0;
+  for (Reduction &r : c->reds) {
+    r.acc = (double *)(c->arena + off);
+    r.committed = (double *)(c->arena + off + 8);
+    off += 256;
+    if (r.op == OOC_RED_SUM) {
+      r.npartials = sum_partials(c);
+      r.partials = (double *)(c->arena + off);
+      off += align256(r.npartials * 8);
+    }
+  }
+  for (Field &f : c->fields) {
+    if (!f.resident) continue;
+    f.dev_res = (double *)(c->arena + off);
+    off += align256((uint64_t)f.nrows * f.row_elems * 8);
+  }
+  if (off > budget)
+    throw ArgError(OOC_E_BUDGET, "resident fields and reductions need " + std::to_string(off) +
+                                     " bytes, more than the budget of " + std::to_string(budget));
+  c->slot_base = c->arena + off;
+  c->slot_stride = (budget - off) / c->slots / 256 * 256;
+  // initial device state: reductions, resident fields
+  for (Reduction &r : c->reds) {
+    double v = r.host_set ? r.host_value : 0.0;
+    HIPCHK(hipMemcpyAsync(r.committed, &v, 8, hipMemcpyHostToDevice, c->s_comp));
+  }
+  for (Field &f : c->fields) {
+    if (!f.resident) continue;
+    HIPCHK(hipMemcpyAsync(f.dev_res, f.host, (size_t)f.nrows * f.row_elems * 8, hipMemcpyHostToDevice,
+                          c->s_comp));
+    f.dev_valid = true;
+    f.host_valid = true;
+  }
+  HIPCHK(hipStreamSynchronize(c->s_comp));
+  c->ready = true;
+}
+
+// ------------------------------------------------------------ chain running
+std::string plan_key(ooc_ctx *c, const LoopRec *L, int n) {
+  std::string k;
+  auto put = [&](const void *p, size_t b) { k.append((const char *)p, b); };
+  int hdr[4] = {(c->flags & OOC_FLAG_CYCLIC) ? 1 : 0, c->slots, n, 0};
+  put(hdr, sizeof hdr);
+  put(&c->tile_rows, 8);
+  put(&c->slot_stride, 8);
+  for (int i = 0; i < n; i++) {
+    put(&L[i].kid, 4);
+    put(L[i].lo, 24);
+    put(L[i].hi, 24);
+    for (const ArgRec &a : L[i].args) {
+      int h[3] = {a.kind, a.handle, a.access};
+      put(h, sizeof h);
+      if (a.kind == OOC_ARG_DAT) {
+        int np = a.npts();
+        put(&np, 4);
+        put(a.offs.data(), a.offs.size() * 4);
+      }
+    }
+  }
+  return k;
+}
+
+const Plan &get_plan(ooc_ctx *c, const LoopRec *L, int n) {
+  std::string key = plan_key(c, L, n);
+  auto it = c->plans.find(key);
+  if (it != c->plans.end()) return it->second;
+  PlanInput in;
+  in.ndim = c->ndim;
+  in.tax = c->tax;
+  in.halo = c->halo;
+  in.fields = &c->fields;
+  in.loops = L;
+  in.nloops = n;
+  in.cyclic = (c->flags & OOC_FLAG_CYCLIC) != 0;
+  in.S = c->slots;
+  in.forced_h = c->tile_rows;
+  in.slot_capacity = c->ready ? c->slot_stride : UINT64_MAX;
+  if (!c->ready) {
+    // planning before the device exists (inspection): use the budget minus
+    // what resident fields and reductions will take
+    const uint64_t used = reserved_bytes(c);
+    in.slot_capacity = c->budget > used ? (c->budget - used) / c->slots / 256 * 256 : 0;
+  }
+  Plan p;
+  std::string err;
+  int rc = make_plan(in, p, err);
+  if (rc != OOC_OK) throw ArgError(rc, err);
+  if (c->plans.size() > 64) c->plans.clear();
+  return c->plans.emplace(key, std::move(p)).first->second;
+}
+
+double *field_ptr(ooc_ctx *c, int f, const Plan &P, int t, char *slot) {
+  Field &fd = c->fields[f];
+  char *base;
+  int64_t A;
+  if (fd.resident) {
+    base = (char *)fd.dev_res;
+    A = 0;
+  } else {
+    base = slot + P.slab_off[f];
+    A = P.resA[(size_t)f * P.T + t];
+  }
+  int64_t shift = -A * fd.row_elems - fd.lo[0] - fd.lo[1] * c->pitch;
+  if (c->ndim == 3) shift -= fd.lo[2] * c->plane;
+  return (double *)(base + shift * 8);
+}
+
+void launch_loop(ooc_ctx *c, const LoopRec &L, const Plan &P, int i, int t, char *slot) {
+  const KernelInfo &ki = table()[L.kid];
+  KArgs a;
+  std::memset(&a, 0, sizeof a);
+  for (int d = 0; d < 3; d++) {
+    a.lo[d] = (int32_t)L.lo[d];
+    a.hi[d] = (int32_t)L.hi[d];
+  }
+  a.lo[c->tax] = (int32_t)P.s(i, t);
+  a.hi[c->tax] = (int32_t)P.en(i, t);
+  a.pitch = c->pitch;
+  a.plane = c->plane;
+  a.halo = c->halo;
+  a.red_rows = c->dims[1] + 2 * c->halo + 1;
+  int nd = 0, nc = 0, ndv = 0, nr = 0;
+  uint64_t bytes = 0;
+  int64_t pts = 1;
+  for (int d = 0; d < c->ndim; d++) pts *= (a.hi[d] - a.lo[d]);
+  for (const ArgRec &g : L.args) {
+    switch (g.kind) {
+      case OOC_ARG_DAT:
+        a.p[nd] = field_ptr(c, g.handle, P, t, slot);
+        for (int q = 0; q < 3; q++) a.off[nd][q] = g.offs[q];
+        if (nd == 1) {
+          a.nst = std::min(g.npts(), kMaxStencil);
+          for (int s = 0; s < a.nst; s++)
+            for (int q = 0; q < 3; q++) a.st[s][q] = g.offs[3 * s + q];
+        }
+        bytes += (uint64_t)pts * 8 * (g.access == OOC_RW || g.access == OOC_INC ? 2 : 1);
+        nd++;
+        break;
+      case OOC_ARG_CONST: a.c[nc++] = g.value; break;
+      case OOC_ARG_DEVSCALAR: a.ds[ndv++] = c->reds[g.handle].committed; break;
+      case OOC_ARG_RED: {
+        Reduction &r = c->reds[g.handle];
+        a.red[nr++] = r.op == OOC_RED_SUM ? r.partials : r.acc;
+      } break;
+    }
+  }
+  a.ndat = nd;
+  if (c->timing) {
+    TimedLaunch tl{L.kid, bytes, timing_event(c), timing_event(c)};
+    HIPCHK(hipEventRecord(tl.a, c->s_comp));
+    ki.launch(a, c->ndim, c->s_comp);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(tl.b, c->s_comp));
+    c->timed.push_back(tl);
+  } else {
+    ki.launch(a, c->ndim, c->s_comp);
+    HIPCHK(hipGetLastError());
+  }
+  c->st.launches++;
+}
+
+bool loop_nonempty(const LoopRec &L, int ndim) {
+  for (int d = 0; d < ndim; d++)
+    if (L.hi[d] <= L.lo[d]) return false;
+  return true;
+}
+
+void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
+  const Plan &P = get_plan(c, L, n);
+  if ((uint64_t)P.slot_bytes > c->slot_stride)
+    throw ArgError(OOC_E_BUDGET, "plan does not fit its slot");
+  const int T = P.T, S = c->slots;
+  const bool dbg_sync = (c->flags & OOC_FLAG_DEBUG_SYNC) != 0;
+  // reductions written in this chain: start from the operator's identity
+  std::vector<int> wreds;
+  for (int i = 0; i < n; i++)
+    for (const ArgRec &g : L[i].args)
+      if (g.kind == OOC_ARG_RED && std::find(wreds.begin(), wreds.end(), g.handle) == wreds.end())
+        wreds.push_back(g.handle);
+  for (int h : wreds) {
+    Reduction &r = c->reds[h];
+    if (r.op == OOC_RED_SUM) launch_fill(r.partials, r.npartials, 0.0, c->s_comp);
+    else launch_red_init(r.acc, r.op == OOC_RED_MIN ? INFINITY : -INFINITY, c->s_comp);
+  }
+  // index transfer runs by tile
+  std::vector<std::vector<const Run *>> up(T), down(T), edge(T);
+  for (const Run &r : P.up) up[r.t].push_back(&r);
+  for (const Run &r : P.down) down[r.t].push_back(&r);
+  for (const Run &r : P.edge) edge[r.t].push_back(&r);
+  const int64_t g0 = c->gtile;
+  for (int t = 0; t < T; t++) {
+    const int64_t g = c->gtile++;
+    char *slot = c->slot_base + (uint64_t)(g % S) * c->slot_stride;
+    // ---- upload: the part of the tile's footprint not handed over by the
+    // previous tile (Algorithm 1, "upload right footprint to next slot")
+    wait_tile(c, c->s_up, c->ev_down, g - S);  // slot free again
+    if (t == 0 && prev_last_tile >= 0 && !(c->flags & OOC_FLAG_PREFETCH))
+      wait_tile(c, c->s_up, c->ev_comp, prev_last_tile);  // no early start of the next chain
+    if (c->flags & OOC_FLAG_DEBUG_POISON) launch_fill((double *)slot, P.slot_bytes / 8, NAN, c->s_up);
+    int64_t waited = -1;
+    for (const Run *r : up[t]) {
+      Field &f = c->fields[r->f];
+      int64_t dep = -1;
+      for (int64_t q = r->lo; q < r->hi; q++) dep = std::max(dep, f.last_down[q]);
+      if (dep > waited && dep > c->gsynced) {
+        wait_tile(c, c->s_up, c->ev_down, dep);
+        waited = dep;
+      }
+      const int64_t A = P.resA[(size_t)r->f * T + t];
+      char *dst = slot + P.slab_off[r->f] + (r->lo - A) * f.row_bytes_dev();
+      const size_t nb = (size_t)(r->hi - r->lo) * f.row_bytes_host();
+      HIPCHK(hipMemcpyAsync(dst, (char *)f.host + r->lo * f.row_bytes_host(), nb, hipMemcpyHostToDevice,
+                            c->s_up));
+      c->st.bytes_h2d += nb;
+      c->st.last_bytes_h2d += nb;
+    }
+    HIPCHK(hipEventRecord(evref(c->ev_up, c, g), c->s_up));
+    if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_up));
+    // ---- execute every loop of the chain over its rows of this tile
+    HIPCHK(hipStreamWaitEvent(c->s_comp, evref(c->ev_up, c, g), 0));
+    for (int i = 0; i < n; i++)
+      if (P.s(i, t) < P.en(i, t) && loop_nonempty(L[i], c->ndim)) launch_loop(c, L[i], P, i, t, slot);
+    // ---- hand the right edge to the next tile's slot (on the compute stream)
+    if (t + 1 < T && !edge[t + 1].empty()) {
+      wait_tile(c, c->s_comp, c->ev_down, g + 1 - S);  // next slot free again
+      if (c->flags & OOC_FLAG_DEBUG_POISON) HIPCHK(hipStreamSynchronize(c->s_up));
+      char *nslot = c->slot_base + (uint64_t)((g + 1) % S) * c->slot_stride;
+      std::vector<CopySeg> segs;
+      for (const Run *r : edge[t + 1]) {
+        Field &f = c->fields[r->f];
+        const int64_t A0 = P.resA[(size_t)r->f * T + t], A1 = P.resA[(size_t)r->f * T + t + 1];
+        CopySeg s;
+        s.src = (const double *)(slot + P.slab_off[r->f] + (r->lo - A0) * f.row_bytes_dev());
+        s.dst = (double *)(nslot + P.slab_off[r->f] + (r->lo - A1) * f.row_bytes_dev());
+        s.n = (r->hi - r->lo) * f.row_elems;
+        segs.push_back(s);
+        c->st.bytes_edge += (uint64_t)s.n * 8;
+      }
+      launch_copy_segments(segs.data(), (int)segs.size(), c->s_comp);
+      HIPCHK(hipGetLastError());
+    }
+    if (t == T - 1) {
+      for (int h : wreds) {
+        Reduction &r = c->reds[h];
+        if (r.op == OOC_RED_SUM) launch_sum_finalize(r.partials, r.npartials, r.committed, c->s_comp);
+        else launch_red_commit(r.acc, r.committed, c->s_comp);
+      }
+    }
+    HIPCHK(hipEventRecord(evref(c->ev_comp, c, g), c->s_comp));
+    if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_comp));
+    // ---- download the left footprint of modified datasets
+    HIPCHK(hipStreamWaitEvent(c->s_down, evref(c->ev_comp, c, g), 0));
+    for (const Run *r : down[t]) {
+      Field &f = c->fields[r->f];
+      const int64_t A = P.resA[(size_t)r->f * T + t];
+      const char *src = slot + P.slab_off[r->f] + (r->lo - A) * f.row_bytes_dev();
+      const size_t nb = (size_t)(r->hi - r->lo) * f.row_bytes_host();
+      HIPCHK(hipMemcpyAsync((char *)f.host + r->lo * f.row_bytes_host(), src, nb, hipMemcpyDeviceToHost,
+                            c->s_down));
+      for (int64_t q = r->lo; q < r->hi; q++) f.last_down[q] = g;
+      c->st.bytes_d2h += nb;
+      c->st.last_bytes_d2h += nb;
+    }
+    HIPCHK(hipEventRecord(evref(c->ev_down, c, g), c->s_down));
+    if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_down));
+  }
+  (void)g0;
+  // host-copy bookkeeping
+  const bool cyclic = (c->flags & OOC_FLAG_CYCLIC) != 0;
+  for (size_t f = 0; f < c->fields.size(); f++) {
+    Field &fd = c->fields[f];
+    if (!P.written[f]) continue;
+    if (fd.resident) fd.host_valid = false;
+    else fd.stale = cyclic && P.temporary[f];
+  }
+  c->st.chains++;
+  c->st.tiles += T;
+  c->st.bytes_hbm_alg += P.alg_bytes;
+  c->st.tile_rows = P.h;
+  c->st.ntiles_last = T;
+  c->st.slots = S;
+  c->st.slot_bytes = P.slot_bytes;
+}
+
+void sync_all(ooc_ctx *c) {
+  HIPCHK(hipStreamSynchronize(c->s_up));
+  HIPCHK(hipStreamSynchronize(c->s_comp));
+  HIPCHK(hipStreamSynchronize(c->s_down));
+  c->gsynced = c->gtile - 1;
+  c->gbase = c->gtile;
+}
+
+void collect_timing(ooc_ctx *c) {
+  c->st.last_kernel_ms = 0;
+  for (const TimedLaunch &t : c->timed) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, t.a, t.b));
+    KStat &k = c->kstats[t.kid];
+    k.ms += ms;
+    k.launches++;
+    k.bytes += t.bytes;
+    c->st.last_kernel_ms += ms;
+  }
+  c->timed.clear();
+  c->tev_next = 0;
+}
+
+// Split the queue into chains and run them back to back, then wait.
+int flush(ooc_ctx *c) {
+  if (c->queue.empty()) return OOC_OK;
+  setup_device(c);
+  auto t0 = std::chrono::steady_clock::now();
+  c->st.last_bytes_h2d = c->st.last_bytes_d2h = 0;
+  std::vector<std::pair<int, int>> chains;
+  {
+    int start = 0;
+    std::vector<int> wr;
+    int marks0 = c->queue[0].marks_before;
+    for (int i = 0; i < (int)c->queue.size(); i++) {
+      const LoopRec &L = c->queue[i];
+      bool split = c->chain_steps > 0 && L.marks_before - marks0 >= c->chain_steps;
+      for (const ArgRec &g : L.args)
+        if ((g.kind == OOC_ARG_DEVSCALAR || g.kind == OOC_ARG_RED) &&
+            std::find(wr.begin(), wr.end(), g.handle) != wr.end())
+          split = true;
+      if (split && i > start) {
+        chains.push_back({start, i});
+        start = i;
+        wr.clear();
+        marks0 = L.marks_before;
+      }
+      for (const ArgRec &g : L.args)
+        if (g.kind == OOC_ARG_RED) wr.push_back(g.handle);
+    }
+    chains.push_back({start, (int)c->queue.size()});
+  }
+  int64_t prev_last = -1;
+  for (auto &ch : chains) {
+    run_chain(c, c->queue.data() + ch.first, ch.second - ch.first, prev_last);
+    prev_last = c->gtile - 1;
+  }
+  c->queue.clear();
+  sync_all(c);
+  if (c->timing) collect_timing(c);
+  c->st.last_flush_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return OOC_OK;
+}
+
+void check_loop(ooc_ctx *c, int kid, const int64_t range[6], int nargs, const ooc_arg *args, LoopRec &L) {
+  if (kid <= 0 || kid >= OOC_K_MAX_ID || !table()[kid].launch) throw ArgError(OOC_E_ARG, "unknown kernel id " + std::to_string(kid));
+  const KernelInfo &ki = table()[kid];
+  if (nargs < 0 || (nargs > 0 && !args)) throw ArgError(OOC_E_ARG, "bad argument list");
+  L.kid = kid;
+  for (int d = 0; d < 3; d++) {
+    L.lo[d] = d < c->ndim ? range[2 * d] : 0;
+    L.hi[d] = d < c->ndim ? range[2 * d + 1] : 1;
+    if (L.hi[d] < L.lo[d]) throw ArgError(OOC_E_ARG, "negative iteration range on axis " + std::to_string(d));
+  }
+  const bool empty = !loop_nonempty(L, c->ndim);
+  int nd = 0, nc = 0, ndv = 0, nr = 0;
+  for (int k = 0; k < nargs; k++) {
+    const ooc_arg &a = args[k];
+    ArgRec r;
+    r.kind = a.kind;
+    r.handle = a.handle;
+    r.access = a.access;
+    r.value = a.value;
+    switch (a.kind) {
+      case OOC_ARG_DAT: {
+        if (a.handle < 0 || a.handle >= (int)c->fields.size()) throw ArgError(OOC_E_ARG, "bad field handle");
+        if (a.access < OOC_READ || a.access > OOC_INC) throw ArgError(OOC_E_ARG, "bad access mode");
+        if (a.npts < 1 || a.npts > 64 || !a.offsets) throw ArgError(OOC_E_ARG, "bad stencil");
+        r.offs.assign((size_t)a.npts * 3, 0);
+        for (int p = 0; p < a.npts; p++)
+          for (int d = 0; d < c->ndim; d++) r.offs[3 * p + d] = a.offsets[p * c->ndim + d];
+        if (writes_access(a.access)) {
+          for (int v : r.offs)
+            if (v != 0 || a.npts != 1)
+              throw ArgError(OOC_E_ARG, "field '" + c->fields[a.handle].name +
+                                            "' is written through a stencil other than the point itself");
+        }
+        const Field &f = c->fields[a.handle];
+        if (!empty)
+          for (int p = 0; p < a.npts; p++)
+            for (int d = 0; d < c->ndim; d++) {
+              int64_t o = r.offs[3 * p + d];
+              if (L.lo[d] + o < f.lo[d] || L.hi[d] + o > f.lo[d] + f.n[d])
+                throw ArgError(OOC_E_ARG, std::string("loop ") + table()[kid].name + " reaches outside field '" +
+                                              f.name + "' on axis " + std::to_string(d));
+            }
+        nd++;
+      } break;
+      case OOC_ARG_CONST: nc++; break;
+      case OOC_ARG_DEVSCALAR:
+      case OOC_ARG_RED:
+        if (a.handle < 0 || a.handle >= (int)c->reds.size()) throw ArgError(OOC_E_ARG, "bad reduction handle");
+        if (a.kind == OOC_ARG_RED) nr++;
+        else ndv++;
+        break;
+      default: throw ArgError(OOC_E_ARG, "bad argument kind");
+    }
+    L.args.push_back(std::move(r));
+  }
+  int want_c = ki.nconst < 0 ? nd / 2 : ki.nconst;
+  if (nd < ki.ndat_min || nd > ki.ndat_max || nc != want_c || ndv != ki.ndev || nr != ki.nred ||
+      (ki.nconst < 0 && nd % 2))
+    throw ArgError(OOC_E_ARG, std::string("argument list does not match kernel ") + ki.name);
+  // points are order-free: a written field may be read elsewhere only where
+  // the shifted range cannot meet the written range
+  for (size_t w = 0; w < L.args.size(); w++) {
+    const ArgRec &aw = L.args[w];
+    if (aw.kind != OOC_ARG_DAT || !writes_access(aw.access)) continue;
+    for (size_t r = 0; r < L.args.size(); r++) {
+      const ArgRec &ar = L.args[r];
+      if (ar.kind != OOC_ARG_DAT || ar.handle != aw.handle) continue;
+      if (r != w && writes_access(ar.access)) throw ArgError(OOC_E_ARG, "field written twice by one loop");
+      if (!reads_access(ar.access)) continue;
+      for (int p = 0; p < ar.npts(); p++) {
+        bool zero = true, disjoint = false;
+        for (int d = 0; d < c->ndim; d++) {
+          int64_t o = ar.offs[3 * p + d];
+          if (o) zero = false;
+          if (L.lo[d] + o >= L.hi[d] || L.hi[d] + o <= L.lo[d]) disjoint = true;
+        }
+        if (!zero && !disjoint && !empty)
+          throw ArgError(OOC_E_ARG, "loop reads field '" + c->fields[aw.handle].name +
+                                        "' at a neighbour it also writes (points would not be order-free)");
+      }
+    }
+  }
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+int ooc_create(ooc_ctx **out, int ndim, const int64_t dims[3], int halo, size_t budget, uint32_t flags) {
+  if (!out || (ndim != 2 && ndim != 3) || !dims || halo < 0 || halo > 8) return OOC_E_ARG;
+  for (int d = 0; d < ndim; d++)
+    if (dims[d] < 1 || dims[d] > (1 << 24)) return OOC_E_ARG;
+  ooc_ctx *c = new (std::nothrow) ooc_ctx();
+  if (!c) return OOC_E_NOMEM;
+  c->ndim = ndim;
+  c->tax = ndim - 1;
+  c->halo = halo;
+  for (int d = 0; d < 3; d++) c->dims[d] = d < ndim ? dims[d] : 1;
+  c->budget = budget;
+  c->flags = flags;
+  c->pitch = (dims[0] + 2 * halo + 1 + 31) / 32 * 32;
+  c->plane = ndim == 3 ? c->pitch * (dims[1] + 2 * halo + 1) : 0;
+  *out = c;
+  return OOC_OK;
+}
+
+int ooc_bind_device(ooc_ctx *c, void *arena, size_t arena_bytes, void *s_up, void *s_comp, void *s_down) {
+  GUARD(c);
+  if (c->ready || c->bound) return fail(c, OOC_E_STATE, "device already bound");
+  if (!arena || (uintptr_t)arena % 256 || !s_up || !s_comp || !s_down)
+    return fail(c, OOC_E_ARG, "arena must be 256-byte aligned and all three streams given");
+  if (s_up == s_comp || s_up == s_down || s_comp == s_down)
+    return fail(c, OOC_E_ARG, "the three streams must be distinct");
+  c->arena = (char *)arena;
+  c->arena_bytes = arena_bytes;
+  c->s_up = (hipStream_t)s_up;
+  c->s_comp = (hipStream_t)s_comp;
+  c->s_down = (hipStream_t)s_down;
+  c->bound = true;
+  return OOC_OK;
+}
+
+int ooc_decl_field(ooc_ctx *c, const char *name, const int32_t size_delta[3], const double *init, uint32_t fflags,
+                   ooc_field *out) {
+  GUARD(c);
+  if (!out) return OOC_E_ARG;
+  if (c->ready) return fail(c, OOC_E_STATE, "fields must be declared before the first flush");
+  return guarded(c, [&]() -> int {
+    Field f;
+    f.name = name ? name : ("field" + std::to_string(c->fields.size()));
+    for (int d = 0; d < 3; d++) {
+      f.delta[d] = size_delta && d < c->ndim ? size_delta[d] : 0;
+      if (f.delta[d] < 0 || f.delta[d] > 1) throw ArgError(OOC_E_ARG, "size_delta must be 0 or 1");
+    }
+    f.resident = (fflags & OOC_FIELD_RESIDENT) || (c->flags & OOC_FLAG_INCORE);
+    f.fp32 = (c->flags & OOC_FLAG_FP32_STREAM) && !f.resident;
+    layout_field(c, f);
+    bool pin = false;
+    f.host = alloc_host(c, f.host_bytes(), pin);
+    if (!f.host) throw std::bad_alloc();
+    par_memcpy(f.host, nullptr, f.host_bytes());
+    f.last_down.assign(f.nrows, -1);
+    c->fields.push_back(std::move(f));
+    c->pinned.push_back(pin);
+    Field &fr = c->fields.back();
+    if (init) copy_extent(c, fr, nullptr, init, false);
+    *out = (ooc_field)(c->fields.size() - 1);
+    return OOC_OK;
+  });
+}
+
+int ooc_decl_reduction(ooc_ctx *c, int op, ooc_red *out) {
+  GUARD(c);
+  if (!out || op < OOC_RED_MIN || op > OOC_RED_SUM) return OOC_E_ARG;
+  if (c->ready) return fail(c, OOC_E_STATE, "reductions must be declared before the first flush");
+  Reduction r;
+  r.op = op;
+  c->reds.push_back(r);
+  *out = (ooc_red)(c->reds.size() - 1);
+  return OOC_OK;
+}
+
+int ooc_set_reduction(ooc_ctx *c, ooc_red h, double v) {
+  GUARD(c);
+  if (h < 0 || h >= (int)c->reds.size()) return OOC_E_ARG;
+  return guarded(c, [&]() -> int {
+    Reduction &r = c->reds[h];
+    if (!c->ready) {
+      r.host_value = v;
+      r.host_set = true;
+      return OOC_OK;
+    }
+    int rc = flush(c);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(r.committed, &v, 8, hipMemcpyHostToDevice, c->s_comp));
+    HIPCHK(hipStreamSynchronize(c->s_comp));
+    return OOC_OK;
+  });
+}
+
+int ooc_par_loop(ooc_ctx *c, int kid, const int64_t range[6], int nargs, const ooc_arg *args) {
+  GUARD(c);
+  if (!range) return OOC_E_ARG;
+  return guarded(c, [&]() -> int {
+    LoopRec L;
+    check_loop(c, kid, range, nargs, args, L);
+    L.marks_before = c->marks;
+    c->queue.push_back(std::move(L));
+    return OOC_OK;
+  });
+}
+
+int ooc_mark_step(ooc_ctx *c) {
+  GUARD(c);
+  c->marks++;
+  return OOC_OK;
+}
+
+int ooc_execute(ooc_ctx *c) {
+  GUARD(c);
+  return guarded(c, [&]() -> int { return flush(c); });
+}
+
+int ooc_reduce(ooc_ctx *c, ooc_red h, double *out) {
+  GUARD(c);
+  if (h < 0 || h >= (int)c->reds.size() || !out) return OOC_E_ARG;
+  return guarded(c, [&]() -> int {
+    int rc = flush(c);
+    if (rc) return rc;
+    if (!c->ready) {
+      *out = c->reds[h].host_value;
+      return OOC_OK;
+    }
+    HIPCHK(hipMemcpy(out, c->reds[h].committed, 8, hipMemcpyDeviceToHost));
+    return OOC_OK;
+  });
+}
+
+int ooc_fetch_field(ooc_ctx *c, ooc_field h, double *dst, size_t bytes) {
+  GUARD(c);
+  if (h < 0 || h >= (int)c->fields.size() || !dst) return OOC_E_ARG;
+  return guarded(c, [&]() -> int {
+    Field &f = c->fields[h];
+    if (bytes != (size_t)(f.n[0] * f.n[1] * f.n[2] * 8)) throw ArgError(OOC_E_ARG, "size mismatch");
+    int rc = flush(c);
+    if (rc) return rc;
+    if (f.resident && c->ready && !f.host_valid) {
+      HIPCHK(hipMemcpy(f.host, f.dev_res, (size_t)f.nrows * f.row_elems * 8, hipMemcpyDeviceToHost));
+      f.host_valid = true;
+    }
+    if (f.stale) throw ArgError(OOC_E_STALE, "field '" + f.name + "' is a temporary not downloaded (Cyclic)");
+    copy_extent(c, f, dst, nullptr, true);
+    return OOC_OK;
+  });
+}
+
+int ooc_set_field(ooc_ctx *c, ooc_field h, const double *src, size_t bytes) {
+  GUARD(c);
+  if (h < 0 || h >= (int)c->fields.size() || !src) return OOC_E_ARG;
+  return guarded(c, [&]() -> int {
+    Field &f = c->fields[h];
+    if (bytes != (size_t)(f.n[0] * f.n[1] * f.n[2] * 8)) throw ArgError(OOC_E_ARG, "size mismatch");
+    int rc = flush(c);
+    if (rc) return rc;
+    copy_extent(c, f, nullptr, src, false);
+    f.stale = false;
+    if (f.resident && c->ready) {
+      HIPCHK(hipMemcpy(f.dev_res, f.host, (size_t)f.nrows * f.row_elems * 8, hipMemcpyHostToDevice));
+      f.host_valid = true;
+    }
+    return OOC_OK;
+  });
+}
+
+int ooc_set_flags(ooc_ctx *c, uint32_t set, uint32_t clear) {
+  GUARD(c);
+  const uint32_t fixed = OOC_FLAG_FP32_STREAM | OOC_FLAG_INCORE;
+  if ((set | clear) & fixed) return fail(c, OOC_E_STATE, "FP32_STREAM and INCORE are fixed at creation");
+  return guarded(c, [&]() -> int {
+    int rc = flush(c);  // flags apply to chains queued from now on
+    if (rc) return rc;
+    c->flags = (c->flags | set) & ~clear;
+    return OOC_OK;
+  });
+}
+
+int ooc_set_schedule(ooc_ctx *c, int64_t tile_rows, int chain_steps, int slots) {
+  GUARD(c);
+  if (tile_rows < 0 || chain_steps < 0 || slots < 0 || slots == 1 || slots > 8) return OOC_E_ARG;
+  return guarded(c, [&]() -> int {
+    int rc = flush(c);
+    if (rc) return rc;
+    const int s = slots ? slots : 3;
+    if (c->ready && s != c->slots) {
+      const uint64_t base = (uint64_t)(c->slot_base - c->arena);
+      const size_t budget = std::min(c->budget, c->arena_bytes);
+      c->slot_stride = (budget - base) / s / 256 * 256;
+    }
+    c->tile_rows = tile_rows;
+    c->chain_steps = chain_steps;
+    c->slots = s;
+    c->plans.clear();
+    return OOC_OK;
+  });
+}
+
+int ooc_get_stats(ooc_ctx *c, ooc_stats *out) {
+  if (!c || !out) return OOC_E_ARG;
+  *out = c->st;
+  return OOC_OK;
+}
+
+int ooc_set_timing(ooc_ctx *c, int on) {
+  GUARD(c);
+  c->timing = on != 0;
+  c->kstats.clear();
+  return OOC_OK;
+}
+
+int ooc_kernel_stats(ooc_ctx *c, int kid, double *ms, uint64_t *launches, uint64_t *bytes) {
+  if (!c) return OOC_E_ARG;
+  auto it = c->kstats.find(kid);
+  KStat k = it == c->kstats.end() ? KStat() : it->second;
+  if (ms) *ms = k.ms;
+  if (launches) *launches = k.launches;
+  if (bytes) *bytes = k.bytes;
+  return OOC_OK;
+}
+
+const char *ooc_last_error(ooc_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int ooc_destroy(ooc_ctx *c) {
+  if (!c) return OOC_E_ARG;
+  if (c->ready && !c->failed) {
+    (void)hipStreamSynchronize(c->s_up);
+    (void)hipStreamSynchronize(c->s_comp);
+    (void)hipStreamSynchronize(c->s_down);
+  }
+  for (auto *v : {&c->ev_up, &c->ev_comp, &c->ev_down, &c->tev_pool})
+    for (hipEvent_t e : *v) (void)hipEventDestroy(e);
+  for (size_t k = 0; k < c->fields.size(); k++) free_host(c->fields[k].host, c->pinned[k]);
+  if (c->own_streams) {
+    (void)hipStreamDestroy(c->s_up);
+    (void)hipStreamDestroy(c->s_comp);
+    (void)hipStreamDestroy(c->s_down);
+  }
+  if (c->own_arena) (void)hipFree(c->arena);
+  delete c;
+  return OOC_OK;
+}
+
+int ooc_field_shape(ooc_ctx *c, ooc_field h, int64_t lo[3], int64_t n[3]) {
+  if (!c || h < 0 || h >= (int)c->fields.size()) return OOC_E_ARG;
+  for (int d = 0; d < 3; d++) {
+    if (lo) lo[d] = c->fields[h].lo[d];
+    if (n) n[d] = c->fields[h].n[d];
+  }
+  return OOC_OK;
+}
+
+int ooc_debug_plan(ooc_ctx *c, ooc_plan_info *out) {
+  GUARD(c);
+  if (!out) return OOC_E_ARG;
+  return guarded(c, [&]() -> int {
+    if (c->queue.empty()) throw ArgError(OOC_E_STATE, "nothing queued");
+    // the first chain of the queue, split as a flush would split it
+    int end = (int)c->queue.size();
+    {
+      std::vector<int> wr;
+      int marks0 = c->queue[0].marks_before;
+      for (int i = 0; i < (int)c->queue.size(); i++) {
+        const LoopRec &L = c->queue[i];
+        bool split = c->chain_steps > 0 && L.marks_before - marks0 >= c->chain_steps;
+        for (const ArgRec &g : L.args)
+          if ((g.kind == OOC_ARG_DEVSCALAR || g.kind == OOC_ARG_RED) &&
+              std::find(wr.begin(), wr.end(), g.handle) != wr.end())
+            split = true;
+        if (split && i > 0) {
+          end = i;
+          break;
+        }
+        for (const ArgRec &g : L.args)
+          if (g.kind == OOC_ARG_RED) wr.push_back(g.handle);
+      }
+    }
+    c->dbg = get_plan(c, c->queue.data(), end);
+    const Plan &P = c->dbg;
+    const int nf = (int)c->fields.size();
+    c->dbg_loop_rows.assign((size_t)P.nloops * P.T * 2, 0);
+    for (int i = 0; i < P.nloops; i++)
+      for (int t = 0; t < P.T; t++) {
+        c->dbg_loop_rows[((size_t)i * P.T + t) * 2] = P.s(i, t);
+        c->dbg_loop_rows[((size_t)i * P.T + t) * 2 + 1] = P.en(i, t);
+      }
+    c->dbg_res.assign((size_t)nf * P.T * 2, 0);
+    for (int f : P.slot_fields)
+      for (int t = 0; t < P.T; t++) {
+        c->dbg_res[((size_t)f * P.T + t) * 2] = P.resA[(size_t)f * P.T + t];
+        c->dbg_res[((size_t)f * P.T + t) * 2 + 1] = P.resB[(size_t)f * P.T + t];
+      }
+    auto pack = [](const std::vector<Run> &v, std::vector<int64_t> &o) {
+      o.clear();
+      for (const Run &r : v) o.insert(o.end(), {r.f, r.t, r.lo, r.hi});
+    };
+    pack(P.up, c->dbg_up);
+    pack(P.down, c->dbg_down);
+    pack(P.edge, c->dbg_edge);
+    out->ntiles = P.T;
+    out->nloops = P.nloops;
+    out->nfields = nf;
+    out->slots = c->slots;
+    out->tile_rows = P.h;
+    out->slot_bytes = P.slot_bytes;
+    out->loop_rows = c->dbg_loop_rows.data();
+    out->resident = c->dbg_res.data();
+    out->nup = (int)P.up.size();
+    out->ndown = (int)P.down.size();
+    out->nedge = (int)P.edge.size();
+    out->up = c->dbg_up.data();
+    out->down = c->dbg_down.data();
+    out->edge = c->dbg_edge.data();
+    out->temporary = P.temporary.data();
+    return OOC_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,239 @@
+"""Host-only tests of the loop-chain analysis and tile planning (no GPU):
+the plan is taken from the real library (ooc_debug_plan) and executed by the
+numpy tile simulator with NaN-poisoned slots."""
+import numpy as np
+import pytest
+
+from paper_1709_02125_amd import ooc
+from paper_1709_02125_amd.ooc import READ, WRITE, RW, INC, Const, dat
+import tile_sim
+
+H = 2
+CENTRINGS = [(0, 0), (1, 1), (1, 0), (0, 1)]
+
+
+def make_ctx(nx, ny, nfields, rng, budget=1 << 30, flags=0, centrings=None):
+    c = ooc.Context(2, (nx, ny), H, budget, flags, bind=False)
+    host, shapes = {}, {}
+    for f in range(nfields):
+        cen = centrings[f] if centrings else CENTRINGS[rng.integers(len(CENTRINGS))]
+        shape = c.field_shape_for(cen)
+        init = rng.standard_normal(shape)
+        h = c.decl_field("f%d" % f, cen, init)
+        host[h] = init
+        shapes[h] = cen
+    return c, host, shapes
+
+
+def extent(nx, ny, cen):
+    return (-H, nx + H + cen[0]), (-H, ny + H + cen[1])
+
+
+def random_chain(nx, ny, shapes, rng, nloops):
+    """Random valid toy loops (AVG / INC_ADD / MIRROR / FILL)."""
+    fields = list(shapes)
+    loops = []
+    tries = 0
+    while len(loops) < nloops and tries < 2000:
+        tries += 1
+        kind = rng.choice(["avg", "avg", "avg", "inc", "mirror", "fill"])
+        fo = int(rng.choice(fields))
+        ex, ey = extent(nx, ny, shapes[fo])
+        if kind == "fill":
+            x0 = int(rng.integers(ex[0], ex[1]))
+            x1 = int(rng.integers(x0 + 1, ex[1] + 1))
+            y0 = int(rng.integers(ey[0], ey[1]))
+            y1 = int(rng.integers(y0 + 1, ey[1] + 1))
+            loops.append(tile_sim.ToyLoop(tile_sim.K_FILL, ((x0, x1), (y0, y1)), [(fo, WRITE, ((0, 0),))],
+                                          [float(rng.standard_normal())]))
+            continue
+        fi = int(rng.choice([f for f in fields if f != fo] or fields))
+        if kind == "mirror":
+            fi = fo
+            ix, iy = extent(nx, ny, shapes[fi])
+            side = rng.integers(4)
+            dep = int(rng.integers(1, H + 1))
+            if side < 2:  # strip along y boundary (bottom/top) rows, mirrored read
+                y0 = ey[0] if side == 0 else ey[1] - dep
+                y1 = y0 + dep
+                oy = (2 * dep) if side == 0 else -(2 * dep)
+                rng_ = ((ex[0], ex[1]), (y0, y1))
+                off = (0, oy)
+            else:
+                x0 = ex[0] if side == 2 else ex[1] - dep
+                ox = (2 * dep) if side == 2 else -(2 * dep)
+                rng_ = ((x0, x0 + dep), (ey[0], ey[1]))
+                off = (ox, 0)
+            loops.append(tile_sim.ToyLoop(tile_sim.K_MIRROR, rng_, [(fo, WRITE, ((0, 0),)), (fi, READ, (off,))],
+                                          [float(rng.choice([-1.0, 1.0]))]))
+            continue
+        ix, iy = extent(nx, ny, shapes[fi])
+        if kind == "inc":
+            offs = ((0, 0),)
+        else:
+            npts = int(rng.integers(1, 5))
+            offs = tuple((int(rng.integers(-2, 3)), int(rng.integers(-2, 3))) for _ in range(npts))
+        mnx, mxx = min(o[0] for o in offs), max(o[0] for o in offs)
+        mny, mxy = min(o[1] for o in offs), max(o[1] for o in offs)
+        lx0, lx1 = max(ex[0], ix[0] - mnx), min(ex[1], ix[1] - mxx)
+        ly0, ly1 = max(ey[0], iy[0] - mny), min(ey[1], iy[1] - mxy)
+        if lx1 <= lx0 or ly1 <= ly0:
+            continue
+        x0 = int(rng.integers(lx0, lx1))
+        x1 = int(rng.integers(x0 + 1, lx1 + 1))
+        if rng.random() < 0.5:
+            x0, x1 = lx0, lx1
+        y0 = int(rng.integers(ly0, ly1))
+        y1 = int(rng.integers(y0 + 1, ly1 + 1))
+        if rng.random() < 0.6:
+            y0, y1 = ly0, ly1
+        if kind == "inc":
+            loops.append(tile_sim.ToyLoop(tile_sim.K_INC_ADD, ((x0, x1), (y0, y1)),
+                                          [(fo, INC, ((0, 0),)), (fi, READ, offs)], [0.5]))
+        else:
+            loops.append(tile_sim.ToyLoop(tile_sim.K_AVG, ((x0, x1), (y0, y1)),
+                                          [(fo, WRITE, ((0, 0),)), (fi, READ, offs)],
+                                          [float(rng.uniform(0.5, 1.5)), float(rng.standard_normal())]))
+    return loops
+
+
+def queue(c, loops):
+    for lp in loops:
+        args = [dat(f, acc, *offs) for (f, acc, offs) in lp.dats] + [Const(v) for v in lp.consts]
+        c.par_loop(lp.kid, lp.rng, args)
+
+
+def test_skew_closed_form_for_jacobi_chain():
+    # k radius-1 smoothing loops alternating between two fields: every loop
+    # must run exactly one row ahead of the next one (read-after-write plus
+    # write-after-read of radius 1), so the first loop leads the last by k-1.
+    rng = np.random.default_rng(0)
+    nx, ny, k = 6, 60, 7
+    c, host, shapes = make_ctx(nx, ny, 2, rng, centrings=[(0, 0), (0, 0)])
+    c.set_schedule(tile_rows=10)
+    a, b = 0, 1
+    for n in range(k):
+        src, dst = (a, b) if n % 2 == 0 else (b, a)
+        c.par_loop(tile_sim.K_AVG, ((0, nx), (-1, ny + 1)),
+                   [dat(dst, WRITE), dat(src, READ, (0, -1), (0, 0), (0, 1)), Const(1.0), Const(0.0)])
+    p = c.debug_plan()
+    e = p["loop_rows"][:, :, 1]
+    for t in range(p["ntiles"] - 1):
+        lead = e[:, t]
+        if lead[0] < ny + 1:  # interior tiles, before the clamp at the range end
+            assert list(np.diff(lead)) == [-1] * (k - 1)
+            assert lead[-1] == -1 + (t + 1) * 10  # cut: span start + (t+1) h
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_chains_tiled_equals_untiled(seed):
+    rng = np.random.default_rng(seed)
+    nx, ny = int(rng.integers(3, 9)), int(rng.integers(5, 14))
+    nf = int(rng.integers(2, 5))
+    _, _, shapes = make_ctx(nx, ny, nf, np.random.default_rng(seed))
+    loops = random_chain(nx, ny, shapes, rng, int(rng.integers(3, 12)))
+    rows = ny + 2 * H + 1
+    cyclic = bool(seed % 2)
+    for slots in (2, 3):
+        for h in range(1, rows + 1):
+            c, host, shapes2 = make_ctx(nx, ny, nf, np.random.default_rng(seed),
+                                        flags=ooc.FLAG_CYCLIC if cyclic else 0)
+            assert shapes2 == shapes
+            c.set_schedule(tile_rows=h, slots=slots)
+            queue(c, loops)
+            p = c.debug_plan()
+            ref = tile_sim.run_untiled(loops, host, H)
+            got = tile_sim.run_tiled(loops, host, p, H, slots)
+            for f in host:
+                if cyclic and p["temporary"][f] and any(d[0] == f for lp in loops for d in lp.dats):
+                    continue  # host copy intentionally stale
+                assert np.array_equal(got[f], ref[f]), (seed, h, slots, f)
+            # partition: every loop's tile ranges tile its range exactly
+            for i, lp in enumerate(loops):
+                lr = p["loop_rows"][i]
+                assert lr[0, 0] == lp.rng[1][0] and lr[-1, 1] == lp.rng[1][1]
+                assert all(lr[t, 1] == lr[t + 1, 0] for t in range(p["ntiles"] - 1))
+                assert all(lr[t, 1] >= lr[t, 0] for t in range(p["ntiles"]))
+            # each row moves at most once per chain in each direction
+            for key in ("up", "down"):
+                seen = set()
+                for f, t, r0, r1 in p[key]:
+                    for r in range(r0, r1):
+                        assert (f, r) not in seen
+                        seen.add((f, r))
+            c.close()
+
+
+def test_hydro_chain_classification():
+    # Section 4.1: read-only data is never downloaded, write-first data never
+    # uploaded, and with Cyclic the write-first temporaries are not downloaded.
+    from paper_1709_02125_amd import hydro2d as h2
+    nx, ny = 24, 300
+    app = h2.Hydro2D(nx, ny, np.full((ny, nx), 0.2), np.full((ny, nx), 1.0), budget=h2.footprint_bytes(nx, ny) // 3,
+                     bind=False)
+    app.ctx.set_flags(ooc.FLAG_CYCLIC, 0)
+    app.queue_step()
+    p = app.ctx.debug_plan()
+    names = [n for n, _ in h2.FIELDS]
+    up = {names[f] for f in p["up"][:, 0]}
+    down = {names[f] for f in p["down"][:, 0]}
+    temp = {names[f] for f in range(len(names)) if p["temporary"][f]}
+    assert up == {"rho0", "e0", "u0", "v0", "vol", "xarea", "yarea"}
+    assert down == {"rho0", "e0", "u0", "v0"}
+    assert temp == set(names) - up
+    assert p["ntiles"] > 3
+    app.close()
+
+
+def test_hydro_chain_without_cyclic_downloads_temporaries():
+    from paper_1709_02125_amd import hydro2d as h2
+    nx, ny = 24, 300
+    app = h2.Hydro2D(nx, ny, np.full((ny, nx), 0.2), np.full((ny, nx), 1.0), budget=h2.footprint_bytes(nx, ny) // 2,
+                     bind=False)
+    app.queue_step()
+    p = app.ctx.debug_plan()
+    names = [n for n, _ in h2.FIELDS]
+    down = {names[f] for f in p["down"][:, 0]}
+    assert {"rho1", "p", "q", "w_mf"} <= down
+    assert not ({"vol", "xarea", "yarea"} & down)   # read-only: never downloaded
+    app.close()
+
+
+def test_budget_too_small_is_reported():
+    rng = np.random.default_rng(1)
+    c, host, shapes = make_ctx(8, 8, 2, rng, budget=600, centrings=[(0, 0), (0, 0)])
+    c.par_loop(tile_sim.K_AVG, ((0, 8), (0, 8)), [dat(1, WRITE), dat(0, READ, (0, 0)), Const(1.0), Const(0.0)])
+    with pytest.raises(ooc.OocError) as e:
+        c.debug_plan()
+    assert e.value.code == ooc.E_BUDGET
+
+
+@pytest.mark.parametrize("bad", ["write_offset", "outside", "race", "kernel", "sig"])
+def test_par_loop_rejects_invalid_loops(bad):
+    rng = np.random.default_rng(2)
+    c, host, shapes = make_ctx(8, 8, 2, rng, centrings=[(0, 0), (0, 0)])
+    with pytest.raises(ooc.OocError) as e:
+        if bad == "write_offset":
+            c.par_loop(tile_sim.K_AVG, ((0, 8), (0, 8)), [dat(1, WRITE, (0, 1)), dat(0, READ), Const(1), Const(0)])
+        elif bad == "outside":
+            c.par_loop(tile_sim.K_AVG, ((0, 8), (0, 8)), [dat(1, WRITE), dat(0, READ, (0, 3)), Const(1), Const(0)])
+        elif bad == "race":
+            c.par_loop(tile_sim.K_AVG, ((0, 8), (0, 8)), [dat(0, WRITE), dat(0, READ, (0, 1)), Const(1), Const(0)])
+        elif bad == "kernel":
+            c.par_loop(9999, ((0, 8), (0, 8)), [dat(0, WRITE)])
+        else:
+            c.par_loop(tile_sim.K_AVG, ((0, 8), (0, 8)), [dat(1, WRITE), dat(0, READ)])
+    assert e.value.code == ooc.E_ARG
+    c.close()
+
+
+def test_library_exports_every_declared_symbol():
+    import re
+    import os
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "ooc.h")).read()
+    names = set(re.findall(r"^(?:int|const char \*)\s*(ooc_\w+)\(", hdr, re.M))
+    lib = ooc.load_library()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(ooc.EXPORTS) == names

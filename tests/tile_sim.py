@@ -1,0 +1,113 @@
+"""Host-side tile simulator (test infrastructure).
+
+Executes a chain of toy loops twice in numpy: once untiled (every loop over its
+full range, in program order) and once following the library's plan exactly
+as the device pipeline would: per tile, a NaN-poisoned slot buffer per field,
+the edge copy from the previous tile's slot, the planned uploads, every loop
+over its planned rows of that tile, then the planned downloads.  Any missing
+upload or edge row, or a wrong skew, shows up as a NaN or a difference.
+
+The toy kernels are defined here (not in the library and not in the oracle):
+  AVG      out = c0 * mean_k in(p + o_k) + c1
+  INC_ADD  out = out + c * in
+  MIRROR   dst_q = sign_q * src_q(p + o_q)
+  FILL     dst = value
+"""
+import numpy as np
+
+K_MIRROR, K_FILL, K_AVG, K_INC_ADD = 1, 2, 4, 5
+
+
+class ToyLoop:
+    def __init__(self, kid, rng, dats, consts):
+        self.kid, self.rng, self.dats, self.consts = kid, rng, dats, consts  # dats: (field, access, offsets)
+
+
+def apply_loop(loop, get, put, rows):
+    """Run one toy loop over x-range x its rows (a (lo, hi) along y)."""
+    (x0, x1), _ = loop.rng
+    j0, j1 = rows
+    if j1 <= j0 or x1 <= x0:
+        return
+    J, I = np.meshgrid(np.arange(j0, j1), np.arange(x0, x1), indexing="ij")
+    if loop.kid == K_AVG:
+        (fo, _, _), (fi, _, offs) = loop.dats
+        s = np.zeros(J.shape)
+        for (ox, oy) in offs:
+            s = s + get(fi, I + ox, J + oy)
+        put(fo, I, J, loop.consts[0] * (s / float(len(offs))) + loop.consts[1])
+    elif loop.kid == K_INC_ADD:
+        (fo, _, _), (fi, _, _) = loop.dats
+        put(fo, I, J, get(fo, I, J) + loop.consts[0] * get(fi, I, J))
+    elif loop.kid == K_MIRROR:
+        vals = []
+        for q in range(len(loop.dats) // 2):
+            fs, _, offs = loop.dats[2 * q + 1]
+            ox, oy = offs[0]
+            vals.append(loop.consts[q] * get(fs, I + ox, J + oy))
+        for q in range(len(loop.dats) // 2):
+            put(loop.dats[2 * q][0], I, J, vals[q])
+    elif loop.kid == K_FILL:
+        put(loop.dats[0][0], I, J, np.full(J.shape, loop.consts[0]))
+    else:
+        raise ValueError(loop.kid)
+
+
+def run_untiled(loops, host, H):
+    arr = {f: a.copy() for f, a in host.items()}
+
+    def get(f, I, J):
+        return arr[f][J + H, I + H]
+
+    def put(f, I, J, v):
+        arr[f][J + H, I + H] = v
+
+    for lp in loops:
+        apply_loop(lp, get, put, lp.rng[1])
+    return arr
+
+
+def run_tiled(loops, host, plan, H, slots):
+    """Follow the plan; returns the host arrays after all downloads."""
+    T = plan["ntiles"]
+    res = plan["resident"]
+    arr = {f: a.copy() for f, a in host.items()}
+    ncols = {f: a.shape[1] for f, a in host.items()}
+    used = sorted(set(f for lp in loops for (f, _, _) in lp.dats))
+    cap = {f: int(max(res[f, t, 1] - res[f, t, 0] for t in range(T))) for f in used}
+    slot = {}  # (s, f) -> array
+    up = {t: [r for r in plan["up"] if r[1] == t] for t in range(T)}
+    down = {t: [r for r in plan["down"] if r[1] == t] for t in range(T)}
+    edge = {t: [r for r in plan["edge"] if r[1] == t] for t in range(T)}
+    for t in range(T):
+        s = t % slots
+        for f in used:
+            slot[(s, f)] = np.full((max(cap[f], 1), ncols[f]), np.nan)
+        if t > 0:
+            ps = (t - 1) % slots
+            for f, _, r0, r1 in edge[t]:
+                A0, A1 = res[f, t - 1, 0], res[f, t, 0]
+                slot[(s, f)][r0 - A1:r1 - A1] = slot[(ps, f)][r0 - A0:r1 - A0]
+        for f, _, r0, r1 in up[t]:
+            A = res[f, t, 0]
+            slot[(s, f)][r0 - A:r1 - A] = arr[f][r0:r1]
+
+        def get(f, I, J, t=t, s=s):
+            A, B = res[f, t, 0], res[f, t, 1]
+            r = J + H
+            assert (r >= A).all() and (r < B).all(), "read outside the rows held for tile %d" % t
+            return slot[(s, f)][r - A, I + H]
+
+        def put(f, I, J, v, t=t, s=s):
+            A, B = res[f, t, 0], res[f, t, 1]
+            r = J + H
+            assert (r >= A).all() and (r < B).all(), "write outside the rows held for tile %d" % t
+            slot[(s, f)][r - A, I + H] = v
+
+        for i, lp in enumerate(loops):
+            a, b = plan["loop_rows"][i, t]
+            apply_loop(lp, get, put, (a, b))
+        for f, _, r0, r1 in down[t]:
+            A = res[f, t, 0]
+            arr[f][r0:r1] = slot[(s, f)][r0 - A:r1 - A]
+    return arr
