@@ -152,6 +152,11 @@ int ooc_mark_step(ooc_ctx *ctx);
 /* Flush: analyse and execute everything queued, then wait for the device. */
 int ooc_execute(ooc_ctx *ctx);
 
+/* Analyse and issue everything queued without waiting for the device: the
+ * chains run asynchronously on the context's streams while the caller queues
+ * more loops.  The next ooc_execute or data-returning call waits. */
+int ooc_submit(ooc_ctx *ctx);
+
 /* Flush, then return the committed value of a reduction (Section 3: getting
  * the result of a reduction ends the chain). */
 int ooc_reduce(ooc_ctx *ctx, ooc_red red, double *out);

@@ -26,6 +26,7 @@
  * Build: gcc -O2 -ffp-contract=off -fopenmp (no fast-math, no contraction).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -69,6 +70,7 @@ void h2d_destroy(h2d_state *s) {
 }
 
 double *h2d_field(h2d_state *s, int k) { return s->f[k]; }
+int oracle_threads(void) { return omp_get_max_threads(); }
 long h2d_pitch(h2d_state *s) { return s->pitch; }
 long h2d_rows(h2d_state *s) { return s->rows; }
 

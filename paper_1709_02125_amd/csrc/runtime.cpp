@@ -94,6 +94,7 @@ struct ooc_ctx {
   uint64_t slot_stride = 0;
   // tiles and events
   int64_t gtile = 0, gbase = 0, gsynced = -1;
+  int64_t prev_last_tile = -1;  // last tile of the previously issued chain
   std::vector<hipEvent_t> ev_up, ev_comp, ev_down;  // indexed by g - gbase
   std::map<std::string, Plan> plans;
   Plan dbg;
@@ -466,7 +467,12 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
     wait_tile(c, c->s_up, c->ev_down, g - S);  // slot free again
     if (t == 0 && prev_last_tile >= 0 && !(c->flags & OOC_FLAG_PREFETCH))
       wait_tile(c, c->s_up, c->ev_comp, prev_last_tile);  // no early start of the next chain
-    if (c->flags & OOC_FLAG_DEBUG_POISON) launch_fill((double *)slot, P.slot_bytes / 8, NAN, c->s_up);
+    if (c->flags & OOC_FLAG_DEBUG_POISON) {
+      // a slot with an incoming edge was poisoned on the compute stream just
+      // before that edge copy (see below); order this tile's uploads after it
+      if (t == 0) launch_fill((double *)slot, P.slot_bytes / 8, NAN, c->s_up);
+      else wait_tile(c, c->s_up, c->ev_comp, g - 1);
+    }
     int64_t waited = -1;
     for (const Run *r : up[t]) {
       Field &f = c->fields[r->f];
@@ -491,10 +497,11 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
     for (int i = 0; i < n; i++)
       if (P.s(i, t) < P.en(i, t) && loop_nonempty(L[i], c->ndim)) launch_loop(c, L[i], P, i, t, slot);
     // ---- hand the right edge to the next tile's slot (on the compute stream)
-    if (t + 1 < T && !edge[t + 1].empty()) {
+    const bool poison = (c->flags & OOC_FLAG_DEBUG_POISON) != 0;
+    if (t + 1 < T && (poison || !edge[t + 1].empty())) {
       wait_tile(c, c->s_comp, c->ev_down, g + 1 - S);  // next slot free again
-      if (c->flags & OOC_FLAG_DEBUG_POISON) HIPCHK(hipStreamSynchronize(c->s_up));
       char *nslot = c->slot_base + (uint64_t)((g + 1) % S) * c->slot_stride;
+      if (poison) launch_fill((double *)nslot, P.slot_bytes / 8, NAN, c->s_comp);
       std::vector<CopySeg> segs;
       for (const Run *r : edge[t + 1]) {
         Field &f = c->fields[r->f];
@@ -575,9 +582,16 @@ void collect_timing(ooc_ctx *c) {
   c->tev_next = 0;
 }
 
-// Split the queue into chains and run them back to back, then wait.
-int flush(ooc_ctx *c) {
-  if (c->queue.empty()) return OOC_OK;
+// Split the queue into chains and issue them back to back; with wait, block
+// until the device has finished everything issued so far.
+int flush(ooc_ctx *c, bool wait = true) {
+  if (c->queue.empty()) {
+    if (wait && c->ready && c->gtile - 1 > c->gsynced) {
+      sync_all(c);
+      if (c->timing) collect_timing(c);
+    }
+    return OOC_OK;
+  }
   setup_device(c);
   auto t0 = std::chrono::steady_clock::now();
   c->st.last_bytes_h2d = c->st.last_bytes_d2h = 0;
@@ -604,12 +618,12 @@ int flush(ooc_ctx *c) {
     }
     chains.push_back({start, (int)c->queue.size()});
   }
-  int64_t prev_last = -1;
   for (auto &ch : chains) {
-    run_chain(c, c->queue.data() + ch.first, ch.second - ch.first, prev_last);
-    prev_last = c->gtile - 1;
+    run_chain(c, c->queue.data() + ch.first, ch.second - ch.first, c->prev_last_tile);
+    c->prev_last_tile = c->gtile - 1;
   }
   c->queue.clear();
+  if (!wait) return OOC_OK;
   sync_all(c);
   if (c->timing) collect_timing(c);
   c->st.last_flush_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -707,6 +721,7 @@ extern "C" {
 
 int ooc_create(ooc_ctx **out, int ndim, const int64_t dims[3], int halo, size_t budget, uint32_t flags) {
   if (!out || (ndim != 2 && ndim != 3) || !dims || halo < 0 || halo > 8) return OOC_E_ARG;
+  if (flags & OOC_FLAG_FP32_STREAM) return OOC_E_ARG;  // float32 streaming: not available yet
   for (int d = 0; d < ndim; d++)
     if (dims[d] < 1 || dims[d] > (1 << 24)) return OOC_E_ARG;
   ooc_ctx *c = new (std::nothrow) ooc_ctx();
@@ -818,6 +833,11 @@ int ooc_mark_step(ooc_ctx *c) {
 int ooc_execute(ooc_ctx *c) {
   GUARD(c);
   return guarded(c, [&]() -> int { return flush(c); });
+}
+
+int ooc_submit(ooc_ctx *c) {
+  GUARD(c);
+  return guarded(c, [&]() -> int { return flush(c, false); });
 }
 
 int ooc_reduce(ooc_ctx *c, ooc_red h, double *out) {

@@ -41,6 +41,16 @@ def footprint_bytes(nx: int, ny: int) -> int:
     return tot
 
 
+def device_footprint_bytes(nx: int, ny: int) -> int:
+    """Device bytes to hold every field resident in the library's padded
+    layout (row pitch rounded up to 32 elements), plus reduction buffers."""
+    pitch = (nx + 2 * H + 1 + 31) // 32 * 32
+    tot = 0
+    for _, (dx, dy) in FIELDS:
+        tot += ((ny + 2 * H + dy) * pitch * 8 + 255) // 256 * 256
+    return tot + 64 * 1024 + ((ny + 2 * H + 1) * 8 + 255) // 256 * 256
+
+
 def full_extent(nx, ny, centring, interior=None):
     a = np.zeros((ny + 2 * H + centring[1], nx + 2 * H + centring[0]))
     if interior is not None:
@@ -206,9 +216,14 @@ class Hydro2D:
         self._loop(K_SUM_PROD, ((0, self.nx), (0, self.ny)), self.d("rho0"), self.d("vol"), Red(self.mass))
 
     # ---------------------------------------------------------------- driver
-    def run(self, steps: int):
+    def run(self, steps: int, overlap: bool = True):
+        """Advance `steps` steps.  With overlap, each step is issued as soon as
+        it is queued (ooc_submit), so the host queues step n+1 while the device
+        runs step n; the call returns when the device is done."""
         for _ in range(steps):
             self.queue_step()
+            if overlap:
+                self.ctx.submit()
         self.ctx.execute()
 
     def fetch(self, name: str) -> np.ndarray:

@@ -58,7 +58,7 @@ class ooc_plan_info(ctypes.Structure):
 
 
 EXPORTS = ["ooc_create", "ooc_bind_device", "ooc_decl_field", "ooc_decl_reduction", "ooc_set_reduction",
-           "ooc_par_loop", "ooc_mark_step", "ooc_execute", "ooc_reduce", "ooc_fetch_field",
+           "ooc_par_loop", "ooc_mark_step", "ooc_execute", "ooc_submit", "ooc_reduce", "ooc_fetch_field",
            "ooc_set_field", "ooc_set_flags", "ooc_set_schedule", "ooc_get_stats", "ooc_set_timing",
            "ooc_kernel_stats", "ooc_last_error", "ooc_destroy", "ooc_debug_plan", "ooc_field_shape"]
 
@@ -72,6 +72,10 @@ def load_library() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError("libooc.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    # PyTorch-ROCm ships its own HIP runtime with the same soname as the system
+    # one; load torch first so the library binds to that single runtime instead
+    # of bringing a second HIP/HSA runtime into the process.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, I, I64, U32, SZ, D = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32,
                              ctypes.c_size_t, ctypes.c_double)
@@ -87,6 +91,7 @@ def load_library() -> ctypes.CDLL:
         "ooc_par_loop": [P, I, I64P, I, ctypes.POINTER(ooc_arg)],
         "ooc_mark_step": [P],
         "ooc_execute": [P],
+        "ooc_submit": [P],
         "ooc_reduce": [P, ctypes.c_int32, DP],
         "ooc_fetch_field": [P, ctypes.c_int32, DP, SZ],
         "ooc_set_field": [P, ctypes.c_int32, DP, SZ],
@@ -246,6 +251,9 @@ class Context:
 
     def execute(self):
         self._check(self.lib.ooc_execute(self._h))
+
+    def submit(self):
+        self._check(self.lib.ooc_submit(self._h))
 
     def reduce(self, r: int) -> float:
         v = ctypes.c_double()

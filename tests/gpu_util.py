@@ -1,0 +1,66 @@
+"""Helpers shared by the GPU tests: running the hydro proxy through the HIP
+library and through the CPU oracle on the same seeded input."""
+import sys
+
+import numpy as np
+
+from paper_1709_02125_amd import hydro2d as h2, ooc
+from paper_1709_02125_amd.inputs import hydro_initial_state
+
+H = 2
+STATE = ("rho0", "e0", "u0", "v0")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(g, o):
+    """Max-norm error relative to the oracle field's max magnitude; a field
+    that is identically zero in the oracle must be exactly zero."""
+    m = np.abs(o).max()
+    if m == 0.0:
+        return 0.0 if np.all(g == 0.0) else np.inf
+    return np.abs(g - o).max() / m
+
+
+def gpu_hydro(nx, ny, steps, budget=None, flags=0, tile_rows=0, slots=0, incore=False, rho=None, ene=None,
+              per_step_dt=False, resident_geometry=False):
+    if rho is None:
+        rho, ene = hydro_initial_state((nx, ny))
+    if incore:
+        flags |= ooc.FLAG_INCORE
+        budget = h2.device_footprint_bytes(nx, ny)
+    elif budget is None:
+        budget = h2.footprint_bytes(nx, ny) // 3
+    app = h2.Hydro2D(nx, ny, rho, ene, budget=budget, flags=flags, resident_geometry=resident_geometry)
+    if tile_rows or slots:
+        app.ctx.set_schedule(tile_rows=tile_rows, slots=slots)
+    dts = [app.initialise()]
+    if per_step_dt:
+        for _ in range(steps):
+            app.queue_step()
+            dts.append(app.ctx.reduce(app.dt))
+    else:
+        app.run(steps)
+        dts.append(app.ctx.reduce(app.dt))
+    out = {n: app.fetch(n) for n in STATE}
+    st = app.ctx.stats()
+    app.close()
+    return out, dts, st
+
+
+def oracle_hydro(nx, ny, steps, rho=None, ene=None):
+    import oracle.hydro2d as oh
+    if rho is None:
+        rho, ene = hydro_initial_state((nx, ny))
+    o = oh.Hydro2D(nx, ny)
+    o.set_state(rho, ene)
+    dts, nxt = o.run(steps)
+    out = {}
+    for n in STATE:
+        a = o.field(n)
+        c = dict(h2.FIELDS)[n]
+        out[n] = a[:ny + 2 * H + c[1], :nx + 2 * H + c[0]].copy()
+    return out, dts + [nxt]

@@ -1,0 +1,117 @@
+"""GPU parity of the 2D hydro proxy: HIP library vs the CPU oracle (1e-12 per
+field), and tiled vs untiled runs of the library (bit-exact)."""
+import numpy as np
+import pytest
+
+from paper_1709_02125_amd import hydro2d as h2, ooc
+from gpu_util import STATE, gpu_hydro, oracle_hydro, rel_err, say
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def test_hydro2d_small_tiled_matches_oracle_step_by_step():
+    nx, ny, steps = 96, 80, 6
+    say("case: hydro2d 96x80 tiled 1/3 budget, dt per step")
+    got, gdts, st = gpu_hydro(nx, ny, steps, per_step_dt=True, flags=ooc.FLAG_PREFETCH)
+    ref, odts = oracle_hydro(nx, ny, steps)
+    assert st["ntiles_last"] > 2
+    for n in STATE:
+        e = rel_err(got[n], ref[n])
+        say(n, e)
+        assert e <= TOL, n
+    assert np.allclose(gdts, odts, rtol=TOL, atol=0)
+
+
+def test_hydro2d_c1_config_matches_oracle():
+    # 960 x 960, 10 steps, device budget one third of the footprint, tiles on y
+    nx = ny = 960
+    say("case: hydro2d C1 960^2 10 steps 1/3 budget")
+    got, gdts, st = gpu_hydro(nx, ny, 10, flags=ooc.FLAG_PREFETCH)
+    ref, odts = oracle_hydro(nx, ny, 10)
+    say("tiles", st["ntiles_last"], "rows", st["tile_rows"])
+    assert st["ntiles_last"] >= 3
+    for n in STATE:
+        e = rel_err(got[n], ref[n])
+        say(n, e)
+        assert e <= TOL, n
+    assert abs(gdts[-1] - odts[-1]) <= TOL * odts[-1]
+
+
+@pytest.mark.parametrize("tile_rows,slots,flags", [
+    (1, 2, 0), (2, 3, ooc.FLAG_CYCLIC), (3, 3, ooc.FLAG_PREFETCH | ooc.FLAG_CYCLIC), (7, 4, 0),
+    (16, 3, ooc.FLAG_DEBUG_POISON | ooc.FLAG_CYCLIC), (33, 2, ooc.FLAG_PREFETCH), (0, 3, ooc.FLAG_DEBUG_SYNC)])
+def test_hydro2d_tiled_equals_untiled_bit_exact(tile_rows, slots, flags):
+    nx, ny, steps = 40, 51, 4
+    say("case: tiled vs in-core", tile_rows, slots, flags)
+    ref, rdts, _ = gpu_hydro(nx, ny, steps, incore=True)
+    got, gdts, st = gpu_hydro(nx, ny, steps, budget=h2.footprint_bytes(nx, ny), tile_rows=tile_rows,
+                              slots=slots, flags=flags)
+    for n in STATE:
+        assert np.array_equal(got[n], ref[n]), n
+    assert gdts == rdts
+
+
+def test_hydro2d_incore_matches_oracle():
+    nx, ny, steps = 64, 48, 8
+    say("case: in-core vs oracle")
+    got, gdts, _ = gpu_hydro(nx, ny, steps, incore=True)
+    ref, odts = oracle_hydro(nx, ny, steps)
+    for n in STATE:
+        assert rel_err(got[n], ref[n]) <= TOL, n
+
+
+def test_hydro2d_resident_geometry_bit_exact():
+    nx, ny, steps = 48, 60, 3
+    say("case: resident geometry")
+    ref, _, _ = gpu_hydro(nx, ny, steps, incore=True)
+    got, _, st = gpu_hydro(nx, ny, steps, budget=h2.footprint_bytes(nx, ny) // 2, resident_geometry=True)
+    for n in STATE:
+        assert np.array_equal(got[n], ref[n]), n
+
+
+def test_hydro2d_transfer_bytes_match_plan():
+    nx, ny = 64, 90
+    say("case: transfer bytes vs plan")
+    from paper_1709_02125_amd.inputs import hydro_initial_state
+    rho, ene = hydro_initial_state((nx, ny))
+    app = h2.Hydro2D(nx, ny, rho, ene, budget=h2.footprint_bytes(nx, ny) // 3)
+    app.initialise()
+    app.queue_step()
+    p = app.ctx.debug_plan()
+    pitch = (nx + 5 + 31) // 32 * 32
+    up = int((p["up"][:, 3] - p["up"][:, 2]).sum()) * pitch * 8
+    down = int((p["down"][:, 3] - p["down"][:, 2]).sum()) * pitch * 8
+    app.ctx.execute()
+    st = app.ctx.stats()
+    assert st["last_bytes_h2d"] == up and st["last_bytes_d2h"] == down
+    names = [n for n, _ in h2.FIELDS]
+    assert {names[f] for f in p["down"][:, 0]} == {"rho0", "e0", "u0", "v0"}
+    app.close()
+
+
+def test_hydro2d_mass_sum_is_tiling_independent_and_conserved():
+    nx, ny = 80, 70
+    say("case: mass sum")
+    from paper_1709_02125_amd.inputs import hydro_initial_state
+    import oracle.hydro2d as oh
+    rho, ene = hydro_initial_state((nx, ny))
+    masses = []
+    for incore in (True, False):
+        flags = ooc.FLAG_INCORE if incore else 0
+        budget = h2.device_footprint_bytes(nx, ny) if incore else h2.footprint_bytes(nx, ny) // 3
+        app = h2.Hydro2D(nx, ny, rho, ene, budget=budget, flags=flags)
+        app.initialise()
+        app.queue_mass()
+        m0 = app.ctx.reduce(app.mass)
+        app.run(5)
+        app.queue_mass()
+        m1 = app.ctx.reduce(app.mass)
+        masses.append((m0, m1))
+        app.close()
+    assert masses[0] == masses[1]
+    m0, m1 = masses[0]
+    assert abs(m1 - m0) <= 1e-13 * m0
+    o = oh.Hydro2D(nx, ny)
+    o.set_state(rho, ene)
+    assert abs(o.sum_cells("rho0") - m0) <= 1e-12 * m0

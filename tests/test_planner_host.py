@@ -237,3 +237,11 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(ooc.EXPORTS) == names
+
+
+def test_single_hip_runtime_in_process():
+    import re
+    ooc.load_library()
+    maps = open("/proc/self/maps").read()
+    hips = set(re.findall(r"\S*libamdhip64\S*", maps))
+    assert len(hips) == 1, hips
