@@ -618,6 +618,26 @@ int flush(ooc_ctx *c, bool wait = true) {
     }
     chains.push_back({start, (int)c->queue.size()});
   }
+  // Cyclic skips downloads of temporaries, which leaves their host copies
+  // stale; a later chain that reads such a field before writing it would read
+  // garbage.  Follow the stale state through the chains before issuing any.
+  {
+    std::vector<char> stale(c->fields.size());
+    for (size_t f = 0; f < c->fields.size(); f++) stale[f] = c->fields[f].stale;
+    const bool cyclic = (c->flags & OOC_FLAG_CYCLIC) != 0;
+    for (auto &ch : chains) {
+      const Plan &P = get_plan(c, c->queue.data() + ch.first, ch.second - ch.first);
+      for (const Run &r : P.up)
+        if (stale[r.f]) {
+          c->queue.clear();
+          throw ArgError(OOC_E_STALE, "field '" + c->fields[r.f].name +
+                                          "' is read before written, but its host copy was skipped as a "
+                                          "temporary under Cyclic in an earlier chain");
+        }
+      for (size_t f = 0; f < c->fields.size(); f++)
+        if (P.written[f] && !c->fields[f].resident) stale[f] = cyclic && P.temporary[f];
+    }
+  }
   for (auto &ch : chains) {
     run_chain(c, c->queue.data() + ch.first, ch.second - ch.first, c->prev_last_tile);
     c->prev_last_tile = c->gtile - 1;

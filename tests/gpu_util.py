@@ -26,7 +26,7 @@ def rel_err(g, o):
 
 
 def gpu_hydro(nx, ny, steps, budget=None, flags=0, tile_rows=0, slots=0, incore=False, rho=None, ene=None,
-              per_step_dt=False, resident_geometry=False):
+              per_step_dt=False, resident_geometry=False, cyclic=True):
     if rho is None:
         rho, ene = hydro_initial_state((nx, ny))
     if incore:
@@ -34,7 +34,8 @@ def gpu_hydro(nx, ny, steps, budget=None, flags=0, tile_rows=0, slots=0, incore=
         budget = h2.device_footprint_bytes(nx, ny)
     elif budget is None:
         budget = h2.footprint_bytes(nx, ny) // 3
-    app = h2.Hydro2D(nx, ny, rho, ene, budget=budget, flags=flags, resident_geometry=resident_geometry)
+    app = h2.Hydro2D(nx, ny, rho, ene, budget=budget, flags=flags, resident_geometry=resident_geometry,
+                     cyclic_after_init=cyclic)
     if tile_rows or slots:
         app.ctx.set_schedule(tile_rows=tile_rows, slots=slots)
     dts = [app.initialise()]

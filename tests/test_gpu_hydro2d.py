@@ -38,15 +38,18 @@ def test_hydro2d_c1_config_matches_oracle():
     assert abs(gdts[-1] - odts[-1]) <= TOL * odts[-1]
 
 
-@pytest.mark.parametrize("tile_rows,slots,flags", [
-    (1, 2, 0), (2, 3, ooc.FLAG_CYCLIC), (3, 3, ooc.FLAG_PREFETCH | ooc.FLAG_CYCLIC), (7, 4, 0),
-    (16, 3, ooc.FLAG_DEBUG_POISON | ooc.FLAG_CYCLIC), (33, 2, ooc.FLAG_PREFETCH), (0, 3, ooc.FLAG_DEBUG_SYNC)])
-def test_hydro2d_tiled_equals_untiled_bit_exact(tile_rows, slots, flags):
+@pytest.mark.parametrize("tile_rows,slots,flags,cyclic", [
+    (1, 2, 0, False), (2, 3, 0, True), (3, 3, ooc.FLAG_PREFETCH, True), (7, 4, 0, False),
+    (16, 3, ooc.FLAG_DEBUG_POISON, True), (33, 2, ooc.FLAG_PREFETCH, False), (0, 3, ooc.FLAG_DEBUG_SYNC, True)])
+def test_hydro2d_tiled_equals_untiled_bit_exact(tile_rows, slots, flags, cyclic):
     nx, ny, steps = 40, 51, 4
-    say("case: tiled vs in-core", tile_rows, slots, flags)
+    say("case: tiled vs in-core", tile_rows, slots, flags, cyclic)
     ref, rdts, _ = gpu_hydro(nx, ny, steps, incore=True)
-    got, gdts, st = gpu_hydro(nx, ny, steps, budget=h2.footprint_bytes(nx, ny), tile_rows=tile_rows,
-                              slots=slots, flags=flags)
+    # budget large enough for any forced tile height at this slot count
+    got, gdts, st = gpu_hydro(nx, ny, steps, budget=slots * h2.device_footprint_bytes(nx, ny),
+                              tile_rows=tile_rows, slots=slots, flags=flags, cyclic=cyclic)
+    if tile_rows:
+        assert st["ntiles_last"] == -(-(ny + 4) // tile_rows) or st["ntiles_last"] >= 2
     for n in STATE:
         assert np.array_equal(got[n], ref[n]), n
     assert gdts == rdts
@@ -115,3 +118,21 @@ def test_hydro2d_mass_sum_is_tiling_independent_and_conserved():
     o = oh.Hydro2D(nx, ny)
     o.set_state(rho, ene)
     assert abs(o.sum_cells("rho0") - m0) <= 1e-12 * m0
+
+
+def test_cyclic_before_init_is_refused():
+    # Section 4.1: Cyclic is unsafe while the initialisation phase still writes
+    # data that later chains read (here: the mesh geometry); the library must
+    # refuse the read of a skipped temporary instead of using stale data.
+    nx, ny = 32, 40
+    say("case: cyclic before init")
+    from paper_1709_02125_amd.inputs import hydro_initial_state
+    rho, ene = hydro_initial_state((nx, ny))
+    app = h2.Hydro2D(nx, ny, rho, ene, budget=h2.footprint_bytes(nx, ny), flags=ooc.FLAG_CYCLIC)
+    app.queue_init()
+    app.ctx.execute()
+    app.queue_step()
+    with pytest.raises(ooc.OocError) as e:
+        app.ctx.execute()
+    assert e.value.code == ooc.E_STALE
+    app.close()
