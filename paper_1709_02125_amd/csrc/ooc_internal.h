@@ -128,6 +128,7 @@ struct Plan {
   std::vector<int64_t> cap;         // [nfields] slab rows
   std::vector<uint64_t> slab_off;   // [nfields] byte offset of the slab inside a slot
   uint64_t slot_bytes = 0;
+  uint64_t stage_up_off = 0, stage_down_off = 0;  // float32 staging inside a slot
   std::vector<Run> up, down, edge;
   std::vector<int> temporary;       // [nfields]
   std::vector<int> written;         // [nfields] written anywhere in the chain

@@ -221,6 +221,29 @@ int make_plan(const PlanInput &in, Plan &P, std::string &err) {
   for (int f = 0; f < nf; f++)
     if (used[f] && !F[f].resident) P.slot_fields.push_back(f);
 
+  // ---- transfer predicates.  A row is uploaded when it first becomes held if
+  // some element of it is read before written, or if it will be downloaded
+  // without every element being written (so the download cannot clobber the
+  // host copy with unset values).  A row is downloaded when it stops being
+  // held if the chain wrote it -- unless Cyclic skips temporaries.
+  std::vector<std::vector<char>> need_up(nf), need_down(nf);
+  bool any_fp32 = false;
+  for (int f : P.slot_fields) {
+    const bool skip_down = in.cyclic && P.temporary[f];
+    need_up[f].assign(F[f].nrows, 0);
+    need_down[f].assign(F[f].nrows, 0);
+    for (int64_t r = 0; r < F[f].nrows; r++) {
+      need_down[f][r] = written[f][r] && !skip_down;
+      need_up[f][r] = readfirst[f][r] || (need_down[f][r] && !full[f][r]);
+    }
+    any_fp32 |= F[f].fp32;
+  }
+  auto count = [](const std::vector<char> &v, int64_t r0, int64_t r1) {
+    int64_t n = 0;
+    for (int64_t r = std::max<int64_t>(r0, 0); r < std::min<int64_t>(r1, (int64_t)v.size()); r++) n += v[r];
+    return n;
+  };
+
   // ---- skewed tiling for a given tile height
   auto tile_plan = [&](int64_t h, Plan &Q) -> uint64_t {
     const int T = (int)((R - L + h - 1) / h);
@@ -293,8 +316,29 @@ int make_plan(const PlanInput &in, Plan &P, std::string &err) {
       Q.cap[f] = cap;
       bytes += (uint64_t)((cap * F[f].row_bytes_dev() + 255) / 256 * 256);
     }
-    Q.slot_bytes = bytes;
-    return bytes;
+    // float32 streaming: staging for one tile's uploads and one tile's downloads
+    uint64_t sup = 0, sdown = 0;
+    if (any_fp32)
+      for (int t = 0; t < T; t++) {
+        uint64_t u = 0, d = 0;
+        for (int f : P.slot_fields) {
+          if (!F[f].fp32) continue;
+          const int64_t A = Q.resA[(size_t)f * T + t], B = Q.resB[(size_t)f * T + t];
+          if (B <= A) continue;
+          const bool prev = t > 0 && Q.resB[(size_t)f * T + t - 1] > Q.resA[(size_t)f * T + t - 1];
+          const int64_t new0 = prev ? std::max(A, Q.resB[(size_t)f * T + t - 1]) : A;
+          const bool next = t + 1 < T && Q.resB[(size_t)f * T + t + 1] > Q.resA[(size_t)f * T + t + 1];
+          const int64_t leave1 = next ? std::min(B, Q.resA[(size_t)f * T + t + 1]) : B;
+          u += (uint64_t)((count(need_up[f], new0, B) * F[f].row_bytes_host() + 255) / 256 * 256);
+          d += (uint64_t)((count(need_down[f], A, leave1) * F[f].row_bytes_host() + 255) / 256 * 256);
+        }
+        sup = std::max(sup, u);
+        sdown = std::max(sdown, d);
+      }
+    Q.stage_up_off = bytes;
+    Q.stage_down_off = bytes + sup;
+    Q.slot_bytes = bytes + sup + sdown;
+    return Q.slot_bytes;
   };
 
   const int64_t span = R - L;
@@ -331,6 +375,8 @@ int make_plan(const PlanInput &in, Plan &P, std::string &err) {
   P.resB.swap(Q.resB);
   P.cap.swap(Q.cap);
   P.slot_bytes = Q.slot_bytes;
+  P.stage_up_off = Q.stage_up_off;
+  P.stage_down_off = Q.stage_down_off;
   P.slab_off.assign(nf, 0);
   {
     uint64_t off = 0;
@@ -340,16 +386,11 @@ int make_plan(const PlanInput &in, Plan &P, std::string &err) {
     }
   }
 
-  // ---- transfer sets.  A row is uploaded when it first becomes held if some
-  // element of it is read before written, or if it will be downloaded without
-  // every element being written (so the download cannot clobber the host copy
-  // with unset values).  A row is downloaded when it stops being held if the
-  // chain wrote it -- unless Cyclic skips temporaries.
+  // ---- transfer sets (runs of consecutive rows)
   const int T = P.T;
   for (int f : P.slot_fields) {
-    const bool skip_down = in.cyclic && P.temporary[f];
-    auto need_down = [&](int64_t r) { return written[f][r] && !skip_down; };
-    auto need_up = [&](int64_t r) { return readfirst[f][r] || (need_down(r) && !full[f][r]); };
+    auto up_pred = [&](int64_t r) { return need_up[f][r] != 0; };
+    auto down_pred = [&](int64_t r) { return need_down[f][r] != 0; };
     auto emit = [&](std::vector<Run> &out, int t, int64_t r0, int64_t r1, auto pred) {
       int64_t r = r0;
       while (r < r1) {
@@ -366,11 +407,11 @@ int make_plan(const PlanInput &in, Plan &P, std::string &err) {
       bool prev = t > 0 && P.resB[(size_t)f * T + t - 1] > P.resA[(size_t)f * T + t - 1];
       if (prev) pB = P.resB[(size_t)f * T + t - 1];
       const int64_t new0 = prev ? std::max(A, pB) : A;
-      emit(P.up, t, new0, B, need_up);
+      emit(P.up, t, new0, B, up_pred);
       if (prev && pB > A) P.edge.push_back(Run{f, t, A, std::min(pB, B)});
       bool next = t + 1 < T && P.resB[(size_t)f * T + t + 1] > P.resA[(size_t)f * T + t + 1];
       const int64_t leave1 = next ? std::min(B, P.resA[(size_t)f * T + t + 1]) : B;
-      emit(P.down, t, A, leave1, need_down);
+      emit(P.down, t, A, leave1, down_pred);
     }
   }
   return OOC_OK;

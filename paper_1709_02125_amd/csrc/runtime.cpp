@@ -474,6 +474,7 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       else wait_tile(c, c->s_up, c->ev_comp, g - 1);
     }
     int64_t waited = -1;
+    uint64_t stage_up = 0, stage_down = 0;
     for (const Run *r : up[t]) {
       Field &f = c->fields[r->f];
       int64_t dep = -1;
@@ -485,8 +486,15 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       const int64_t A = P.resA[(size_t)r->f * T + t];
       char *dst = slot + P.slab_off[r->f] + (r->lo - A) * f.row_bytes_dev();
       const size_t nb = (size_t)(r->hi - r->lo) * f.row_bytes_host();
-      HIPCHK(hipMemcpyAsync(dst, (char *)f.host + r->lo * f.row_bytes_host(), nb, hipMemcpyHostToDevice,
-                            c->s_up));
+      const char *src = (const char *)f.host + r->lo * f.row_bytes_host();
+      if (f.fp32) {  // float32 rows land in staging, widened into the slab
+        char *stage = slot + P.stage_up_off + stage_up;
+        HIPCHK(hipMemcpyAsync(stage, src, nb, hipMemcpyHostToDevice, c->s_up));
+        launch_f32_to_f64((const float *)stage, (double *)dst, (r->hi - r->lo) * f.row_elems, c->s_up);
+        stage_up += align256(nb);
+      } else {
+        HIPCHK(hipMemcpyAsync(dst, src, nb, hipMemcpyHostToDevice, c->s_up));
+      }
       c->st.bytes_h2d += nb;
       c->st.last_bytes_h2d += nb;
     }
@@ -532,8 +540,15 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       const int64_t A = P.resA[(size_t)r->f * T + t];
       const char *src = slot + P.slab_off[r->f] + (r->lo - A) * f.row_bytes_dev();
       const size_t nb = (size_t)(r->hi - r->lo) * f.row_bytes_host();
-      HIPCHK(hipMemcpyAsync((char *)f.host + r->lo * f.row_bytes_host(), src, nb, hipMemcpyDeviceToHost,
-                            c->s_down));
+      char *dst = (char *)f.host + r->lo * f.row_bytes_host();
+      if (f.fp32) {  // rounded to float32 (nearest even) in staging, then sent
+        char *stage = slot + P.stage_down_off + stage_down;
+        launch_f64_to_f32((const double *)src, (float *)stage, (r->hi - r->lo) * f.row_elems, c->s_down);
+        HIPCHK(hipMemcpyAsync(dst, stage, nb, hipMemcpyDeviceToHost, c->s_down));
+        stage_down += align256(nb);
+      } else {
+        HIPCHK(hipMemcpyAsync(dst, src, nb, hipMemcpyDeviceToHost, c->s_down));
+      }
       for (int64_t q = r->lo; q < r->hi; q++) f.last_down[q] = g;
       c->st.bytes_d2h += nb;
       c->st.last_bytes_d2h += nb;
@@ -741,7 +756,6 @@ extern "C" {
 
 int ooc_create(ooc_ctx **out, int ndim, const int64_t dims[3], int halo, size_t budget, uint32_t flags) {
   if (!out || (ndim != 2 && ndim != 3) || !dims || halo < 0 || halo > 8) return OOC_E_ARG;
-  if (flags & OOC_FLAG_FP32_STREAM) return OOC_E_ARG;  // float32 streaming: not available yet
   for (int d = 0; d < ndim; d++)
     if (dims[d] < 1 || dims[d] > (1 << 24)) return OOC_E_ARG;
   ooc_ctx *c = new (std::nothrow) ooc_ctx();

@@ -136,3 +136,26 @@ def test_cyclic_before_init_is_refused():
         app.ctx.execute()
     assert e.value.code == ooc.E_STALE
     app.close()
+
+
+def test_hydro2d_fp32_streaming_error_is_stated_and_tiling_independent():
+    # Extension: streamed fields stored and moved as float32 (rounded to nearest
+    # even on the way out, widened exactly on the way in); compute, dt and the
+    # sums stay float64.  The error against the float64 oracle is reported, and
+    # different tilings give identical results (each chain rounds the state
+    # once, whatever the tiles).
+    nx, ny, steps = 96, 120, 20
+    say("case: fp32 streaming")
+    flags = ooc.FLAG_FP32_STREAM | ooc.FLAG_PREFETCH
+    a, adts, st = gpu_hydro(nx, ny, steps, flags=flags, resident_geometry=True,
+                            budget=h2.footprint_bytes(nx, ny) // 3)
+    b, bdts, _ = gpu_hydro(nx, ny, steps, flags=flags, resident_geometry=True, tile_rows=5, slots=4,
+                           budget=h2.footprint_bytes(nx, ny))
+    for n in STATE:
+        assert np.array_equal(a[n], b[n]), n
+    assert st["ntiles_last"] > 2
+    ref, odts = oracle_hydro(nx, ny, steps)
+    errs = {n: rel_err(a[n], ref[n]) for n in STATE}
+    say("fp32 streaming max rel error after %d steps:" % steps, errs)
+    for n, e in errs.items():
+        assert e < 1e-4, (n, e)
