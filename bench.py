@@ -25,9 +25,12 @@ def log(*a):
 
 
 def timed_run(app, steps, warmup, timing):
+    """Warm up, then time `steps` steps with wall clock between device syncs.
+    With timing, a further pass of `timing` steps records every launch with
+    hipEvents on the compute stream (kept out of the timed region)."""
     import torch
     app.run(warmup)
-    app.ctx.set_timing(timing)
+    app.ctx.set_timing(False)
     s0 = app.ctx.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -38,6 +41,11 @@ def timed_run(app, steps, warmup, timing):
     d = {k: s1[k] - s0[k] for k in ("bytes_h2d", "bytes_d2h", "bytes_edge", "bytes_hbm_alg", "tiles", "chains",
                                      "launches")}
     d["seconds"] = t1 - t0
+    d["issue_ms"] = s1["last_issue_ms"]
+    d["max_call_ms"] = s1["max_call_ms"]
+    if timing:
+        app.ctx.set_timing(True)
+        app.run(timing)
     d["ntiles"] = s1["ntiles_last"]
     d["tile_rows"] = s1["tile_rows"]
     d["slot_bytes"] = s1["slot_bytes"]
@@ -91,6 +99,7 @@ def main():
     ap.add_argument("--n", type=int, default=15360)
     ap.add_argument("--budget", type=float, default=16e9)
     ap.add_argument("--resident-geometry", action="store_true")
+    ap.add_argument("--fp32", action="store_true", help="store and stream fields as float32 on the host")
     ap.add_argument("--no-prefetch", action="store_true")
     ap.add_argument("--no-cyclic", action="store_true")
     ap.add_argument("--no-incore", action="store_true")
@@ -114,6 +123,8 @@ def main():
 
     # ---- out of core: budget capped, tiles streamed through HBM
     flags = 0 if args.no_prefetch else ooc.FLAG_PREFETCH
+    if args.fp32:
+        flags |= ooc.FLAG_FP32_STREAM
     t = time.perf_counter()
     app = h2.Hydro2D(nx, ny, rho, ene, budget=int(args.budget), flags=flags,
                      resident_geometry=args.resident_geometry, cyclic_after_init=not args.no_cyclic)
@@ -121,15 +132,16 @@ def main():
         app.ctx.set_schedule(tile_rows=args.tile_rows, slots=args.slots)
     app.initialise()
     log("out-of-core setup %.1f s" % (time.perf_counter() - t))
-    ooc_r = timed_run(app, args.steps, args.warmup, timing=True)
+    ooc_r = timed_run(app, args.steps, args.warmup, timing=2)
     ooc_dom = dominant_kernel(app)
     ooc_kernel_ms = {KNAMES.get(k, str(k)): app.ctx.kernel_stats(k)[0] for k in KNAMES}
     app.close()
     del app
     torch.cuda.empty_cache()
     ooc_rate = cells * args.steps / ooc_r["seconds"]
-    log("out-of-core: %.3f s/step, %.3g upd/s, tiles %d x %d rows" %
-        (ooc_r["seconds"] / args.steps, ooc_rate, ooc_r["ntiles"], ooc_r["tile_rows"]))
+    log("out-of-core: %.3f s/step, %.3g upd/s, tiles %d x %d rows, host issue %.1f ms (max call %.2f ms)" %
+        (ooc_r["seconds"] / args.steps, ooc_rate, ooc_r["ntiles"], ooc_r["tile_rows"], ooc_r["issue_ms"],
+         ooc_r["max_call_ms"]))
 
     # ---- in core: same grid and kernels, every field resident
     inc_rate, inc_r, dom = None, None, ooc_dom
@@ -138,7 +150,7 @@ def main():
         app = h2.Hydro2D(nx, ny, rho, ene, budget=h2.device_footprint_bytes(nx, ny), flags=ooc.FLAG_INCORE)
         app.initialise()
         log("in-core setup %.1f s" % (time.perf_counter() - t))
-        inc_r = timed_run(app, args.steps, args.warmup, timing=True)
+        inc_r = timed_run(app, args.steps, args.warmup, timing=5)
         dom = dominant_kernel(app)
         app.close()
         del app
@@ -177,7 +189,8 @@ def main():
                                 h2.footprint_bytes(nx, ny) / args.budget),
                    "global_batch": cells, "seq_len": 1, "parallelism": "single-gpu",
                    "prefetch": not args.no_prefetch, "cyclic": not args.no_cyclic,
-                   "resident_geometry": args.resident_geometry, "tiles": ooc_r["ntiles"],
+                   "resident_geometry": args.resident_geometry, "fp32_stream": args.fp32,
+                   "tiles": ooc_r["ntiles"],
                    "tile_rows": ooc_r["tile_rows"], "slots": args.slots or 3},
         "incore_value": inc_rate,
         "pct_of_incore": round(100.0 * ooc_rate / inc_rate, 2) if inc_rate else None,

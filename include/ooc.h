@@ -102,12 +102,15 @@ typedef struct {
   uint64_t slot_bytes;                         /* bytes of one slot of the last plan */
   double last_flush_ms;                        /* device time of the last flush */
   double last_kernel_ms;                       /* summed kernel time of the last flush (if timed) */
+  double last_issue_ms;                        /* host time spent issuing the last flush's chains */
+  double max_call_ms;                          /* longest single runtime call while issuing */
 } ooc_stats;
 
 /* Create a context for a grid of ndim (2 or 3) axes with dims[a] interior cells
  * per axis and halo depth `halo` (Section 3: a block).  device_budget_bytes
- * caps the device memory the context may use (tile slots, resident fields and
- * reduction buffers).  Nothing is allocated on the device here. */
+ * caps the device memory the context may use for data: tile slots, resident
+ * fields and reduction buffers (the kernels' launch-argument table, a few MB,
+ * is allocated apart from it).  Nothing is allocated on the device here. */
 int ooc_create(ooc_ctx **out, int ndim, const int64_t dims[3], int halo,
                size_t device_budget_bytes, uint32_t flags);
 

@@ -17,7 +17,8 @@ KernelInfo *kernel_table() {
 
 // ---------------------------------------------------------------- generic
 // dst_q(p) = sign_q * src_q(p + o_q) for each of the n pairs.
-__global__ void __launch_bounds__(256) k_mirror(KArgs a) {
+OOC_KERNEL(k_mirror) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   const int n = a.ndat / 2;
   for (int q = 0; q < n; q++) {
@@ -26,25 +27,29 @@ __global__ void __launch_bounds__(256) k_mirror(KArgs a) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_fill_pt(KArgs a) {
+OOC_KERNEL(k_fill_pt) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   AT(0, 0, 0, 0) = a.c[0];
 }
 
 // out = c0 * (sum over the stencil of in) / npts + c1, stencil summed in order
-__global__ void __launch_bounds__(256) k_avg(KArgs a) {
+OOC_KERNEL(k_avg) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   double s = 0.0;
   for (int q = 0; q < a.nst; q++) s += AT(1, a.st[q][0], a.st[q][1], a.st[q][2]);
   AT(0, 0, 0, 0) = a.c[0] * (s / (double)a.nst) + a.c[1];
 }
 
-__global__ void __launch_bounds__(256) k_inc_add(KArgs a) {
+OOC_KERNEL(k_inc_add) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   AT(0, 0, 0, 0) = AT(0, 0, 0, 0) + a.c[0] * AT(1, 0, 0, 0);
 }
 
-__global__ void __launch_bounds__(256) k_minmax(KArgs a) {
+OOC_KERNEL(k_minmax) {
+  ARGS
   POINT_INDEX_ACTIVE;
   double v = active ? AT(0, 0, 0, 0) : INFINITY;
   double w = active ? AT(0, 0, 0, 0) : -INFINITY;
@@ -55,7 +60,8 @@ __global__ void __launch_bounds__(256) k_minmax(KArgs a) {
 // One block per row (y, z): the row's product sum in a fixed order, written to
 // the row's partial slot.  Independent of tiling because a row is always
 // summed by one block in the same order.
-__global__ void __launch_bounds__(256) k_sum_prod(KArgs a) {
+OOC_KERNEL(k_sum_prod) {
+  ARGS
   const int j = a.lo[1] + blockIdx.y;
   const int k = a.lo[2] + blockIdx.z;
   double s = 0.0;
@@ -72,24 +78,24 @@ __global__ void __launch_bounds__(256) k_sum_prod(KArgs a) {
   }
 }
 
-void launch_point(void (*k)(KArgs), const KArgs &a, int ndim, void *s) {
+void launch_point(void (*k)(const KArgs *), const KArgs &a, const KArgs *dev, int ndim, void *s) {
   dim3 grid = point_grid(a, ndim);
-  if (grid.x && grid.y && grid.z) hipLaunchKernelGGL(k, grid, dim3(64, 4, 1), 0, (hipStream_t)s, a);
+  if (grid.x && grid.y && grid.z) hipLaunchKernelGGL(k, grid, dim3(64, 4, 1), 0, (hipStream_t)s, dev);
 }
 
-void launch_rows(void (*k)(KArgs), const KArgs &a, int ndim, void *s) {
+void launch_rows(void (*k)(const KArgs *), const KArgs &a, const KArgs *dev, int ndim, void *s) {
   dim3 grid(1, a.hi[1] - a.lo[1], ndim == 3 ? a.hi[2] - a.lo[2] : 1);
-  if (grid.y && grid.z && a.hi[0] > a.lo[0]) hipLaunchKernelGGL(k, grid, dim3(256, 1, 1), 0, (hipStream_t)s, a);
+  if (grid.y && grid.z && a.hi[0] > a.lo[0]) hipLaunchKernelGGL(k, grid, dim3(256, 1, 1), 0, (hipStream_t)s, dev);
 }
 
 #define POINT_LAUNCHER(name, kern) \
-  static void name(const KArgs &a, int nd, void *s) { launch_point(kern, a, nd, s); }
+  static void name(const KArgs &a, const KArgs *d, int nd, void *s) { launch_point(kern, a, d, nd, s); }
 POINT_LAUNCHER(l_mirror, k_mirror)
 POINT_LAUNCHER(l_fill, k_fill_pt)
 POINT_LAUNCHER(l_avg, k_avg)
 POINT_LAUNCHER(l_inc_add, k_inc_add)
 POINT_LAUNCHER(l_minmax, k_minmax)
-static void l_sum_prod(const KArgs &a, int nd, void *s) { launch_rows(k_sum_prod, a, nd, s); }
+static void l_sum_prod(const KArgs &a, const KArgs *d, int nd, void *s) { launch_rows(k_sum_prod, a, d, nd, s); }
 
 void register_common_kernels(KernelInfo *t) {
   t[OOC_K_MIRROR] = {"mirror", 2, 12, -1, 0, 0, kPointGrid, l_mirror};

@@ -9,6 +9,11 @@
 
 namespace ooc {
 
+// Every loop kernel reads its argument block from device memory (a per-chain
+// table built once by the runtime): the launch itself carries one pointer.
+#define OOC_KERNEL(name) __global__ void __launch_bounds__(256) name(const KArgs *__restrict__ ap)
+#define ARGS const KArgs &a = *ap;
+
 // Point kernels run 64 x 4 blocks: one wavefront per row segment of 64 x-points,
 // so every load of a field row is a coalesced 512-byte access.
 #define POINT_INDEX_OR_RETURN                                     \
@@ -96,7 +101,7 @@ __device__ inline double block_sum_fixed(double v) {
   return sm[0];
 }
 
-void launch_point(void (*k)(KArgs), const KArgs &a, int ndim, void *s);
-void launch_rows(void (*k)(KArgs), const KArgs &a, int ndim, void *s);
+void launch_point(void (*k)(const KArgs *), const KArgs &a, const KArgs *dev, int ndim, void *s);
+void launch_rows(void (*k)(const KArgs *), const KArgs &a, const KArgs *dev, int ndim, void *s);
 
 }  // namespace ooc

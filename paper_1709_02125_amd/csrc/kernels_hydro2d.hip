@@ -25,7 +25,8 @@ constexpr double kCq1 = 0.5;  // linear viscosity coefficient
 constexpr double kCfl = 0.5;
 
 // p = (g-1) rho e ; cs = sqrt(g p / rho)
-__global__ void __launch_bounds__(256) k_eos(KArgs a) {
+OOC_KERNEL(k_eos) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   const double r = AT(0, 0, 0, 0);
   const double p = (kGm1 * r) * AT(1, 0, 0, 0);
@@ -33,13 +34,15 @@ __global__ void __launch_bounds__(256) k_eos(KArgs a) {
   AT(3, 0, 0, 0) = sqrt((kGamma * p) / r);
 }
 
-__global__ void __launch_bounds__(256) k_eos_p(KArgs a) {
+OOC_KERNEL(k_eos_p) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   AT(2, 0, 0, 0) = (kGm1 * AT(0, 0, 0, 0)) * AT(1, 0, 0, 0);
 }
 
 // q from the velocity jumps across the cell: compression d = du + dv < 0
-__global__ void __launch_bounds__(256) k_visc(KArgs a) {
+OOC_KERNEL(k_visc) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   const double du = 0.5 * ((AT(2, 1, 0, 0) + AT(2, 1, 1, 0)) - (AT(2, 0, 0, 0) + AT(2, 0, 1, 0)));
   const double dv = 0.5 * ((AT(3, 0, 1, 0) + AT(3, 1, 1, 0)) - (AT(3, 0, 0, 0) + AT(3, 1, 0, 0)));
@@ -53,7 +56,8 @@ __global__ void __launch_bounds__(256) k_visc(KArgs a) {
 // each face; the corrector sums start and end velocities), then density and
 // energy update.  Argument indices of rho1/e1 depend on the phase.
 template <bool kCorr>
-__global__ void __launch_bounds__(256) k_pdv(KArgs a) {
+OOC_KERNEL(k_pdv) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   const double fac = 0.25 * a.ds[0][0];
   double ul, ur, vb, vt;
@@ -82,7 +86,8 @@ __global__ void __launch_bounds__(256) k_pdv(KArgs a) {
 
 // Node acceleration from the pressure + viscosity of the four surrounding
 // cells; wall-normal velocity of wall nodes held at zero.
-__global__ void __launch_bounds__(256) k_accel(KArgs a) {
+OOC_KERNEL(k_accel) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   const double pbl = AT(2, -1, -1, 0) + AT(3, -1, -1, 0);
   const double pbr = AT(2, 0, -1, 0) + AT(3, 0, -1, 0);
@@ -104,14 +109,16 @@ __global__ void __launch_bounds__(256) k_accel(KArgs a) {
 
 // face volume flux of the step; D = 0: x-faces (nodes j, j+1), D = 1: y-faces
 template <int D>
-__global__ void __launch_bounds__(256) k_flux(KArgs a) {
+OOC_KERNEL(k_flux) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   const int ex = D == 1, ey = D == 0;  // step to the face's second node
   const double fac = 0.25 * a.ds[0][0];
   AT(3, 0, 0, 0) = (fac * AT(0, 0, 0, 0)) * ((AT(1, 0, 0, 0) + AT(2, 0, 0, 0)) + (AT(1, ex, ey, 0) + AT(2, ex, ey, 0)));
 }
 
-__global__ void __launch_bounds__(256) k_adv_vol_x(KArgs a) {
+OOC_KERNEL(k_adv_vol_x) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   const double dfx = AT(1, 1, 0, 0) - AT(1, 0, 0, 0);
   const double pre = AT(0, 0, 0, 0) + (dfx + (AT(2, 0, 1, 0) - AT(2, 0, 0, 0)));
@@ -119,7 +126,8 @@ __global__ void __launch_bounds__(256) k_adv_vol_x(KArgs a) {
   AT(4, 0, 0, 0) = pre - dfx;
 }
 
-__global__ void __launch_bounds__(256) k_adv_vol_y(KArgs a) {
+OOC_KERNEL(k_adv_vol_y) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   AT(2, 0, 0, 0) = AT(0, 0, 0, 0) + (AT(1, 0, 1, 0) - AT(1, 0, 0, 0));
   AT(3, 0, 0, 0) = AT(0, 0, 0, 0);
@@ -127,7 +135,8 @@ __global__ void __launch_bounds__(256) k_adv_vol_y(KArgs a) {
 
 // donor-cell mass and energy flux through the face between cells p-e and p
 template <int D>
-__global__ void __launch_bounds__(256) k_adv_flux(KArgs a) {
+OOC_KERNEL(k_adv_flux) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   const int ex = D == 0, ey = D == 1;
   const double f = AT(0, 0, 0, 0);
@@ -144,7 +153,8 @@ __global__ void __launch_bounds__(256) k_adv_flux(KArgs a) {
 }
 
 template <int D>
-__global__ void __launch_bounds__(256) k_adv_cell(KArgs a) {
+OOC_KERNEL(k_adv_cell) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   const int ex = D == 0, ey = D == 1;
   const double pm = AT(0, 0, 0, 0) * AT(2, 0, 0, 0);
@@ -156,7 +166,8 @@ __global__ void __launch_bounds__(256) k_adv_cell(KArgs a) {
 
 // dual-face mass flux: mean of the four face mass fluxes around it
 template <int D>
-__global__ void __launch_bounds__(256) k_nflux(KArgs a) {
+OOC_KERNEL(k_nflux) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   if (D == 0)
     AT(1, 0, 0, 0) = 0.25 * ((AT(0, 0, -1, 0) + AT(0, 0, 0, 0)) + (AT(0, 1, -1, 0) + AT(0, 1, 0, 0)));
@@ -166,7 +177,8 @@ __global__ void __launch_bounds__(256) k_nflux(KArgs a) {
 
 // node masses after the sweep (from the swept cells) and before it
 template <int D>
-__global__ void __launch_bounds__(256) k_nmass(KArgs a) {
+OOC_KERNEL(k_nmass) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   const int ex = D == 0, ey = D == 1;
   const double post = 0.25 * ((AT(0, -1, -1, 0) * AT(1, -1, -1, 0) + AT(0, 0, -1, 0) * AT(1, 0, -1, 0)) +
@@ -177,7 +189,8 @@ __global__ void __launch_bounds__(256) k_nmass(KArgs a) {
 
 // donor-cell momentum flux through the dual face between nodes p and p+e
 template <int D>
-__global__ void __launch_bounds__(256) k_mflux(KArgs a) {
+OOC_KERNEL(k_mflux) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   const int ex = D == 0, ey = D == 1;
   const double f = AT(0, 0, 0, 0);
@@ -188,7 +201,8 @@ __global__ void __launch_bounds__(256) k_mflux(KArgs a) {
 }
 
 template <int D>
-__global__ void __launch_bounds__(256) k_vel(KArgs a) {
+OOC_KERNEL(k_vel) {
+  ARGS
   POINT_INDEX_OR_RETURN;
   const int ex = D == 0, ey = D == 1;
   AT(0, 0, 0, 0) = (AT(0, 0, 0, 0) * AT(1, 0, 0, 0) + (AT(3, -ex, -ey, 0) - AT(3, 0, 0, 0))) / AT(2, 0, 0, 0);
@@ -196,7 +210,8 @@ __global__ void __launch_bounds__(256) k_vel(KArgs a) {
 
 // stable step of a cell, min-reduced: CFL * min over axes of spacing /
 // (sqrt(c^2 + 2 q / rho) + largest node speed along the axis)
-__global__ void __launch_bounds__(256) k_dt(KArgs a) {
+OOC_KERNEL(k_dt) {
+  ARGS
   POINT_INDEX_ACTIVE;
   double t = INFINITY;
   if (active) {
@@ -219,7 +234,7 @@ __global__ void __launch_bounds__(256) k_dt(KArgs a) {
 }
 
 #define L(name, kern) \
-  void name(const KArgs &a, int nd, void *s) { launch_point(kern, a, nd, s); }
+  void name(const KArgs &a, const KArgs *d, int nd, void *s) { launch_point(kern, a, d, nd, s); }
 L(l_eos, k_eos)
 L(l_eos_p, k_eos_p)
 L(l_visc, k_visc)

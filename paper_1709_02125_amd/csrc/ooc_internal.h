@@ -45,7 +45,8 @@ struct KernelInfo {
   int nconst = 0;                  // -1: equals ndat / 2 (MIRROR)
   int ndev = 0, nred = 0;
   int shape = kPointGrid;
-  void (*launch)(const KArgs &, int ndim, void *stream) = nullptr;
+  // host copy (for the grid shape) and device copy (what the kernel reads)
+  void (*launch)(const KArgs &, const KArgs *dev, int ndim, void *stream) = nullptr;
 };
 
 // Registry filled by the kernel translation units.

@@ -105,6 +105,11 @@ struct ooc_ctx {
   std::vector<hipEvent_t> tev_pool;
   size_t tev_next = 0;
   std::map<int, KStat> kstats;
+  // per-chain launch-argument tables: device copy read by the kernels, pinned
+  // host mirror it is uploaded from, cache keyed by chain and slot phase
+  KArgs *argtab_dev = nullptr, *argtab_host = nullptr;
+  size_t argtab_cap = 0, argtab_used = 0;
+  std::map<std::string, size_t> argtab_cache;
   std::string err;
 };
 
@@ -131,9 +136,28 @@ hipEvent_t &evref(std::vector<hipEvent_t> &v, ooc_ctx *c, int64_t g) {
   return v[k];
 }
 
+// Host-side issue profile (OOC_PROFILE_HOST=1 prints it per flush): time spent
+// in each kind of runtime call while issuing.
+enum { kCallH2D, kCallD2H, kCallLaunch, kCallWait, kCallRecord, kCallN };
+double g_call_ms[kCallN];
+int g_call_n[kCallN];
+double g_call_max[kCallN];
+
+template <class Fn>
+void timed_call(ooc_ctx *c, Fn fn, int kind = kCallH2D) {
+  auto a = std::chrono::steady_clock::now();
+  fn();
+  double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
+  c->st.max_call_ms = std::max(c->st.max_call_ms, ms);
+  g_call_ms[kind] += ms;
+  g_call_n[kind]++;
+  g_call_max[kind] = std::max(g_call_max[kind], ms);
+}
+
 void wait_tile(ooc_ctx *c, hipStream_t s, std::vector<hipEvent_t> &v, int64_t g) {
   if (g <= c->gsynced || g < c->gbase) return;
-  HIPCHK(hipStreamWaitEvent(s, evref(v, c, g), 0));
+  hipEvent_t e = evref(v, c, g);
+  timed_call(c, [&] { HIPCHK(hipStreamWaitEvent(s, e, 0)); }, 3);
 }
 
 hipEvent_t timing_event(ooc_ctx *c) {
@@ -228,6 +252,27 @@ int guarded(ooc_ctx *c, Fn fn) {
   }
 }
 
+// The launch-argument table is metadata, not field data: it lives in its own
+// small device allocation (outside the field budget), grown only at a point
+// where no kernel can be reading it.
+void grow_argtab(ooc_ctx *c, size_t entries) {
+  if (entries <= c->argtab_cap) return;
+  if (c->argtab_dev) {
+    HIPCHK(hipStreamSynchronize(c->s_comp));
+    HIPCHK(hipFree(c->argtab_dev));
+    free_host(c->argtab_host, true);
+    c->argtab_dev = nullptr;
+    c->argtab_host = nullptr;
+  }
+  HIPCHK(hipMalloc((void **)&c->argtab_dev, entries * sizeof(KArgs)));
+  bool pin = false;
+  c->argtab_host = (KArgs *)alloc_host(c, entries * sizeof(KArgs), pin);
+  if (!pin) throw DeviceError("pinned allocation of the argument table failed");
+  c->argtab_cap = entries;
+  c->argtab_used = 0;
+  c->argtab_cache.clear();
+}
+
 // ------------------------------------------------------------- device setup
 int64_t sum_partials(const ooc_ctx *c) {
   return c->ndim == 2 ? c->dims[1] + 2 * c->halo + 1
@@ -235,6 +280,8 @@ int64_t sum_partials(const ooc_ctx *c) {
 }
 
 // Device bytes taken ahead of the slots: reduction buffers and resident fields.
+constexpr size_t kArgTableBytes = 8u << 20;  // initial size of the launch-argument table
+
 uint64_t reserved_bytes(const ooc_ctx *c) {
   uint64_t used = 0;
   for (const Reduction &r : c->reds) used += 256 + (r.op == OOC_RED_SUM ? align256(sum_partials(c) * 8) : 0);
@@ -270,6 +317,7 @@ void setup_device(ooc_ctx *c) {
   }
   const size_t budget = std::min(c->budget, c->arena_bytes);
   uint64_t off = 0;
+  grow_argtab(c, kArgTableBytes / sizeof(KArgs));
   for (Reduction &r : c->reds) {
     r.acc = (double *)(c->arena + off);
     r.committed = (double *)(c->arena + off + 8);
@@ -376,8 +424,7 @@ double *field_ptr(ooc_ctx *c, int f, const Plan &P, int t, char *slot) {
   return (double *)(base + shift * 8);
 }
 
-void launch_loop(ooc_ctx *c, const LoopRec &L, const Plan &P, int i, int t, char *slot) {
-  const KernelInfo &ki = table()[L.kid];
+KArgs make_kargs(ooc_ctx *c, const LoopRec &L, const Plan &P, int i, int t, char *slot, uint64_t *bytes_out) {
   KArgs a;
   std::memset(&a, 0, sizeof a);
   for (int d = 0; d < 3; d++) {
@@ -416,15 +463,21 @@ void launch_loop(ooc_ctx *c, const LoopRec &L, const Plan &P, int i, int t, char
     }
   }
   a.ndat = nd;
+  *bytes_out = bytes;
+  return a;
+}
+
+void launch_loop(ooc_ctx *c, int kid, const KArgs &a, const KArgs *dev, uint64_t bytes) {
+  const KernelInfo &ki = table()[kid];
   if (c->timing) {
-    TimedLaunch tl{L.kid, bytes, timing_event(c), timing_event(c)};
+    TimedLaunch tl{kid, bytes, timing_event(c), timing_event(c)};
     HIPCHK(hipEventRecord(tl.a, c->s_comp));
-    ki.launch(a, c->ndim, c->s_comp);
+    ki.launch(a, dev, c->ndim, c->s_comp);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(tl.b, c->s_comp));
     c->timed.push_back(tl);
   } else {
-    ki.launch(a, c->ndim, c->s_comp);
+    timed_call(c, [&] { ki.launch(a, dev, c->ndim, c->s_comp); }, kCallLaunch);
     HIPCHK(hipGetLastError());
   }
   c->st.launches++;
@@ -437,6 +490,7 @@ bool loop_nonempty(const LoopRec &L, int ndim) {
 }
 
 void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
+  auto issue0 = std::chrono::steady_clock::now();
   const Plan &P = get_plan(c, L, n);
   if ((uint64_t)P.slot_bytes > c->slot_stride)
     throw ArgError(OOC_E_BUDGET, "plan does not fit its slot");
@@ -459,6 +513,49 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
   for (const Run &r : P.down) down[r.t].push_back(&r);
   for (const Run &r : P.edge) edge[r.t].push_back(&r);
   const int64_t g0 = c->gtile;
+  // launch arguments of the whole chain, built and uploaded once per distinct
+  // (chain, slot phase) and reused by every later identical chain
+  struct Launch {
+    int kid;
+    uint64_t bytes;
+  };
+  std::vector<Launch> launches;
+  std::vector<KArgs> hostargs;
+  for (int t = 0; t < T; t++) {
+    char *slot = c->slot_base + (uint64_t)((g0 + t) % S) * c->slot_stride;
+    for (int i = 0; i < n; i++)
+      if (P.s(i, t) < P.en(i, t) && loop_nonempty(L[i], c->ndim)) {
+        uint64_t b = 0;
+        hostargs.push_back(make_kargs(c, L[i], P, i, t, slot, &b));
+        launches.push_back({L[i].kid, b});
+      }
+  }
+  std::string akey = plan_key(c, L, n);
+  for (int i = 0; i < n; i++)
+    for (const ArgRec &g : L[i].args)
+      if (g.kind == OOC_ARG_CONST) akey.append((const char *)&g.value, 8);
+  const int64_t phase = g0 % S;
+  akey.append((const char *)&phase, 8);
+  size_t abase;
+  auto hit = c->argtab_cache.find(akey);
+  if (hit != c->argtab_cache.end()) {
+    abase = hit->second;
+  } else {
+    if (hostargs.size() > c->argtab_cap) grow_argtab(c, 2 * hostargs.size());
+    if (c->argtab_used + hostargs.size() > c->argtab_cap) {
+      // table full: wait until no kernel reads it, then start over
+      HIPCHK(hipStreamSynchronize(c->s_comp));
+      c->argtab_cache.clear();
+      c->argtab_used = 0;
+    }
+    abase = c->argtab_used;
+    std::memcpy(c->argtab_host + abase, hostargs.data(), hostargs.size() * sizeof(KArgs));
+    HIPCHK(hipMemcpyAsync(c->argtab_dev + abase, c->argtab_host + abase, hostargs.size() * sizeof(KArgs),
+                          hipMemcpyHostToDevice, c->s_comp));
+    c->argtab_used += hostargs.size();
+    c->argtab_cache.emplace(akey, abase);
+  }
+  size_t li = 0;
   for (int t = 0; t < T; t++) {
     const int64_t g = c->gtile++;
     char *slot = c->slot_base + (uint64_t)(g % S) * c->slot_stride;
@@ -489,21 +586,24 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       const char *src = (const char *)f.host + r->lo * f.row_bytes_host();
       if (f.fp32) {  // float32 rows land in staging, widened into the slab
         char *stage = slot + P.stage_up_off + stage_up;
-        HIPCHK(hipMemcpyAsync(stage, src, nb, hipMemcpyHostToDevice, c->s_up));
+        timed_call(c, [&] { HIPCHK(hipMemcpyAsync(stage, src, nb, hipMemcpyHostToDevice, c->s_up)); });
         launch_f32_to_f64((const float *)stage, (double *)dst, (r->hi - r->lo) * f.row_elems, c->s_up);
         stage_up += align256(nb);
       } else {
-        HIPCHK(hipMemcpyAsync(dst, src, nb, hipMemcpyHostToDevice, c->s_up));
+        timed_call(c, [&] { HIPCHK(hipMemcpyAsync(dst, src, nb, hipMemcpyHostToDevice, c->s_up)); });
       }
       c->st.bytes_h2d += nb;
       c->st.last_bytes_h2d += nb;
     }
-    HIPCHK(hipEventRecord(evref(c->ev_up, c, g), c->s_up));
+    timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_up, c, g), c->s_up)); }, kCallRecord);
     if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_up));
     // ---- execute every loop of the chain over its rows of this tile
-    HIPCHK(hipStreamWaitEvent(c->s_comp, evref(c->ev_up, c, g), 0));
+    timed_call(c, [&] { HIPCHK(hipStreamWaitEvent(c->s_comp, evref(c->ev_up, c, g), 0)); }, kCallWait);
     for (int i = 0; i < n; i++)
-      if (P.s(i, t) < P.en(i, t) && loop_nonempty(L[i], c->ndim)) launch_loop(c, L[i], P, i, t, slot);
+      if (P.s(i, t) < P.en(i, t) && loop_nonempty(L[i], c->ndim)) {
+        launch_loop(c, launches[li].kid, hostargs[li], c->argtab_dev + abase + li, launches[li].bytes);
+        li++;
+      }
     // ---- hand the right edge to the next tile's slot (on the compute stream)
     const bool poison = (c->flags & OOC_FLAG_DEBUG_POISON) != 0;
     if (t + 1 < T && (poison || !edge[t + 1].empty())) {
@@ -531,10 +631,10 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
         else launch_red_commit(r.acc, r.committed, c->s_comp);
       }
     }
-    HIPCHK(hipEventRecord(evref(c->ev_comp, c, g), c->s_comp));
+    timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_comp, c, g), c->s_comp)); }, kCallRecord);
     if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_comp));
     // ---- download the left footprint of modified datasets
-    HIPCHK(hipStreamWaitEvent(c->s_down, evref(c->ev_comp, c, g), 0));
+    timed_call(c, [&] { HIPCHK(hipStreamWaitEvent(c->s_down, evref(c->ev_comp, c, g), 0)); }, kCallWait);
     for (const Run *r : down[t]) {
       Field &f = c->fields[r->f];
       const int64_t A = P.resA[(size_t)r->f * T + t];
@@ -544,16 +644,16 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       if (f.fp32) {  // rounded to float32 (nearest even) in staging, then sent
         char *stage = slot + P.stage_down_off + stage_down;
         launch_f64_to_f32((const double *)src, (float *)stage, (r->hi - r->lo) * f.row_elems, c->s_down);
-        HIPCHK(hipMemcpyAsync(dst, stage, nb, hipMemcpyDeviceToHost, c->s_down));
+        timed_call(c, [&] { HIPCHK(hipMemcpyAsync(dst, stage, nb, hipMemcpyDeviceToHost, c->s_down)); }, kCallD2H);
         stage_down += align256(nb);
       } else {
-        HIPCHK(hipMemcpyAsync(dst, src, nb, hipMemcpyDeviceToHost, c->s_down));
+        timed_call(c, [&] { HIPCHK(hipMemcpyAsync(dst, src, nb, hipMemcpyDeviceToHost, c->s_down)); }, kCallD2H);
       }
       for (int64_t q = r->lo; q < r->hi; q++) f.last_down[q] = g;
       c->st.bytes_d2h += nb;
       c->st.last_bytes_d2h += nb;
     }
-    HIPCHK(hipEventRecord(evref(c->ev_down, c, g), c->s_down));
+    timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_down, c, g), c->s_down)); }, kCallRecord);
     if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_down));
   }
   (void)g0;
@@ -565,6 +665,7 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
     if (fd.resident) fd.host_valid = false;
     else fd.stale = cyclic && P.temporary[f];
   }
+  c->st.last_issue_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - issue0).count();
   c->st.chains++;
   c->st.tiles += T;
   c->st.bytes_hbm_alg += P.alg_bytes;
@@ -610,6 +711,7 @@ int flush(ooc_ctx *c, bool wait = true) {
   setup_device(c);
   auto t0 = std::chrono::steady_clock::now();
   c->st.last_bytes_h2d = c->st.last_bytes_d2h = 0;
+  c->st.last_issue_ms = 0;
   std::vector<std::pair<int, int>> chains;
   {
     int start = 0;
@@ -658,6 +760,16 @@ int flush(ooc_ctx *c, bool wait = true) {
     c->prev_last_tile = c->gtile - 1;
   }
   c->queue.clear();
+  if (std::getenv("OOC_PROFILE_HOST")) {
+    const char *nm[kCallN] = {"h2d", "d2h", "launch", "wait", "record"};
+    std::fprintf(stderr, "[ooc host] issue %.1f ms:", c->st.last_issue_ms);
+    for (int k = 0; k < kCallN; k++) {
+      std::fprintf(stderr, " %s %d calls %.1f ms (max %.2f)", nm[k], g_call_n[k], g_call_ms[k], g_call_max[k]);
+      g_call_ms[k] = g_call_max[k] = 0;
+      g_call_n[k] = 0;
+    }
+    std::fprintf(stderr, "\n");
+  }
   if (!wait) return OOC_OK;
   sync_all(c);
   if (c->timing) collect_timing(c);
@@ -992,6 +1104,8 @@ int ooc_destroy(ooc_ctx *c) {
   for (auto *v : {&c->ev_up, &c->ev_comp, &c->ev_down, &c->tev_pool})
     for (hipEvent_t e : *v) (void)hipEventDestroy(e);
   for (size_t k = 0; k < c->fields.size(); k++) free_host(c->fields[k].host, c->pinned[k]);
+  if (c->argtab_host) free_host(c->argtab_host, true);
+  if (c->argtab_dev) (void)hipFree(c->argtab_dev);
   if (c->own_streams) {
     (void)hipStreamDestroy(c->s_up);
     (void)hipStreamDestroy(c->s_comp);
