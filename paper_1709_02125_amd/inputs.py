@@ -84,3 +84,32 @@ def mirror_symmetrise(a: np.ndarray, axis: int) -> np.ndarray:
     """Make an interior cell array symmetric about the domain mid-plane of `axis`
     (numpy axis) by taking the element-wise max with its reflection."""
     return np.maximum(a, np.flip(a, axis=axis))
+
+
+# ------------------------------------------------------ Taylor-Green vortex
+TGV_MACH = 0.1
+TGV_GAMMA = 1.4
+TGV_PERTURB = 1e-3
+
+
+def tgv_initial_state(n: int, perturb: float = TGV_PERTURB, seed: int = SEED):
+    """Taylor-Green vortex on [0, 2 pi]^3 at cell centres, arrays indexed
+    [z, y, x]: u = sin x cos y cos z, v = -cos x sin y cos z, w = 0,
+    p = p0 + (cos 2x + cos 2y)(cos 2z + 2)/16 with p0 = 1/(gamma M^2), uniform
+    temperature (rho = p / p0); then u, v, w each get perturb * (2 r - 1) with
+    r from SplitMix64(seed), u's n^3 draws first, then v's, then w's."""
+    h = 2.0 * np.pi / n
+    c = (np.arange(n) + 0.5) * h
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    p0 = 1.0 / (TGV_GAMMA * TGV_MACH * TGV_MACH)
+    u = np.sin(x) * np.cos(y) * np.cos(z)
+    v = -np.cos(x) * np.sin(y) * np.cos(z)
+    w = np.zeros_like(u)
+    p = p0 + (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0) / 16.0
+    rho = p / p0
+    if perturb:
+        r = splitmix64_array(seed, 3 * n ** 3).reshape(3, n, n, n)
+        u = u + perturb * (2.0 * r[0] - 1.0)
+        v = v + perturb * (2.0 * r[1] - 1.0)
+        w = w + perturb * (2.0 * r[2] - 1.0)
+    return rho, u, v, w, p
