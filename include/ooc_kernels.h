@@ -71,6 +71,21 @@ enum {
   /* R e0, R u0 4n, R v0 4n; CONST dx, CONST dy; RED(MIN) dt */
   OOC_K_H2D_DT = 122,
 
+  /* ---- 3D Navier-Stokes proxy (tiled along z).  q = conserved (rho, rho u,
+   * rho v, rho w, rho E); prims = (rho, u, v, w, p); grads = du/dx, du/dy,
+   * du/dz, dv/dx, ..., dw/dz, dT/dx, dT/dy, dT/dz.  "S" = the 12-point star
+   * {(+-1,0,0),(+-2,0,0),(0,+-1,0),(0,+-2,0),(0,0,+-1),(0,0,+-2)}. ---- */
+  /* R prims x5, W q x5 */
+  OOC_K_NS_INIT = 200,
+  /* R q x5, W prims x5 */
+  OOC_K_NS_PRIMS = 201,
+  /* R rho S, R u S, R v S, R w S, R p S, W grads x12; CONST 1/(12h), CONST gamma M^2 */
+  OOC_K_NS_GRADS = 202,
+  /* R prims x5 S, R grads x12 S, RW q x5, W dq x5 (first stage) or RW dq x5;
+   * CONST 1/(12h), mu, kappa, dt, A_s, B_s: dq = A_s dq + dt R(q); q += B_s dq */
+  OOC_K_NS_RHS_FIRST = 203,
+  OOC_K_NS_RHS = 204,
+
   OOC_K_MAX_ID = 512
 };
 

@@ -11,7 +11,7 @@
 
 namespace ooc {
 
-constexpr int kMaxDat = 24;
+constexpr int kMaxDat = 32;
 constexpr int kMaxConst = 12;
 constexpr int kMaxDev = 2;
 constexpr int kMaxRed = 2;
@@ -53,6 +53,7 @@ struct KernelInfo {
 KernelInfo *kernel_table();
 void register_common_kernels(KernelInfo *t);
 void register_hydro2d_kernels(KernelInfo *t);
+void register_ns3d_kernels(KernelInfo *t);
 
 // Device helpers implemented in kernels_common.hip.
 struct CopySeg {

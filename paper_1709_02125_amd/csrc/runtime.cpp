@@ -122,6 +122,7 @@ KernelInfo *table() {
     g_table = kernel_table();
     register_common_kernels(g_table);
     register_hydro2d_kernels(g_table);
+    register_ns3d_kernels(g_table);
   }
   return g_table;
 }

@@ -1,0 +1,130 @@
+"""3D compressible Navier-Stokes proxy as a user of the loop-chain library:
+27 fields (5 conserved, 5 Runge-Kutta increments, 5 primitives, 12 stored
+gradients), 15 loops per Runge-Kutta stage (12 boundary strips, primitives,
+gradients, residual + update), 3 stages per step, no reductions -- so a chain
+can span several steps (the paper tiles OpenSBLI over 1, 2 or 3 time steps,
+Section 5.3).  Tiled along z; x and y periodic, z mirror walls."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import ooc
+from .ooc import READ, WRITE, RW, Const, dat
+
+NH = 4
+GAMMA, MACH, PRANDTL = 1.4, 0.1, 0.71
+TWO_PI = 2.0 * math.pi
+RK_A = (0.0, -5.0 / 9.0, -153.0 / 128.0)
+RK_B = (1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0)
+K_MIRROR = 1
+K_INIT, K_PRIMS, K_GRADS, K_RHS_FIRST, K_RHS = 200, 201, 202, 203, 204
+
+Q = ["q_r", "q_ru", "q_rv", "q_rw", "q_re"]
+D = ["d_r", "d_ru", "d_rv", "d_rw", "d_re"]
+P = ["p_r", "p_u", "p_v", "p_w", "p_p"]
+G = ["g_ux", "g_uy", "g_uz", "g_vx", "g_vy", "g_vz", "g_wx", "g_wy", "g_wz", "g_tx", "g_ty", "g_tz"]
+FIELDS = Q + D + P + G
+STAR = ((1, 0, 0), (-1, 0, 0), (2, 0, 0), (-2, 0, 0), (0, 1, 0), (0, -1, 0), (0, 2, 0), (0, -2, 0),
+        (0, 0, 1), (0, 0, -1), (0, 0, 2), (0, 0, -2))
+
+
+def stable_dt(n: int, cfl: float = 0.5) -> float:
+    """Fixed step: cfl * h / (flow speed 1 + sound speed 1/M)."""
+    return cfl * (TWO_PI / n) / (1.0 + 1.0 / MACH)
+
+
+def footprint_bytes(n: int) -> int:
+    return len(FIELDS) * (n + 2 * NH) ** 3 * 8
+
+
+def device_footprint_bytes(n: int) -> int:
+    pitch = (n + 2 * NH + 1 + 31) // 32 * 32
+    plane = pitch * (n + 2 * NH + 1)
+    per = ((n + 2 * NH) * plane * 8 + 255) // 256 * 256
+    return len(FIELDS) * per + (1 << 20)
+
+
+class NS3D:
+    """prims: interior arrays (rho, u, v, w, p), indexed [z, y, x]."""
+
+    def __init__(self, n: int, prims, budget: int, flags: int = 0, re: float = 1600.0, bind: bool = True,
+                 cyclic_after_init: bool = True):
+        self.n = n
+        self.ctx = ooc.Context(3, (n, n, n), NH, budget, flags, bind=bind)
+        self.h = TWO_PI / n
+        self.inv = 1.0 / (12.0 * self.h)
+        self.mu = 1.0 / re
+        self.kappa = self.mu / (((GAMMA - 1.0) * (MACH * MACH)) * PRANDTL)
+        self.gm2 = GAMMA * (MACH * MACH)
+        self.dt = stable_dt(n)
+        self.f = {}
+        m = n + 2 * NH
+        for name in FIELDS:
+            init = None
+            if name in P:
+                init = np.zeros((m, m, m))
+                init[NH:NH + n, NH:NH + n, NH:NH + n] = prims[P.index(name)]
+            self.f[name] = self.ctx.decl_field(name, (0, 0, 0), init)
+        self.cyclic_after_init = cyclic_after_init
+
+    def d(self, name, access=READ, *offs):
+        return dat(self.f[name], access, *offs)
+
+    def initialise(self):
+        n = self.n
+        self.ctx.par_loop(K_INIT, ((0, n), (0, n), (0, n)),
+                          [self.d(x) for x in P] + [self.d(x, WRITE) for x in Q])
+        self.ctx.execute()
+        if self.cyclic_after_init:
+            self.ctx.set_flags(ooc.FLAG_CYCLIC, 0)
+
+    def _mirror_q(self, rng, off, signs=(1.0,) * 5):
+        args = []
+        for name in Q:
+            args += [self.d(name, WRITE), self.d(name, READ, off)]
+        self.ctx.par_loop(K_MIRROR, rng, args + [Const(s) for s in signs])
+
+    def queue_stage(self, s: int):
+        n = self.n
+        full = (-NH, n + NH)
+        # x and y periodic strips, then z mirror walls (rho w odd) layer by layer
+        self._mirror_q(((-NH, 0), (0, n), (0, n)), (n, 0, 0))
+        self._mirror_q(((n, n + NH), (0, n), (0, n)), (-n, 0, 0))
+        self._mirror_q((full, (-NH, 0), (0, n)), (0, n, 0))
+        self._mirror_q((full, (n, n + NH), (0, n)), (0, -n, 0))
+        odd = (1.0, 1.0, 1.0, -1.0, 1.0)
+        for m in range(NH):
+            self._mirror_q((full, full, (-1 - m, -m)), (0, 0, 2 * m + 1), odd)
+            self._mirror_q((full, full, (n + m, n + m + 1)), (0, 0, -2 * m - 1), odd)
+        self.ctx.par_loop(K_PRIMS, (full, full, full), [self.d(x) for x in Q] + [self.d(x, WRITE) for x in P])
+        g2 = (-2, n + 2)
+        self.ctx.par_loop(K_GRADS, (g2, g2, g2), [self.d(x, READ, *STAR) for x in P] +
+                          [self.d(x, WRITE) for x in G] + [Const(self.inv), Const(self.gm2)])
+        first = s == 0
+        self.ctx.par_loop(K_RHS_FIRST if first else K_RHS, ((0, n), (0, n), (0, n)),
+                          [self.d(x, READ, *STAR) for x in P] + [self.d(x, READ, *STAR) for x in G] +
+                          [self.d(x, RW) for x in Q] + [self.d(x, WRITE if first else RW) for x in D] +
+                          [Const(self.inv), Const(self.mu), Const(self.kappa), Const(self.dt), Const(RK_A[s]),
+                           Const(RK_B[s])])
+
+    def queue_step(self):
+        for s in range(3):
+            self.queue_stage(s)
+        self.ctx.mark_step()
+
+    def run(self, steps: int, overlap: bool = True):
+        for _ in range(steps):
+            self.queue_step()
+            if overlap:
+                self.ctx.submit()
+        self.ctx.execute()
+
+    def interior(self, name: str) -> np.ndarray:
+        a = self.ctx.fetch_field(self.f[name], (0, 0, 0))
+        n = self.n
+        return a[NH:NH + n, NH:NH + n, NH:NH + n]
+
+    def close(self):
+        self.ctx.close()
