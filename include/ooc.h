@@ -220,6 +220,27 @@ int ooc_debug_plan(ooc_ctx *ctx, ooc_plan_info *out);
  * elements) of the library's layout. */
 int ooc_field_shape(ooc_ctx *ctx, ooc_field f, int64_t lo[3], int64_t n[3]);
 
+/* ------------------------------------------------------- schedule cost model
+ * A small multilayer perceptron (inputs -> H tanh -> H tanh -> 1 linear, FP64,
+ * mean-squared-error loss) trained on the device by the library's own forward,
+ * backward and Adam kernels.  It learns log time per cell-step of a schedule
+ * (tile height, chain length, buffer depth) from features of the plan, and
+ * proposes schedules; the exhaustive sweep is its fallback and judge.  This is
+ * an extension, not part of the paper.  X is row-major N x n_inputs (host);
+ * all buffers are the caller's and copied. */
+typedef struct ooc_mlp ooc_mlp;
+int ooc_mlp_create(ooc_mlp **out, int n_inputs, int n_hidden, uint64_t seed);
+int ooc_mlp_num_params(ooc_mlp *m);
+/* parameter vector layout: W0[H][D], b0[H], W1[H][H], b1[H], W2[H], b2 */
+int ooc_mlp_get_params(ooc_mlp *m, double *out);
+int ooc_mlp_set_params(ooc_mlp *m, const double *in);  /* also resets Adam state */
+int ooc_mlp_predict(ooc_mlp *m, const double *X, int n, double *out);
+/* gradient of the loss with respect to every parameter (same layout) */
+int ooc_mlp_gradient(ooc_mlp *m, const double *X, const double *y, int n, double *grad, double *loss);
+/* full-batch Adam (beta 0.9 / 0.999, eps 1e-8); loss after the last epoch */
+int ooc_mlp_train(ooc_mlp *m, const double *X, const double *y, int n, int epochs, double lr, double *loss);
+int ooc_mlp_destroy(ooc_mlp *m);
+
 #ifdef __cplusplus
 }
 #endif

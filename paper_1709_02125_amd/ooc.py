@@ -61,7 +61,9 @@ class ooc_plan_info(ctypes.Structure):
 EXPORTS = ["ooc_create", "ooc_bind_device", "ooc_decl_field", "ooc_decl_reduction", "ooc_set_reduction",
            "ooc_par_loop", "ooc_mark_step", "ooc_execute", "ooc_submit", "ooc_reduce", "ooc_fetch_field",
            "ooc_set_field", "ooc_set_flags", "ooc_set_schedule", "ooc_get_stats", "ooc_set_timing",
-           "ooc_kernel_stats", "ooc_last_error", "ooc_destroy", "ooc_debug_plan", "ooc_field_shape"]
+           "ooc_kernel_stats", "ooc_last_error", "ooc_destroy", "ooc_debug_plan", "ooc_field_shape",
+           "ooc_mlp_create", "ooc_mlp_num_params", "ooc_mlp_get_params", "ooc_mlp_set_params",
+           "ooc_mlp_predict", "ooc_mlp_gradient", "ooc_mlp_train", "ooc_mlp_destroy"]
 
 _lib = None
 
@@ -105,6 +107,14 @@ def load_library() -> ctypes.CDLL:
         "ooc_destroy": [P],
         "ooc_debug_plan": [P, ctypes.POINTER(ooc_plan_info)],
         "ooc_field_shape": [P, ctypes.c_int32, I64P, I64P],
+        "ooc_mlp_create": [ctypes.POINTER(P), I, I, ctypes.c_uint64],
+        "ooc_mlp_num_params": [P],
+        "ooc_mlp_get_params": [P, DP],
+        "ooc_mlp_set_params": [P, DP],
+        "ooc_mlp_predict": [P, DP, I, DP],
+        "ooc_mlp_gradient": [P, DP, DP, I, DP, DP],
+        "ooc_mlp_train": [P, DP, DP, I, I, D, DP],
+        "ooc_mlp_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -320,3 +330,67 @@ class Context:
         n = (ctypes.c_int64 * 3)()
         self._check(self.lib.ooc_field_shape(self._h, f, lo, n))
         return tuple(lo), tuple(n)
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Mlp:
+    """The library's device-trained cost-model network (ooc_mlp_*)."""
+
+    def __init__(self, n_inputs: int, n_hidden: int = 32, seed: int = 1709):
+        self.lib = load_library()
+        self._h = ctypes.c_void_p()
+        rc = self.lib.ooc_mlp_create(ctypes.byref(self._h), n_inputs, n_hidden, seed)
+        if rc:
+            raise OocError(rc, "ooc_mlp_create failed")
+        self.n_inputs, self.n_hidden = n_inputs, n_hidden
+        self.n_params = self.lib.ooc_mlp_num_params(self._h)
+
+    def _chk(self, rc, what):
+        if rc:
+            raise OocError(rc, what)
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.n_params)
+        self._chk(self.lib.ooc_mlp_get_params(self._h, _dp(out)), "get_params")
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        assert p.size == self.n_params
+        self._chk(self.lib.ooc_mlp_set_params(self._h, _dp(p)), "set_params")
+
+    def predict(self, X) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        out = np.empty(X.shape[0])
+        self._chk(self.lib.ooc_mlp_predict(self._h, _dp(X), X.shape[0], _dp(out)), "predict")
+        return out
+
+    def gradient(self, X, y):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        g = np.empty(self.n_params)
+        loss = np.empty(1)
+        self._chk(self.lib.ooc_mlp_gradient(self._h, _dp(X), _dp(y), X.shape[0], _dp(g), _dp(loss)), "gradient")
+        return g, float(loss[0])
+
+    def train(self, X, y, epochs: int, lr: float) -> float:
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        loss = np.empty(1)
+        self._chk(self.lib.ooc_mlp_train(self._h, _dp(X), _dp(y), X.shape[0], int(epochs), float(lr), _dp(loss)),
+                  "train")
+        return float(loss[0])
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self.lib.ooc_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
