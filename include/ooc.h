@@ -74,7 +74,8 @@ enum {
   OOC_FLAG_INCORE = 8,        /* keep every field resident on the device (no streaming) */
   OOC_FLAG_GRAPH = 16,        /* replay each chain's tile pipeline from a captured hipGraph */
   OOC_FLAG_DEBUG_POISON = 64, /* fill every slot with NaN before use (finds missing uploads) */
-  OOC_FLAG_DEBUG_SYNC = 128   /* serialise the three streams (separates races from plan bugs) */
+  OOC_FLAG_DEBUG_SYNC = 128,  /* serialise the three streams (separates races from plan bugs) */
+  OOC_FLAG_PLAN_ONLY = 256    /* no host or device storage: for ooc_debug_plan only (schedule search) */
 };
 
 /* per-field flags for ooc_decl_field */
@@ -148,6 +149,10 @@ int ooc_set_reduction(ooc_ctx *ctx, ooc_red red, double value);
 int ooc_par_loop(ooc_ctx *ctx, int kernel_id, const int64_t range[6], int nargs,
                  const ooc_arg *args);
 
+/* Drop everything queued without executing it (after ooc_debug_plan, for
+ * schedule search). */
+int ooc_discard_queue(ooc_ctx *ctx);
+
 /* Mark a step boundary in the queue; with ooc_set_schedule(chain_steps = k)
  * a chain ends after every k marks. */
 int ooc_mark_step(ooc_ctx *ctx);
@@ -155,9 +160,11 @@ int ooc_mark_step(ooc_ctx *ctx);
 /* Flush: analyse and execute everything queued, then wait for the device. */
 int ooc_execute(ooc_ctx *ctx);
 
-/* Analyse and issue everything queued without waiting for the device: the
- * chains run asynchronously on the context's streams while the caller queues
- * more loops.  The next ooc_execute or data-returning call waits. */
+/* Analyse and issue the queued chains without waiting for the device: they
+ * run asynchronously on the context's streams while the caller queues more
+ * loops.  With a chain length set (ooc_set_schedule), a trailing chain that
+ * has not yet reached its step marks stays queued.  The next ooc_execute or
+ * data-returning call issues the rest and waits. */
 int ooc_submit(ooc_ctx *ctx);
 
 /* Flush, then return the committed value of a reduction (Section 3: getting

@@ -702,6 +702,10 @@ void collect_timing(ooc_ctx *c) {
 // Split the queue into chains and issue them back to back; with wait, block
 // until the device has finished everything issued so far.
 int flush(ooc_ctx *c, bool wait = true) {
+  if (c->flags & OOC_FLAG_PLAN_ONLY) {
+    if (c->queue.empty()) return OOC_OK;
+    throw ArgError(OOC_E_STATE, "a plan-only context cannot execute");
+  }
   if (c->queue.empty()) {
     if (wait && c->ready && c->gtile - 1 > c->gsynced) {
       sync_all(c);
@@ -736,6 +740,13 @@ int flush(ooc_ctx *c, bool wait = true) {
     }
     chains.push_back({start, (int)c->queue.size()});
   }
+  // a non-blocking submit issues only complete chains: with a chain length
+  // set, the trailing chain waits until it has all its step marks
+  if (!wait && c->chain_steps > 0) {
+    auto &last = chains.back();
+    if (c->marks - c->queue[last.first].marks_before < c->chain_steps) chains.pop_back();
+    if (chains.empty()) return OOC_OK;
+  }
   // Cyclic skips downloads of temporaries, which leaves their host copies
   // stale; a later chain that reads such a field before writing it would read
   // garbage.  Follow the stale state through the chains before issuing any.
@@ -760,7 +771,7 @@ int flush(ooc_ctx *c, bool wait = true) {
     run_chain(c, c->queue.data() + ch.first, ch.second - ch.first, c->prev_last_tile);
     c->prev_last_tile = c->gtile - 1;
   }
-  c->queue.clear();
+  c->queue.erase(c->queue.begin(), c->queue.begin() + chains.back().second);
   if (std::getenv("OOC_PROFILE_HOST")) {
     const char *nm[kCallN] = {"h2d", "d2h", "launch", "wait", "record"};
     std::fprintf(stderr, "[ooc host] issue %.1f ms:", c->st.last_issue_ms);
@@ -917,14 +928,17 @@ int ooc_decl_field(ooc_ctx *c, const char *name, const int32_t size_delta[3], co
     f.fp32 = (c->flags & OOC_FLAG_FP32_STREAM) && !f.resident;
     layout_field(c, f);
     bool pin = false;
-    f.host = alloc_host(c, f.host_bytes(), pin);
-    if (!f.host) throw std::bad_alloc();
-    par_memcpy(f.host, nullptr, f.host_bytes());
+    const bool plan_only = (c->flags & OOC_FLAG_PLAN_ONLY) != 0;
+    if (!plan_only) {
+      f.host = alloc_host(c, f.host_bytes(), pin);
+      if (!f.host) throw std::bad_alloc();
+      par_memcpy(f.host, nullptr, f.host_bytes());
+    }
     f.last_down.assign(f.nrows, -1);
     c->fields.push_back(std::move(f));
     c->pinned.push_back(pin);
     Field &fr = c->fields.back();
-    if (init) copy_extent(c, fr, nullptr, init, false);
+    if (init && !plan_only) copy_extent(c, fr, nullptr, init, false);
     *out = (ooc_field)(c->fields.size() - 1);
     return OOC_OK;
   });
@@ -971,6 +985,12 @@ int ooc_par_loop(ooc_ctx *c, int kid, const int64_t range[6], int nargs, const o
   });
 }
 
+int ooc_discard_queue(ooc_ctx *c) {
+  GUARD(c);
+  c->queue.clear();
+  return OOC_OK;
+}
+
 int ooc_mark_step(ooc_ctx *c) {
   GUARD(c);
   c->marks++;
@@ -1008,6 +1028,7 @@ int ooc_fetch_field(ooc_ctx *c, ooc_field h, double *dst, size_t bytes) {
   return guarded(c, [&]() -> int {
     Field &f = c->fields[h];
     if (bytes != (size_t)(f.n[0] * f.n[1] * f.n[2] * 8)) throw ArgError(OOC_E_ARG, "size mismatch");
+    if (!f.host) throw ArgError(OOC_E_STATE, "plan-only context has no field data");
     int rc = flush(c);
     if (rc) return rc;
     if (f.resident && c->ready && !f.host_valid) {
@@ -1026,6 +1047,7 @@ int ooc_set_field(ooc_ctx *c, ooc_field h, const double *src, size_t bytes) {
   return guarded(c, [&]() -> int {
     Field &f = c->fields[h];
     if (bytes != (size_t)(f.n[0] * f.n[1] * f.n[2] * 8)) throw ArgError(OOC_E_ARG, "size mismatch");
+    if (!f.host) throw ArgError(OOC_E_STATE, "plan-only context has no field data");
     int rc = flush(c);
     if (rc) return rc;
     copy_extent(c, f, nullptr, src, false);
@@ -1040,7 +1062,7 @@ int ooc_set_field(ooc_ctx *c, ooc_field h, const double *src, size_t bytes) {
 
 int ooc_set_flags(ooc_ctx *c, uint32_t set, uint32_t clear) {
   GUARD(c);
-  const uint32_t fixed = OOC_FLAG_FP32_STREAM | OOC_FLAG_INCORE;
+  const uint32_t fixed = OOC_FLAG_FP32_STREAM | OOC_FLAG_INCORE | OOC_FLAG_PLAN_ONLY;
   if ((set | clear) & fixed) return fail(c, OOC_E_STATE, "FP32_STREAM and INCORE are fixed at creation");
   return guarded(c, [&]() -> int {
     int rc = flush(c);  // flags apply to chains queued from now on

@@ -67,13 +67,18 @@ class Hydro2D:
 
     def __init__(self, nx: int, ny: int, rho: np.ndarray, ene: np.ndarray, budget: int, flags: int = 0,
                  resident_geometry: bool = False, cyclic_after_init: bool = True, bind: bool = True,
-                 arena_bytes: int | None = None):
+                 arena_bytes: int | None = None, plan_only: bool = False):
         self.nx, self.ny = nx, ny
+        if plan_only:
+            flags |= ooc.FLAG_PLAN_ONLY
+            bind = False
         self.ctx = ooc.Context(2, (nx, ny), H, budget, flags, bind=bind, arena_bytes=arena_bytes)
         self.f = {}
         for name, c in FIELDS:
             init = None
-            if name == "rho0":
+            if plan_only:
+                pass
+            elif name == "rho0":
                 init = full_extent(nx, ny, c, rho)
             elif name == "e0":
                 init = full_extent(nx, ny, c, ene)

@@ -50,8 +50,12 @@ class NS3D:
     """prims: interior arrays (rho, u, v, w, p), indexed [z, y, x]."""
 
     def __init__(self, n: int, prims, budget: int, flags: int = 0, re: float = 1600.0, bind: bool = True,
-                 cyclic_after_init: bool = True):
+                 cyclic_after_init: bool = True, plan_only: bool = False):
+        """plan_only: a context without storage, for planning schedules only."""
         self.n = n
+        if plan_only:
+            flags |= ooc.FLAG_PLAN_ONLY
+            bind = False
         self.ctx = ooc.Context(3, (n, n, n), NH, budget, flags, bind=bind)
         self.h = TWO_PI / n
         self.inv = 1.0 / (12.0 * self.h)
@@ -63,7 +67,7 @@ class NS3D:
         m = n + 2 * NH
         for name in FIELDS:
             init = None
-            if name in P:
+            if name in P and not plan_only:
                 init = np.zeros((m, m, m))
                 init[NH:NH + n, NH:NH + n, NH:NH + n] = prims[P.index(name)]
             self.f[name] = self.ctx.decl_field(name, (0, 0, 0), init)

@@ -18,7 +18,7 @@ READ, WRITE, RW, INC = 1, 2, 3, 4
 RED_MIN, RED_MAX, RED_SUM = 1, 2, 3
 ARG_DAT, ARG_RED, ARG_CONST, ARG_DEVSCALAR = 0, 1, 2, 3
 FLAG_CYCLIC, FLAG_PREFETCH, FLAG_FP32_STREAM, FLAG_INCORE = 1, 2, 4, 8
-FLAG_GRAPH, FLAG_DEBUG_POISON, FLAG_DEBUG_SYNC = 16, 64, 128
+FLAG_GRAPH, FLAG_DEBUG_POISON, FLAG_DEBUG_SYNC, FLAG_PLAN_ONLY = 16, 64, 128, 256
 FIELD_RESIDENT = 1
 
 _ERRNAMES = {E_ARG: "OOC_E_ARG", E_BUDGET: "OOC_E_BUDGET", E_DEVICE: "OOC_E_DEVICE",
@@ -59,7 +59,7 @@ class ooc_plan_info(ctypes.Structure):
 
 
 EXPORTS = ["ooc_create", "ooc_bind_device", "ooc_decl_field", "ooc_decl_reduction", "ooc_set_reduction",
-           "ooc_par_loop", "ooc_mark_step", "ooc_execute", "ooc_submit", "ooc_reduce", "ooc_fetch_field",
+           "ooc_par_loop", "ooc_mark_step", "ooc_discard_queue", "ooc_execute", "ooc_submit", "ooc_reduce", "ooc_fetch_field",
            "ooc_set_field", "ooc_set_flags", "ooc_set_schedule", "ooc_get_stats", "ooc_set_timing",
            "ooc_kernel_stats", "ooc_last_error", "ooc_destroy", "ooc_debug_plan", "ooc_field_shape",
            "ooc_mlp_create", "ooc_mlp_num_params", "ooc_mlp_get_params", "ooc_mlp_set_params",
@@ -93,6 +93,7 @@ def load_library() -> ctypes.CDLL:
         "ooc_set_reduction": [P, ctypes.c_int32, D],
         "ooc_par_loop": [P, I, I64P, I, ctypes.POINTER(ooc_arg)],
         "ooc_mark_step": [P],
+        "ooc_discard_queue": [P],
         "ooc_execute": [P],
         "ooc_submit": [P],
         "ooc_reduce": [P, ctypes.c_int32, DP],
@@ -259,6 +260,9 @@ class Context:
 
     def mark_step(self):
         self._check(self.lib.ooc_mark_step(self._h))
+
+    def discard_queue(self):
+        self._check(self.lib.ooc_discard_queue(self._h))
 
     def execute(self):
         self._check(self.lib.ooc_execute(self._h))

@@ -1,0 +1,122 @@
+"""Schedule search for a loop-chain workload (an extension beyond the paper).
+
+A schedule is (tile height h, chain length k in time steps, slot count S).
+`plan_features` describes a schedule from the library's own plan of one chain
+(transfer bytes, edge bytes, skew, tiles, slot use) without running it, using
+a plan-only context.  `sweep` is the exhaustive autotuner: it measures every
+feasible schedule on the device.  `CostModel` wraps the library's
+device-trained MLP (ooc_mlp_*): it learns log(seconds per cell-step) from the
+sweep's records and proposes the schedule with the lowest prediction; the
+exhaustive sweep is its fallback and the judge of its regret."""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import ooc
+
+FEATURE_NAMES = ["log2_h", "h_over_span", "tiles", "chain_steps", "slots", "slot_frac", "up_B_per_cell_step",
+                 "down_B_per_cell_step", "edge_B_per_cell_step", "lead_over_h", "launches_per_step",
+                 "inv_tiles"]
+
+
+def plan_features(plan_ctx, queue_steps, cells, row_bytes, budget, h, k, S):
+    """Features of schedule (h, k, S) for a workload whose loops
+    `queue_steps(k)` queues on the plan-only context; None if infeasible."""
+    try:
+        plan_ctx.set_schedule(tile_rows=h, chain_steps=k, slots=S)
+        queue_steps(k)
+        p = plan_ctx.debug_plan()
+    except ooc.OocError as e:
+        plan_ctx.discard_queue()
+        if e.code == ooc.E_BUDGET:
+            return None
+        raise
+    plan_ctx.discard_queue()
+    T = p["ntiles"]
+    lr = p["loop_rows"]
+    span = max(1, int(lr[:, -1, 1].max() - lr[:, 0, 0].min()))
+    hh = p["tile_rows"] if p["tile_rows"] > 0 else span
+    nrows = lambda runs: int((runs[:, 3] - runs[:, 2]).sum()) if len(runs) else 0
+    denom = float(cells) * k
+    up = nrows(p["up"]) * row_bytes / denom
+    down = nrows(p["down"]) * row_bytes / denom
+    edge = nrows(p["edge"]) * row_bytes / denom
+    ends0 = lr[:, 0, 1]
+    nonempty = ends0 > lr[:, 0, 0]
+    lead = float(ends0[nonempty].max() - ends0[nonempty].min()) if nonempty.any() else 0.0
+    launches = int((lr[:, :, 1] > lr[:, :, 0]).sum())
+    return np.array([math.log2(hh), hh / span, T / 16.0, float(k), float(S), p["slot_bytes"] * S / budget,
+                     up / 100.0, down / 100.0, edge / 100.0, lead / hh, launches / (100.0 * k), 1.0 / T])
+
+
+def grid(hs, ks, ss):
+    return [(h, k, s) for h in hs for k in ks for s in ss]
+
+
+def measure(app, cells, h, k, S, chains=2):
+    """Seconds per cell-step of schedule (h, k, S) on a live app (one warm-up
+    chain, then `chains` timed chains issued back to back)."""
+    import torch
+    app.ctx.set_schedule(tile_rows=h, chain_steps=k, slots=S)
+    app.run(k)  # warm-up: plan, argument table, first transfers
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    app.run(chains * k)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / (cells * chains * k)
+
+
+def sweep(app, plan_ctx, queue_steps, cells, row_bytes, budget, candidates, chains=2, log=None):
+    """Exhaustive autotuner: features and measured time of every feasible
+    candidate.  Returns a list of records."""
+    recs = []
+    for (h, k, S) in candidates:
+        f = plan_features(plan_ctx, queue_steps, cells, row_bytes, budget, h, k, S)
+        if f is None:
+            continue
+        try:
+            t = measure(app, cells, h, k, S, chains)
+        except ooc.OocError as e:
+            if e.code == ooc.E_BUDGET:
+                continue
+            raise
+        recs.append({"h": h, "k": k, "S": S, "features": f.tolist(), "sec_per_cell_step": t})
+        if log:
+            log("h=%d k=%d S=%d: %.3e s/cell-step" % (h, k, S, t))
+    return recs
+
+
+class CostModel:
+    """The library's MLP on standardised plan features -> log time."""
+
+    def __init__(self, n_hidden: int = 32, seed: int = 1709):
+        self.n_hidden, self.seed = n_hidden, seed
+        self.net = None
+
+    def fit(self, records, epochs: int = 3000, lr: float = 3e-3) -> float:
+        X = np.array([r["features"] for r in records], dtype=np.float64)
+        y = np.log(np.array([r["sec_per_cell_step"] for r in records]))
+        self.mu, self.sd = X.mean(0), X.std(0) + 1e-12
+        self.ymu, self.ysd = y.mean(), y.std() + 1e-12
+        if self.net is None:
+            self.net = ooc.Mlp(X.shape[1], self.n_hidden, self.seed)
+        return self.net.train((X - self.mu) / self.sd, (y - self.ymu) / self.ysd, epochs, lr)
+
+    def predict(self, features) -> np.ndarray:
+        X = np.atleast_2d(np.asarray(features, dtype=np.float64))
+        return np.exp(self.net.predict((X - self.mu) / self.sd) * self.ysd + self.ymu)
+
+    def propose(self, candidates_with_features):
+        """candidates_with_features: list of ((h, k, S), features); returns
+        the candidate with the lowest predicted time."""
+        feats = np.array([f for _, f in candidates_with_features])
+        pred = self.predict(feats)
+        i = int(np.argmin(pred))
+        return candidates_with_features[i][0], float(pred[i])
+
+    def close(self):
+        if self.net is not None:
+            self.net.close()
