@@ -73,6 +73,7 @@ enum {
   OOC_FLAG_FP32_STREAM = 4,   /* store streamed fields on the host as float32 (transfers halved) */
   OOC_FLAG_INCORE = 8,        /* keep every field resident on the device (no streaming) */
   OOC_FLAG_GRAPH = 16,        /* replay each chain's tile pipeline from a captured hipGraph */
+  OOC_FLAG_FUSE = 32,         /* launch independent strip (mirror) loops of a tile together */
   OOC_FLAG_DEBUG_POISON = 64, /* fill every slot with NaN before use (finds missing uploads) */
   OOC_FLAG_DEBUG_SYNC = 128,  /* serialise the three streams (separates races from plan bugs) */
   OOC_FLAG_PLAN_ONLY = 256    /* no host or device storage: for ooc_debug_plan only (schedule search) */

@@ -17,13 +17,60 @@ KernelInfo *kernel_table() {
 
 // ---------------------------------------------------------------- generic
 // dst_q(p) = sign_q * src_q(p + o_q) for each of the n pairs.
-OOC_KERNEL(k_mirror) {
-  ARGS
-  POINT_INDEX_OR_RETURN;
+__device__ inline void mirror_point(const KArgs &a, int i, int j, int k) {
   const int n = a.ndat / 2;
   for (int q = 0; q < n; q++) {
     const int32_t *o = a.off[2 * q + 1];
     AT(2 * q, 0, 0, 0) = a.c[q] * AT(2 * q + 1, o[0], o[1], o[2]);
+  }
+}
+
+OOC_KERNEL(k_mirror) {
+  ARGS
+  POINT_INDEX_OR_RETURN;
+  mirror_point(a, i, j, k);
+}
+
+// Several independent mirror loops of one tile in a single launch: block b
+// belongs to the loop whose block range holds it (prefix sums in blk0), and
+// runs exactly the single-loop body there.
+struct MirrorBatch {
+  const KArgs *args[32];
+  int32_t gx[32], gy[32];
+  int32_t blk0[33];
+  int32_t n;
+};
+
+__global__ void __launch_bounds__(256) k_mirror_batch(MirrorBatch mb) {
+  const int b = blockIdx.x;
+  int s = 0;
+  while (s + 1 < mb.n && b >= mb.blk0[s + 1]) s++;
+  const KArgs &a = *mb.args[s];
+  const int lb = b - mb.blk0[s];
+  const int bx = lb % mb.gx[s], by = (lb / mb.gx[s]) % mb.gy[s], bz = lb / (mb.gx[s] * mb.gy[s]);
+  const int i = a.lo[0] + bx * 64 + (int)threadIdx.x;
+  const int j = a.lo[1] + by * 4 + (int)threadIdx.y;
+  const int k = a.lo[2] + bz;
+  if (i >= a.hi[0] || j >= a.hi[1]) return;
+  mirror_point(a, i, j, k);
+}
+
+void launch_mirror_batch(const KArgs *const *host_args, const KArgs *const *dev_args, int n, int ndim,
+                         void *stream) {
+  for (int s0 = 0; s0 < n; s0 += 32) {
+    MirrorBatch mb{};
+    mb.n = n - s0 < 32 ? n - s0 : 32;
+    int blocks = 0;
+    for (int q = 0; q < mb.n; q++) {
+      dim3 g = point_grid(*host_args[s0 + q], ndim);
+      mb.args[q] = dev_args[s0 + q];
+      mb.gx[q] = (int)g.x;
+      mb.gy[q] = (int)g.y;
+      mb.blk0[q] = blocks;
+      blocks += (int)(g.x * g.y * g.z);
+    }
+    mb.blk0[mb.n] = blocks;
+    if (blocks) hipLaunchKernelGGL(k_mirror_batch, dim3(blocks), dim3(64, 4, 1), 0, (hipStream_t)stream, mb);
   }
 }
 

@@ -62,6 +62,9 @@ struct CopySeg {
   int64_t n;  // doubles
 };
 void launch_copy_segments(const CopySeg *segs, int nseg, void *stream);
+// independent mirror loops of one tile in one launch (host and device argument blocks)
+void launch_mirror_batch(const KArgs *const *host_args, const KArgs *const *dev_args, int n, int ndim,
+                         void *stream);
 void launch_fill(double *dst, int64_t n, double value, void *stream);
 void launch_red_init(double *acc, double value, void *stream);
 void launch_red_commit(const double *acc, double *committed, void *stream);

@@ -110,6 +110,14 @@ struct ooc_ctx {
   KArgs *argtab_dev = nullptr, *argtab_host = nullptr;
   size_t argtab_cap = 0, argtab_used = 0;
   std::map<std::string, size_t> argtab_cache;
+  // captured chain pipelines (OOC_FLAG_GRAPH), keyed like the argument table
+  struct ChainGraph {
+    hipGraphExec_t exec;
+    uint64_t launches;
+  };
+  std::map<std::string, ChainGraph> graphs;
+  int64_t capture_g0 = -1;  // first tile of the chain being captured, -1 if none
+  hipEvent_t ev_fork = nullptr, ev_join_c = nullptr, ev_join_d = nullptr, ev_pre = nullptr, ev_post = nullptr;
   std::string err;
 };
 
@@ -157,6 +165,7 @@ void timed_call(ooc_ctx *c, Fn fn, int kind = kCallH2D) {
 
 void wait_tile(ooc_ctx *c, hipStream_t s, std::vector<hipEvent_t> &v, int64_t g) {
   if (g <= c->gsynced || g < c->gbase) return;
+  if (c->capture_g0 >= 0 && g < c->capture_g0) return;  // ordered before the graph instead
   hipEvent_t e = evref(v, c, g);
   timed_call(c, [&] { HIPCHK(hipStreamWaitEvent(s, e, 0)); }, 3);
 }
@@ -253,11 +262,19 @@ int guarded(ooc_ctx *c, Fn fn) {
   }
 }
 
+void drop_graphs(ooc_ctx *c) {
+  if (c->graphs.empty()) return;
+  HIPCHK(hipStreamSynchronize(c->s_up));
+  for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second.exec);
+  c->graphs.clear();
+}
+
 // The launch-argument table is metadata, not field data: it lives in its own
 // small device allocation (outside the field budget), grown only at a point
 // where no kernel can be reading it.
 void grow_argtab(ooc_ctx *c, size_t entries) {
   if (entries <= c->argtab_cap) return;
+  drop_graphs(c);
   if (c->argtab_dev) {
     HIPCHK(hipStreamSynchronize(c->s_comp));
     HIPCHK(hipFree(c->argtab_dev));
@@ -484,6 +501,30 @@ void launch_loop(ooc_ctx *c, int kid, const KArgs &a, const KArgs *dev, uint64_t
   c->st.launches++;
 }
 
+// Can loops a and b (a before b) run in one launch?  Only if neither writes a
+// point the other reads or writes: every write box is tested against every
+// access box of the other loop on the same field.
+bool loops_independent(const LoopRec &a, const LoopRec &b, int ndim) {
+  auto box_meet = [&](const LoopRec &x, const int32_t *ox, const LoopRec &y, const int32_t *oy) {
+    for (int d = 0; d < ndim; d++)
+      if (x.lo[d] + ox[d] >= y.hi[d] + oy[d] || y.lo[d] + oy[d] >= x.hi[d] + ox[d]) return false;
+    return true;
+  };
+  static const int32_t zero[3] = {0, 0, 0};
+  for (int pass = 0; pass < 2; pass++) {
+    const LoopRec &w = pass ? b : a, &o = pass ? a : b;
+    for (const ArgRec &gw : w.args) {
+      if (gw.kind != OOC_ARG_DAT || !writes_access(gw.access)) continue;
+      for (const ArgRec &go : o.args) {
+        if (go.kind != OOC_ARG_DAT || go.handle != gw.handle) continue;
+        for (int p = 0; p < go.npts(); p++)
+          if (box_meet(w, zero, o, &go.offs[3 * p])) return false;
+      }
+    }
+  }
+  return true;
+}
+
 bool loop_nonempty(const LoopRec &L, int ndim) {
   for (int d = 0; d < ndim; d++)
     if (L.hi[d] <= L.lo[d]) return false;
@@ -503,11 +544,6 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
     for (const ArgRec &g : L[i].args)
       if (g.kind == OOC_ARG_RED && std::find(wreds.begin(), wreds.end(), g.handle) == wreds.end())
         wreds.push_back(g.handle);
-  for (int h : wreds) {
-    Reduction &r = c->reds[h];
-    if (r.op == OOC_RED_SUM) launch_fill(r.partials, r.npartials, 0.0, c->s_comp);
-    else launch_red_init(r.acc, r.op == OOC_RED_MIN ? INFINITY : -INFINITY, c->s_comp);
-  }
   // index transfer runs by tile
   std::vector<std::vector<const Run *>> up(T), down(T), edge(T);
   for (const Run &r : P.up) up[r.t].push_back(&r);
@@ -545,6 +581,7 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
     if (hostargs.size() > c->argtab_cap) grow_argtab(c, 2 * hostargs.size());
     if (c->argtab_used + hostargs.size() > c->argtab_cap) {
       // table full: wait until no kernel reads it, then start over
+      drop_graphs(c);
       HIPCHK(hipStreamSynchronize(c->s_comp));
       c->argtab_cache.clear();
       c->argtab_used = 0;
@@ -555,6 +592,26 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
                           hipMemcpyHostToDevice, c->s_comp));
     c->argtab_used += hostargs.size();
     c->argtab_cache.emplace(akey, abase);
+  }
+  // transfer byte counts (known from the plan)
+  for (const Run &r : P.up) {
+    const uint64_t nb = (uint64_t)(r.hi - r.lo) * c->fields[r.f].row_bytes_host();
+    c->st.bytes_h2d += nb;
+    c->st.last_bytes_h2d += nb;
+  }
+  for (const Run &r : P.down) {
+    const uint64_t nb = (uint64_t)(r.hi - r.lo) * c->fields[r.f].row_bytes_host();
+    c->st.bytes_d2h += nb;
+    c->st.last_bytes_d2h += nb;
+  }
+  for (const Run &r : P.edge) c->st.bytes_edge += (uint64_t)(r.hi - r.lo) * c->fields[r.f].row_elems * 8;
+  const uint64_t launches0 = c->st.launches;
+
+  auto body = [&]() {
+  for (int h : wreds) {
+    Reduction &r = c->reds[h];
+    if (r.op == OOC_RED_SUM) launch_fill(r.partials, r.npartials, 0.0, c->s_comp);
+    else launch_red_init(r.acc, r.op == OOC_RED_MIN ? INFINITY : -INFINITY, c->s_comp);
   }
   size_t li = 0;
   for (int t = 0; t < T; t++) {
@@ -593,18 +650,43 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       } else {
         timed_call(c, [&] { HIPCHK(hipMemcpyAsync(dst, src, nb, hipMemcpyHostToDevice, c->s_up)); });
       }
-      c->st.bytes_h2d += nb;
-      c->st.last_bytes_h2d += nb;
     }
     timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_up, c, g), c->s_up)); }, kCallRecord);
     if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_up));
     // ---- execute every loop of the chain over its rows of this tile
     timed_call(c, [&] { HIPCHK(hipStreamWaitEvent(c->s_comp, evref(c->ev_up, c, g), 0)); }, kCallWait);
+    const bool fuse = (c->flags & OOC_FLAG_FUSE) && !c->timing;
+    std::vector<const KArgs *> bh, bd;  // pending batch of independent mirror loops
+    std::vector<int> bl;
+    auto flush_batch = [&] {
+      if (bh.size() == 1) {
+        launch_loop(c, OOC_K_MIRROR, *bh[0], bd[0], 0);
+      } else if (!bh.empty()) {
+        timed_call(c, [&] { launch_mirror_batch(bh.data(), bd.data(), (int)bh.size(), c->ndim, c->s_comp); },
+                   kCallLaunch);
+        HIPCHK(hipGetLastError());
+        c->st.launches++;
+      }
+      bh.clear();
+      bd.clear();
+      bl.clear();
+    };
     for (int i = 0; i < n; i++)
       if (P.s(i, t) < P.en(i, t) && loop_nonempty(L[i], c->ndim)) {
-        launch_loop(c, launches[li].kid, hostargs[li], c->argtab_dev + abase + li, launches[li].bytes);
+        if (fuse && L[i].kid == OOC_K_MIRROR) {
+          bool ok = true;
+          for (int q : bl) ok = ok && loops_independent(L[q], L[i], c->ndim);
+          if (!ok) flush_batch();
+          bh.push_back(&hostargs[li]);
+          bd.push_back(c->argtab_dev + abase + li);
+          bl.push_back(i);
+        } else {
+          flush_batch();
+          launch_loop(c, launches[li].kid, hostargs[li], c->argtab_dev + abase + li, launches[li].bytes);
+        }
         li++;
       }
+    flush_batch();
     // ---- hand the right edge to the next tile's slot (on the compute stream)
     const bool poison = (c->flags & OOC_FLAG_DEBUG_POISON) != 0;
     if (t + 1 < T && (poison || !edge[t + 1].empty())) {
@@ -620,7 +702,6 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
         s.dst = (double *)(nslot + P.slab_off[r->f] + (r->lo - A1) * f.row_bytes_dev());
         s.n = (r->hi - r->lo) * f.row_elems;
         segs.push_back(s);
-        c->st.bytes_edge += (uint64_t)s.n * 8;
       }
       launch_copy_segments(segs.data(), (int)segs.size(), c->s_comp);
       HIPCHK(hipGetLastError());
@@ -650,14 +731,72 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       } else {
         timed_call(c, [&] { HIPCHK(hipMemcpyAsync(dst, src, nb, hipMemcpyDeviceToHost, c->s_down)); }, kCallD2H);
       }
-      for (int64_t q = r->lo; q < r->hi; q++) f.last_down[q] = g;
-      c->st.bytes_d2h += nb;
-      c->st.last_bytes_d2h += nb;
     }
     timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_down, c, g), c->s_down)); }, kCallRecord);
     if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_down));
   }
-  (void)g0;
+  };  // body
+
+  const bool graph = (c->flags & OOC_FLAG_GRAPH) && !c->timing &&
+                     !(c->flags & (OOC_FLAG_DEBUG_POISON | OOC_FLAG_DEBUG_SYNC));
+  if (!graph) {
+    body();
+  } else {
+    // The chain runs as one graph launched on the upload stream.  Everything
+    // it depends on from earlier chains (compute, reduction commits, the
+    // argument-table upload, downloads) is ordered before it.
+    for (hipEvent_t *e : {&c->ev_fork, &c->ev_join_c, &c->ev_join_d, &c->ev_pre, &c->ev_post})
+      if (!*e) HIPCHK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(c->ev_pre, c->s_comp));
+    HIPCHK(hipStreamWaitEvent(c->s_up, c->ev_pre, 0));
+    wait_tile(c, c->s_up, c->ev_down, prev_last_tile);
+    for (int64_t g = g0; g < g0 + T; g++) {  // create the tile events outside any capture
+      (void)evref(c->ev_up, c, g);
+      (void)evref(c->ev_comp, c, g);
+      (void)evref(c->ev_down, c, g);
+    }
+    auto it = c->graphs.find(akey);
+    if (it != c->graphs.end()) {
+      HIPCHK(hipGraphLaunch(it->second.exec, c->s_up));
+      c->gtile += T;
+      c->st.launches += it->second.launches;
+    } else {
+      c->capture_g0 = g0;
+      HIPCHK(hipStreamBeginCapture(c->s_up, hipStreamCaptureModeThreadLocal));
+      HIPCHK(hipEventRecord(c->ev_fork, c->s_up));
+      HIPCHK(hipStreamWaitEvent(c->s_comp, c->ev_fork, 0));
+      HIPCHK(hipStreamWaitEvent(c->s_down, c->ev_fork, 0));
+      hipGraph_t gr = nullptr;
+      try {
+        body();
+        HIPCHK(hipEventRecord(c->ev_join_c, c->s_comp));
+        HIPCHK(hipEventRecord(c->ev_join_d, c->s_down));
+        HIPCHK(hipStreamWaitEvent(c->s_up, c->ev_join_c, 0));
+        HIPCHK(hipStreamWaitEvent(c->s_up, c->ev_join_d, 0));
+        HIPCHK(hipStreamEndCapture(c->s_up, &gr));
+      } catch (...) {
+        c->capture_g0 = -1;
+        throw;
+      }
+      c->capture_g0 = -1;
+      hipGraphExec_t ex = nullptr;
+      HIPCHK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(gr);
+      c->graphs[akey] = {ex, c->st.launches - launches0};
+      HIPCHK(hipGraphLaunch(ex, c->s_up));
+    }
+    // per-tile events for later chains, and the other streams follow the graph
+    for (int64_t g = g0; g < g0 + T; g++) {
+      HIPCHK(hipEventRecord(evref(c->ev_up, c, g), c->s_up));
+      HIPCHK(hipEventRecord(evref(c->ev_comp, c, g), c->s_up));
+      HIPCHK(hipEventRecord(evref(c->ev_down, c, g), c->s_up));
+    }
+    HIPCHK(hipEventRecord(c->ev_post, c->s_up));
+    HIPCHK(hipStreamWaitEvent(c->s_comp, c->ev_post, 0));
+    HIPCHK(hipStreamWaitEvent(c->s_down, c->ev_post, 0));
+  }
+  for (const Run &r : P.down)
+    for (int64_t q = r.lo; q < r.hi; q++) c->fields[r.f].last_down[q] = g0 + r.t;
   // host-copy bookkeeping
   const bool cyclic = (c->flags & OOC_FLAG_CYCLIC) != 0;
   for (size_t f = 0; f < c->fields.size(); f++) {
@@ -1124,6 +1263,9 @@ int ooc_destroy(ooc_ctx *c) {
     (void)hipStreamSynchronize(c->s_comp);
     (void)hipStreamSynchronize(c->s_down);
   }
+  for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second.exec);
+  for (hipEvent_t e : {c->ev_fork, c->ev_join_c, c->ev_join_d, c->ev_pre, c->ev_post})
+    if (e) (void)hipEventDestroy(e);
   for (auto *v : {&c->ev_up, &c->ev_comp, &c->ev_down, &c->tev_pool})
     for (hipEvent_t e : *v) (void)hipEventDestroy(e);
   for (size_t k = 0; k < c->fields.size(); k++) free_host(c->fields[k].host, c->pinned[k]);

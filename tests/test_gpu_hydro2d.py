@@ -40,9 +40,11 @@ def test_hydro2d_c1_config_matches_oracle():
 
 @pytest.mark.parametrize("tile_rows,slots,flags,cyclic", [
     (1, 2, 0, False), (2, 3, 0, True), (3, 3, ooc.FLAG_PREFETCH, True), (7, 4, 0, False),
-    (16, 3, ooc.FLAG_DEBUG_POISON, True), (33, 2, ooc.FLAG_PREFETCH, False), (0, 3, ooc.FLAG_DEBUG_SYNC, True)])
+    (16, 3, ooc.FLAG_DEBUG_POISON, True), (33, 2, ooc.FLAG_PREFETCH, False), (0, 3, ooc.FLAG_DEBUG_SYNC, True),
+    (6, 3, ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, True), (5, 3, ooc.FLAG_GRAPH, True),
+    (9, 2, ooc.FLAG_GRAPH | ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, True)])
 def test_hydro2d_tiled_equals_untiled_bit_exact(tile_rows, slots, flags, cyclic):
-    nx, ny, steps = 40, 51, 4
+    nx, ny, steps = 40, 51, 5  # several chains: graph mode replays its capture
     say("case: tiled vs in-core", tile_rows, slots, flags, cyclic)
     ref, rdts, _ = gpu_hydro(nx, ny, steps, incore=True)
     # budget large enough for any forced tile height at this slot count

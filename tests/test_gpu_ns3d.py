@@ -44,13 +44,15 @@ def test_ns3d_tiled_matches_oracle():
         assert e <= TOL, q
 
 
-@pytest.mark.parametrize("tile_rows,chain_steps,slots", [(2, 1, 3), (3, 2, 2), (5, 2, 4), (7, 3, 3), (0, 1, 3)])
-def test_ns3d_tiled_equals_incore(tile_rows, chain_steps, slots):
+@pytest.mark.parametrize("tile_rows,chain_steps,slots,flags", [
+    (2, 1, 3, ooc.FLAG_PREFETCH), (3, 2, 2, ooc.FLAG_PREFETCH), (5, 2, 4, 0), (7, 3, 3, ooc.FLAG_PREFETCH),
+    (0, 1, 3, 0), (4, 1, 3, ooc.FLAG_FUSE | ooc.FLAG_GRAPH)])
+def test_ns3d_tiled_equals_incore(tile_rows, chain_steps, slots, flags):
     n, steps = 20, 3
-    say("case: ns3d tiled vs in-core", tile_rows, chain_steps, slots)
+    say("case: ns3d tiled vs in-core", tile_rows, chain_steps, slots, flags)
     ref, _ = gpu_ns(n, steps, incore=True)
     got, st = gpu_ns(n, steps, tile_rows=tile_rows, chain_steps=chain_steps, slots=slots,
-                     flags=ooc.FLAG_PREFETCH, budget=16 * N.device_footprint_bytes(n))
+                     flags=flags, budget=16 * N.device_footprint_bytes(n))
     for q in N.Q:
         assert np.array_equal(got[q], ref[q]), q
 
