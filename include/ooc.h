@@ -76,7 +76,10 @@ enum {
   OOC_FLAG_FUSE = 32,         /* launch independent strip (mirror) loops of a tile together */
   OOC_FLAG_DEBUG_POISON = 64, /* fill every slot with NaN before use (finds missing uploads) */
   OOC_FLAG_DEBUG_SYNC = 128,  /* serialise the three streams (separates races from plan bugs) */
-  OOC_FLAG_PLAN_ONLY = 256    /* no host or device storage: for ooc_debug_plan only (schedule search) */
+  OOC_FLAG_PLAN_ONLY = 256,   /* no host or device storage: for ooc_debug_plan only (schedule search) */
+  OOC_FLAG_KERNEL_COPY = 512  /* host-link transfers by a copy kernel on the pinned arrays' device
+                                 mapping (one launch per tile and direction; FP32 converted in flight)
+                                 instead of runtime memcpy calls */
 };
 
 /* per-field flags for ooc_decl_field */

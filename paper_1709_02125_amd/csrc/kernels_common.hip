@@ -257,3 +257,66 @@ void launch_f64_to_f32(const double *src, float *dst, int64_t n, void *stream) {
 }
 
 }  // namespace ooc
+
+namespace ooc {
+
+// Host-link transfers done by a kernel that reads or writes the pinned host
+// arrays directly through their device mapping: one launch per tile for all
+// of its runs, with the float32 <-> float64 conversion done in flight.
+struct XferTable {
+  const void *src[32];
+  void *dst[32];
+  int64_t n[32];  // elements (mode 0: 16-byte units)
+  int32_t mode[32];
+  int64_t blk0[33];
+  int32_t nseg;
+};
+constexpr int64_t kXferChunk = 4096;  // elements per block
+
+__global__ void __launch_bounds__(256) k_xfer(XferTable t) {
+  const int64_t b = blockIdx.x;
+  int s = 0;
+  while (s + 1 < t.nseg && b >= t.blk0[s + 1]) s++;
+  const int64_t base = (b - t.blk0[s]) * kXferChunk;
+  const int64_t end = base + kXferChunk < t.n[s] ? base + kXferChunk : t.n[s];
+  if (t.mode[s] == 0) {
+    const double2 *src = (const double2 *)t.src[s];
+    double2 *dst = (double2 *)t.dst[s];
+    for (int64_t e = base + threadIdx.x; e < end; e += 256) dst[e] = src[e];
+  } else if (t.mode[s] == 1) {  // float32 -> float64, 2 elements per lane step
+    const float2 *src = (const float2 *)t.src[s];
+    double2 *dst = (double2 *)t.dst[s];
+    for (int64_t e = base / 2 + threadIdx.x; e < end / 2; e += 256) {
+      const float2 v = src[e];
+      dst[e] = make_double2((double)v.x, (double)v.y);
+    }
+  } else {  // float64 -> float32 (round to nearest even)
+    const double2 *src = (const double2 *)t.src[s];
+    float2 *dst = (float2 *)t.dst[s];
+    for (int64_t e = base / 2 + threadIdx.x; e < end / 2; e += 256) {
+      const double2 v = src[e];
+      dst[e] = make_float2((float)v.x, (float)v.y);
+    }
+  }
+}
+
+void launch_xfer_segments(const XferSeg *segs, int nseg, void *stream) {
+  for (int s0 = 0; s0 < nseg; s0 += 32) {
+    XferTable t{};
+    t.nseg = nseg - s0 < 32 ? nseg - s0 : 32;
+    int64_t blocks = 0;
+    for (int q = 0; q < t.nseg; q++) {
+      const XferSeg &g = segs[s0 + q];
+      t.src[q] = g.src;
+      t.dst[q] = g.dst;
+      t.n[q] = g.n;
+      t.mode[q] = g.mode;
+      t.blk0[q] = blocks;
+      blocks += (g.n + kXferChunk - 1) / kXferChunk;
+    }
+    t.blk0[t.nseg] = blocks;
+    if (blocks) hipLaunchKernelGGL(k_xfer, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, t);
+  }
+}
+
+}  // namespace ooc

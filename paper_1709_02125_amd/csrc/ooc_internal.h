@@ -66,6 +66,15 @@ void launch_copy_segments(const CopySeg *segs, int nseg, void *stream);
 void launch_mirror_batch(const KArgs *const *host_args, const KArgs *const *dev_args, int n, int ndim,
                          void *stream);
 void launch_fill(double *dst, int64_t n, double value, void *stream);
+// host-link transfer by kernel: mode 0 copies n 16-byte units, mode 1 widens
+// n float32 to float64, mode 2 rounds n float64 to float32 (n even)
+struct XferSeg {
+  const void *src;
+  void *dst;
+  int64_t n;
+  int mode;
+};
+void launch_xfer_segments(const XferSeg *segs, int nseg, void *stream);
 void launch_red_init(double *acc, double value, void *stream);
 void launch_red_commit(const double *acc, double *committed, void *stream);
 void launch_sum_finalize(const double *partials, int64_t n, double *committed, void *stream);
@@ -96,6 +105,7 @@ struct Field {
   bool resident = false;
   bool fp32 = false;        // host storage in float32
   void *host = nullptr;     // pinned host array (nrows * row_elems elements)
+  void *host_dev = nullptr; // the same array as the device addresses it (pinned only)
   double *dev_res = nullptr;
   bool dev_valid = false;   // resident: device copy initialised
   bool host_valid = true;   // resident: host copy up to date

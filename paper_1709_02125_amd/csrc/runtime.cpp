@@ -193,6 +193,13 @@ void *alloc_host(ooc_ctx *c, size_t bytes, bool &pinned) {
   return p;
 }
 
+// device address of a pinned host array (kernel-copy transfers)
+void map_host(Field &f) {
+  void *d = nullptr;
+  if (f.host && hipHostGetDevicePointer(&d, f.host, 0) == hipSuccess) f.host_dev = d;
+  else (void)hipGetLastError();
+}
+
 void free_host(void *p, bool pinned) {
   if (!p) return;
   if (pinned) (void)hipHostFree(p);
@@ -332,6 +339,7 @@ void setup_device(ooc_ctx *c) {
     free_host(f.host, false);
     f.host = p;
     c->pinned[k] = pin;
+    if (pin) map_host(f);
   }
   const size_t budget = std::min(c->budget, c->arena_bytes);
   uint64_t off = 0;
@@ -630,6 +638,8 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
     }
     int64_t waited = -1;
     uint64_t stage_up = 0, stage_down = 0;
+    const bool kcopy = (c->flags & OOC_FLAG_KERNEL_COPY) != 0;
+    std::vector<XferSeg> xup;
     for (const Run *r : up[t]) {
       Field &f = c->fields[r->f];
       int64_t dep = -1;
@@ -642,6 +652,13 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       char *dst = slot + P.slab_off[r->f] + (r->lo - A) * f.row_bytes_dev();
       const size_t nb = (size_t)(r->hi - r->lo) * f.row_bytes_host();
       const char *src = (const char *)f.host + r->lo * f.row_bytes_host();
+      if (kcopy) {
+        if (!f.host_dev) throw DeviceError("kernel copy needs device-mapped pinned host arrays");
+        const char *hsrc = (const char *)f.host_dev + r->lo * f.row_bytes_host();
+        const int64_t elems = (r->hi - r->lo) * f.row_elems;
+        xup.push_back(f.fp32 ? XferSeg{hsrc, dst, elems, 1} : XferSeg{hsrc, dst, (int64_t)nb / 16, 0});
+        continue;
+      }
       if (f.fp32) {  // float32 rows land in staging, widened into the slab
         char *stage = slot + P.stage_up_off + stage_up;
         timed_call(c, [&] { HIPCHK(hipMemcpyAsync(stage, src, nb, hipMemcpyHostToDevice, c->s_up)); });
@@ -650,6 +667,10 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       } else {
         timed_call(c, [&] { HIPCHK(hipMemcpyAsync(dst, src, nb, hipMemcpyHostToDevice, c->s_up)); });
       }
+    }
+    if (!xup.empty()) {
+      timed_call(c, [&] { launch_xfer_segments(xup.data(), (int)xup.size(), c->s_up); }, kCallH2D);
+      HIPCHK(hipGetLastError());
     }
     timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_up, c, g), c->s_up)); }, kCallRecord);
     if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_up));
@@ -717,12 +738,20 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
     if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_comp));
     // ---- download the left footprint of modified datasets
     timed_call(c, [&] { HIPCHK(hipStreamWaitEvent(c->s_down, evref(c->ev_comp, c, g), 0)); }, kCallWait);
+    std::vector<XferSeg> xdown;
     for (const Run *r : down[t]) {
       Field &f = c->fields[r->f];
       const int64_t A = P.resA[(size_t)r->f * T + t];
       const char *src = slot + P.slab_off[r->f] + (r->lo - A) * f.row_bytes_dev();
       const size_t nb = (size_t)(r->hi - r->lo) * f.row_bytes_host();
       char *dst = (char *)f.host + r->lo * f.row_bytes_host();
+      if (kcopy) {
+        if (!f.host_dev) throw DeviceError("kernel copy needs device-mapped pinned host arrays");
+        char *hdst = (char *)f.host_dev + r->lo * f.row_bytes_host();
+        const int64_t elems = (r->hi - r->lo) * f.row_elems;
+        xdown.push_back(f.fp32 ? XferSeg{src, hdst, elems, 2} : XferSeg{src, hdst, (int64_t)nb / 16, 0});
+        continue;
+      }
       if (f.fp32) {  // rounded to float32 (nearest even) in staging, then sent
         char *stage = slot + P.stage_down_off + stage_down;
         launch_f64_to_f32((const double *)src, (float *)stage, (r->hi - r->lo) * f.row_elems, c->s_down);
@@ -731,6 +760,10 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       } else {
         timed_call(c, [&] { HIPCHK(hipMemcpyAsync(dst, src, nb, hipMemcpyDeviceToHost, c->s_down)); }, kCallD2H);
       }
+    }
+    if (!xdown.empty()) {
+      timed_call(c, [&] { launch_xfer_segments(xdown.data(), (int)xdown.size(), c->s_down); }, kCallD2H);
+      HIPCHK(hipGetLastError());
     }
     timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_down, c, g), c->s_down)); }, kCallRecord);
     if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_down));
@@ -1074,6 +1107,7 @@ int ooc_decl_field(ooc_ctx *c, const char *name, const int32_t size_delta[3], co
       par_memcpy(f.host, nullptr, f.host_bytes());
     }
     f.last_down.assign(f.nrows, -1);
+    if (pin) map_host(f);
     c->fields.push_back(std::move(f));
     c->pinned.push_back(pin);
     Field &fr = c->fields.back();

@@ -19,6 +19,7 @@ RED_MIN, RED_MAX, RED_SUM = 1, 2, 3
 ARG_DAT, ARG_RED, ARG_CONST, ARG_DEVSCALAR = 0, 1, 2, 3
 FLAG_CYCLIC, FLAG_PREFETCH, FLAG_FP32_STREAM, FLAG_INCORE = 1, 2, 4, 8
 FLAG_GRAPH, FLAG_FUSE, FLAG_DEBUG_POISON, FLAG_DEBUG_SYNC, FLAG_PLAN_ONLY = 16, 32, 64, 128, 256
+FLAG_KERNEL_COPY = 512
 FIELD_RESIDENT = 1
 
 _ERRNAMES = {E_ARG: "OOC_E_ARG", E_BUDGET: "OOC_E_BUDGET", E_DEVICE: "OOC_E_DEVICE",

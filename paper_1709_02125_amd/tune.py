@@ -120,3 +120,57 @@ class CostModel:
     def close(self):
         if self.net is not None:
             self.net.close()
+
+
+# ------------------------------------------------------------ workloads
+def ns3d_workload(n: int, budget: int, flags: int = 0):
+    """(live app, plan-only context, queue_steps, cells, row_bytes) for the
+    Navier-Stokes proxy at n^3 (Taylor-Green input)."""
+    from . import ns3d as N
+    from .inputs import tgv_initial_state
+    app = N.NS3D(n, tgv_initial_state(n), budget=budget, flags=flags | ooc.FLAG_PREFETCH)
+    app.initialise()
+    planner = N.NS3D(n, None, budget=budget, flags=flags, plan_only=True)
+    planner.ctx.set_flags(ooc.FLAG_CYCLIC, 0)
+
+    def queue_steps(k):
+        for _ in range(k):
+            planner.queue_step()
+
+    pitch = (n + 2 * N.NH + 1 + 31) // 32 * 32
+    row_bytes = pitch * (n + 2 * N.NH + 1) * (4 if flags & ooc.FLAG_FP32_STREAM else 8)
+    return app, planner.ctx, queue_steps, n ** 3, row_bytes
+
+
+def main():
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="exhaustive schedule sweep + cost model")
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--budget-frac", type=float, default=1.0 / 3.0)
+    ap.add_argument("--hs", default="8,16,24,32,48,0")
+    ap.add_argument("--ks", default="1,2,3")
+    ap.add_argument("--ss", default="2,3,4")
+    ap.add_argument("--chains", type=int, default=2)
+    ap.add_argument("--fp32", action="store_true")
+    ap.add_argument("--out", default="gpurun_out/tune_records.json")
+    a = ap.parse_args()
+    from . import ns3d as N
+    budget = int(N.footprint_bytes(a.n) * a.budget_frac)
+    flags = ooc.FLAG_FP32_STREAM if a.fp32 else 0
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)
+    app, plan_ctx, q, cells, rb = ns3d_workload(a.n, budget, flags)
+    cands = grid([int(x) for x in a.hs.split(",")], [int(x) for x in a.ks.split(",")],
+                 [int(x) for x in a.ss.split(",")])
+    recs = sweep(app, plan_ctx, q, cells, rb, budget, cands, a.chains, log)
+    with open(a.out, "w") as f:
+        json.dump({"n": a.n, "budget": budget, "fp32": a.fp32, "features": FEATURE_NAMES, "records": recs}, f)
+    best = min(recs, key=lambda r: r["sec_per_cell_step"])
+    log("best h=%d k=%d S=%d %.3e s/cell-step (%.3g updates/s)" %
+        (best["h"], best["k"], best["S"], best["sec_per_cell_step"], 1.0 / best["sec_per_cell_step"]))
+    app.close()
+
+
+if __name__ == "__main__":
+    main()

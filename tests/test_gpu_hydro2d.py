@@ -42,7 +42,8 @@ def test_hydro2d_c1_config_matches_oracle():
     (1, 2, 0, False), (2, 3, 0, True), (3, 3, ooc.FLAG_PREFETCH, True), (7, 4, 0, False),
     (16, 3, ooc.FLAG_DEBUG_POISON, True), (33, 2, ooc.FLAG_PREFETCH, False), (0, 3, ooc.FLAG_DEBUG_SYNC, True),
     (6, 3, ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, True), (5, 3, ooc.FLAG_GRAPH, True),
-    (9, 2, ooc.FLAG_GRAPH | ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, True)])
+    (9, 2, ooc.FLAG_GRAPH | ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, True), (4, 3, ooc.FLAG_KERNEL_COPY, True),
+    (11, 3, ooc.FLAG_KERNEL_COPY | ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, False)])
 def test_hydro2d_tiled_equals_untiled_bit_exact(tile_rows, slots, flags, cyclic):
     nx, ny, steps = 40, 51, 5  # several chains: graph mode replays its capture
     say("case: tiled vs in-core", tile_rows, slots, flags, cyclic)
@@ -156,6 +157,10 @@ def test_hydro2d_fp32_streaming_error_is_stated_and_tiling_independent():
     for n in STATE:
         assert np.array_equal(a[n], b[n]), n
     assert st["ntiles_last"] > 2
+    c, _, _ = gpu_hydro(nx, ny, steps, flags=flags | ooc.FLAG_KERNEL_COPY, resident_geometry=True,
+                        tile_rows=7, budget=h2.footprint_bytes(nx, ny))
+    for n in STATE:   # conversion in the copy kernel == staging + convert kernels
+        assert np.array_equal(a[n], c[n]), n
     ref, odts = oracle_hydro(nx, ny, steps)
     errs = {n: rel_err(a[n], ref[n]) for n in STATE}
     say("fp32 streaming max rel error after %d steps:" % steps, errs)
