@@ -103,7 +103,6 @@ def main():
     ap.add_argument("--no-prefetch", action="store_true")
     ap.add_argument("--kernel-copy", action="store_true", help="host-link transfers by copy kernel")
     ap.add_argument("--fuse", action="store_true", help="fuse independent strip loops per tile")
-    ap.add_argument("--graph", action="store_true", help="replay each chain from a captured hipGraph")
     ap.add_argument("--no-cyclic", action="store_true")
     ap.add_argument("--no-incore", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -132,8 +131,6 @@ def main():
         flags |= ooc.FLAG_KERNEL_COPY
     if args.fuse:
         flags |= ooc.FLAG_FUSE
-    if args.graph:
-        flags |= ooc.FLAG_GRAPH
     t = time.perf_counter()
     app = h2.Hydro2D(nx, ny, rho, ene, budget=int(args.budget), flags=flags,
                      resident_geometry=args.resident_geometry, cyclic_after_init=not args.no_cyclic)
@@ -199,7 +196,7 @@ def main():
                    "global_batch": cells, "seq_len": 1, "parallelism": "single-gpu",
                    "prefetch": not args.no_prefetch, "cyclic": not args.no_cyclic,
                    "resident_geometry": args.resident_geometry, "fp32_stream": args.fp32,
-                   "kernel_copy": args.kernel_copy, "fuse": args.fuse, "graph": args.graph,
+                   "kernel_copy": args.kernel_copy, "fuse": args.fuse,
                    "tiles": ooc_r["ntiles"],
                    "tile_rows": ooc_r["tile_rows"], "slots": args.slots or 3},
         "incore_value": inc_rate,

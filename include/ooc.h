@@ -72,7 +72,9 @@ enum {
   OOC_FLAG_PREFETCH = 2,      /* Section 4.1 opt (3): start the next chain's first tile early */
   OOC_FLAG_FP32_STREAM = 4,   /* store streamed fields on the host as float32 (transfers halved) */
   OOC_FLAG_INCORE = 8,        /* keep every field resident on the device (no streaming) */
-  OOC_FLAG_GRAPH = 16,        /* replay each chain's tile pipeline from a captured hipGraph */
+  OOC_FLAG_GRAPH = 16,        /* replay each chain's tile pipeline from a captured hipGraph.
+                                * Switched off in this version: ooc_create and ooc_set_flags
+                                * reject it with OOC_E_ARG. */
   OOC_FLAG_FUSE = 32,         /* launch independent strip (mirror) loops of a tile together */
   OOC_FLAG_DEBUG_POISON = 64, /* fill every slot with NaN before use (finds missing uploads) */
   OOC_FLAG_DEBUG_SYNC = 128,  /* serialise the three streams (separates races from plan bugs) */

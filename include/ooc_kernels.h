@@ -86,6 +86,58 @@ enum {
   OOC_K_NS_RHS_FIRST = 203,
   OOC_K_NS_RHS = 204,
 
+  /* ---- 3D hydro proxy (tiled along z).  "8n" = the 8 nodes of a cell
+   * {0,1}^3; "8c" = the 8 cells of a node {-1,0}^3; "F4x" = the 4 nodes of a
+   * cell's x-face {(e,0,0),(e,1,0),(e,0,1),(e,1,1)} (likewise y, z); e_D = the
+   * unit vector of sweep D.  EOS / EOS_P of the 2D proxy are point-wise and
+   * serve in 3D unchanged. ---- */
+  /* R rho0, R cs, R u0 8n, R v0 8n, R w0 8n, W q */
+  OOC_K_H3D_VISC = 300,
+  /* R rho0, R e0, R p, R q, R vol, R xarea {0,+x}, R yarea {0,+y}, R zarea {0,+z},
+   * R u0 8n, R v0 8n, R w0 8n, W rho1, W e1; DEVSCALAR dt */
+  OOC_K_H3D_PDV_PRED = 301,
+  /* as PDV_PRED plus R u1 8n, R v1 8n, R w1 8n after w0 */
+  OOC_K_H3D_PDV_CORR = 302,
+  /* R rho0 8c, R vol 8c, R p 8c, R q 8c, R xarea {(0,b,c)}, R yarea {(a,0,c)},
+   * R zarea {(a,b,0)} (a, b, c in {-1,0}), R u0, R v0, R w0, W u1, W v1, W w1;
+   * CONST nx, ny, nz; DEVSCALAR dt */
+  OOC_K_H3D_ACCEL = 303,
+  /* R area, R vel0 F4, R vel1 F4, W vf; DEVSCALAR dt (vel = u for x, v for y, w for z) */
+  OOC_K_H3D_FLUX_X = 304,
+  OOC_K_H3D_FLUX_Y = 305,
+  OOC_K_H3D_FLUX_Z = 306,
+  /* X: R vol, R vfx {0,+x}, R vfy {0,+y}, R vfz {0,+z}, W pre, W post
+   * Y: R vol, R vfy, R vfz, W pre, W post;  Z: R vol, R vfz, W pre, W post */
+  OOC_K_H3D_ADV_VOL_X = 307,
+  OOC_K_H3D_ADV_VOL_Y = 308,
+  OOC_K_H3D_ADV_VOL_Z = 309,
+  /* R vf, R rho1 {-e_D,0}, R e1 {-e_D,0}, W mf, W ef */
+  OOC_K_H3D_ADV_FLUX_X = 310,
+  OOC_K_H3D_ADV_FLUX_Y = 311,
+  OOC_K_H3D_ADV_FLUX_Z = 312,
+  /* RW rho1, RW e1, R pre, R post, R mf {0,+e_D}, R ef {0,+e_D} */
+  OOC_K_H3D_ADV_CELL_X = 313,
+  OOC_K_H3D_ADV_CELL_Y = 314,
+  OOC_K_H3D_ADV_CELL_Z = 315,
+  /* R mf {e e_D - b e_B - c e_C : e, b, c in {0,1}} (B, C the other two axes), W nf */
+  OOC_K_H3D_NFLUX_X = 316,
+  OOC_K_H3D_NFLUX_Y = 317,
+  OOC_K_H3D_NFLUX_Z = 318,
+  /* R rho1 8c, R post 8c, R nf {-e_D,0}, W nmpost, W nmpre */
+  OOC_K_H3D_NMASS_X = 319,
+  OOC_K_H3D_NMASS_Y = 320,
+  OOC_K_H3D_NMASS_Z = 321,
+  /* R nf, R vel {0,+e_D}, W mflux */
+  OOC_K_H3D_MFLUX_X = 322,
+  OOC_K_H3D_MFLUX_Y = 323,
+  OOC_K_H3D_MFLUX_Z = 324,
+  /* RW vel, R nmpre, R nmpost, R mflux {-e_D,0} */
+  OOC_K_H3D_VEL_X = 325,
+  OOC_K_H3D_VEL_Y = 326,
+  OOC_K_H3D_VEL_Z = 327,
+  /* R e0, R u0 8n, R v0 8n, R w0 8n; CONST dx, dy, dz; RED(MIN) dt */
+  OOC_K_H3D_DT = 328,
+
   OOC_K_MAX_ID = 512
 };
 

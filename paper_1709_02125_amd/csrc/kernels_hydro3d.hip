@@ -1,0 +1,364 @@
+// 3D hydro proxy kernels (FP64, gfx950): the three-dimensional form of the 2D
+// proxy -- 8-node cell stencils and 8-cell node stencils, donor-cell remap
+// sweeps x, y, z -- as the paper names CloverLeaf 3D (Section 5.1).  One kernel
+// per loop, a point per thread in 64 x 4 blocks (one wavefront per 64
+// consecutive x of a row), one block row of planes per z.  HBM-bound, no MFMA.
+// Expression order follows the plain program exactly (built without FP
+// contraction), so tiled and untiled runs are bit-identical.
+//
+// The equation of state kernels of the 2D proxy are point-wise and serve here
+// unchanged.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels_device.h"
+#include "ooc_internal.h"
+
+namespace ooc {
+namespace {
+
+constexpr double kGamma = 1.4;
+constexpr double kGm1 = 0.4;
+constexpr double kCq2 = 1.0;
+constexpr double kCq1 = 0.5;
+constexpr double kCfl = 0.5;
+
+// Sum of node field n over the 4 nodes of the face normal to axis AX, at
+// offset e along AX (0 = the cell's lower face, 1 = its upper face).
+template <int AX>
+__device__ __forceinline__ double face4(const KArgs &a, int n, int i, int j, int k, int e) {
+  if (AX == 0) return (AT(n, e, 0, 0) + AT(n, e, 1, 0)) + (AT(n, e, 0, 1) + AT(n, e, 1, 1));
+  if (AX == 1) return (AT(n, 0, e, 0) + AT(n, 1, e, 0)) + (AT(n, 0, e, 1) + AT(n, 1, e, 1));
+  return (AT(n, 0, 0, e) + AT(n, 1, 0, e)) + (AT(n, 0, 1, e) + AT(n, 1, 1, e));
+}
+
+// the same with start-plus-end values (fields n0, n1) at every node
+template <int AX>
+__device__ __forceinline__ double face4_2(const KArgs &a, int n0, int n1, int i, int j, int k, int e) {
+#define P2(di, dj, dk) (AT(n0, di, dj, dk) + AT(n1, di, dj, dk))
+  if (AX == 0) return (P2(e, 0, 0) + P2(e, 1, 0)) + (P2(e, 0, 1) + P2(e, 1, 1));
+  if (AX == 1) return (P2(0, e, 0) + P2(1, e, 0)) + (P2(0, e, 1) + P2(1, e, 1));
+  return (P2(0, 0, e) + P2(1, 0, e)) + (P2(0, 1, e) + P2(1, 1, e));
+#undef P2
+}
+
+// mean velocity jump across the cell along AX (node field n)
+template <int AX>
+__device__ __forceinline__ double jump(const KArgs &a, int n, int i, int j, int k) {
+  return 0.25 * (face4<AX>(a, n, i, j, k, 1) - face4<AX>(a, n, i, j, k, 0));
+}
+
+// args: R rho0, R cs, R u0, R v0, R w0, W q
+OOC_KERNEL(k_visc) {
+  ARGS
+  POINT_INDEX_OR_RETURN;
+  const double d = (jump<0>(a, 2, i, j, k) + jump<1>(a, 3, i, j, k)) + jump<2>(a, 4, i, j, k);
+  double q = 0.0;
+  if (d < 0.0) q = AT(0, 0, 0, 0) * ((kCq2 * d) * d - (kCq1 * AT(1, 0, 0, 0)) * d);
+  AT(5, 0, 0, 0) = q;
+}
+
+// PdV predictor / corrector.  args: 0 rho0, 1 e0, 2 p, 3 q, 4 vol, 5..7 x/y/z
+// area, 8..10 u0 v0 w0, [corrector: 11..13 u1 v1 w1], then W rho1, W e1.
+template <bool kCorr, int AX>
+__device__ __forceinline__ double pdv_df(const KArgs &a, int i, int j, int k, double fac) {
+  const int v0 = 8 + AX, v1 = 11 + AX, ar = 5 + AX;
+  const double sl = kCorr ? face4_2<AX>(a, v0, v1, i, j, k, 0) : face4<AX>(a, v0, i, j, k, 0);
+  const double sh = kCorr ? face4_2<AX>(a, v0, v1, i, j, k, 1) : face4<AX>(a, v0, i, j, k, 1);
+  const double fl = (fac * AT(ar, 0, 0, 0)) * sl;
+  const double fh = (fac * AT(ar, AX == 0, AX == 1, AX == 2)) * sh;
+  return fh - fl;
+}
+
+template <bool kCorr>
+OOC_KERNEL(k_pdv) {
+  ARGS
+  POINT_INDEX_OR_RETURN;
+  const double fac = 0.125 * a.ds[0][0];
+  const double total = (pdv_df<kCorr, 0>(a, i, j, k, fac) + pdv_df<kCorr, 1>(a, i, j, k, fac)) +
+                       pdv_df<kCorr, 2>(a, i, j, k, fac);
+  const double vol = AT(4, 0, 0, 0);
+  const double m = AT(0, 0, 0, 0) * vol;
+  constexpr int R1 = kCorr ? 14 : 11, E1 = kCorr ? 15 : 12;
+  AT(R1, 0, 0, 0) = m / (vol + total);
+  AT(E1, 0, 0, 0) = AT(1, 0, 0, 0) - ((AT(2, 0, 0, 0) + AT(3, 0, 0, 0)) * total) / m;
+}
+
+// Node acceleration: the force along each axis is a quarter of the sum, over
+// the 4 faces normal to it around the node, of area x (P lower - P upper),
+// the adjoint of the PdV volume change; node mass an eighth of its 8 cells.
+// args: 0 rho0, 1 vol, 2 p, 3 q, 4..6 x/y/z area, 7..9 u0 v0 w0, 10..12 u1 v1
+// w1; CONST nx, ny, nz; DEVSCALAR dt
+OOC_KERNEL(k_accel) {
+  ARGS
+  POINT_INDEX_OR_RETURN;
+  double P[2][2][2], M[2][2][2];
+#pragma unroll
+  for (int c = 0; c < 2; c++)
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+      for (int e = 0; e < 2; e++) {
+        P[c][b][e] = AT(2, e - 1, b - 1, c - 1) + AT(3, e - 1, b - 1, c - 1);
+        M[c][b][e] = AT(0, e - 1, b - 1, c - 1) * AT(1, e - 1, b - 1, c - 1);
+      }
+  const double mass = 0.125 * (((M[0][0][0] + M[0][0][1]) + (M[0][1][0] + M[0][1][1])) +
+                               ((M[1][0][0] + M[1][0][1]) + (M[1][1][0] + M[1][1][1])));
+  const double fx = 0.25 * ((AT(4, 0, -1, -1) * (P[0][0][0] - P[0][0][1]) + AT(4, 0, 0, -1) * (P[0][1][0] - P[0][1][1])) +
+                            (AT(4, 0, -1, 0) * (P[1][0][0] - P[1][0][1]) + AT(4, 0, 0, 0) * (P[1][1][0] - P[1][1][1])));
+  const double fy = 0.25 * ((AT(5, -1, 0, -1) * (P[0][0][0] - P[0][1][0]) + AT(5, 0, 0, -1) * (P[0][0][1] - P[0][1][1])) +
+                            (AT(5, -1, 0, 0) * (P[1][0][0] - P[1][1][0]) + AT(5, 0, 0, 0) * (P[1][0][1] - P[1][1][1])));
+  const double fz = 0.25 * ((AT(6, -1, -1, 0) * (P[0][0][0] - P[1][0][0]) + AT(6, 0, -1, 0) * (P[0][0][1] - P[1][0][1])) +
+                            (AT(6, -1, 0, 0) * (P[0][1][0] - P[1][1][0]) + AT(6, 0, 0, 0) * (P[0][1][1] - P[1][1][1])));
+  const double dt = a.ds[0][0];
+  double u = AT(7, 0, 0, 0) + (dt * fx) / mass;
+  double v = AT(8, 0, 0, 0) + (dt * fy) / mass;
+  double w = AT(9, 0, 0, 0) + (dt * fz) / mass;
+  if (i == 0 || i == (int)a.c[0]) u = 0.0;
+  if (j == 0 || j == (int)a.c[1]) v = 0.0;
+  if (k == 0 || k == (int)a.c[2]) w = 0.0;
+  AT(10, 0, 0, 0) = u;
+  AT(11, 0, 0, 0) = v;
+  AT(12, 0, 0, 0) = w;
+}
+
+// face volume flux along D.  args: R area, R vel0, R vel1, W vf; DEVSCALAR dt
+template <int D>
+OOC_KERNEL(k_flux) {
+  ARGS
+  POINT_INDEX_OR_RETURN;
+  const double fac = 0.125 * a.ds[0][0];
+  AT(3, 0, 0, 0) = (fac * AT(0, 0, 0, 0)) * face4_2<D>(a, 1, 2, i, j, k, 0);
+}
+
+// volume change through the faces normal to axis AX of field n
+template <int AX>
+__device__ __forceinline__ double dflux(const KArgs &a, int n, int i, int j, int k) {
+  return AT(n, AX == 0, AX == 1, AX == 2) - AT(n, 0, 0, 0);
+}
+
+// volumes before / after the x sweep.  args: R vol, R vfx, R vfy, R vfz, W pre, W post
+OOC_KERNEL(k_adv_vol_x) {
+  ARGS
+  POINT_INDEX_OR_RETURN;
+  const double dfx = dflux<0>(a, 1, i, j, k);
+  const double pre = AT(0, 0, 0, 0) + ((dfx + dflux<1>(a, 2, i, j, k)) + dflux<2>(a, 3, i, j, k));
+  AT(4, 0, 0, 0) = pre;
+  AT(5, 0, 0, 0) = pre - dfx;
+}
+
+// y sweep.  args: R vol, R vfy, R vfz, W pre, W post
+OOC_KERNEL(k_adv_vol_y) {
+  ARGS
+  POINT_INDEX_OR_RETURN;
+  const double vol = AT(0, 0, 0, 0);
+  const double dfz = dflux<2>(a, 2, i, j, k);
+  AT(3, 0, 0, 0) = vol + (dflux<1>(a, 1, i, j, k) + dfz);
+  AT(4, 0, 0, 0) = vol + dfz;
+}
+
+// z sweep.  args: R vol, R vfz, W pre, W post
+OOC_KERNEL(k_adv_vol_z) {
+  ARGS
+  POINT_INDEX_OR_RETURN;
+  const double vol = AT(0, 0, 0, 0);
+  AT(2, 0, 0, 0) = vol + dflux<2>(a, 1, i, j, k);
+  AT(3, 0, 0, 0) = vol;
+}
+
+// donor-cell mass / energy flux through the face between cells p - e_D and p.
+// args: R vf, R rho1, R e1, W mf, W ef
+template <int D>
+OOC_KERNEL(k_adv_flux) {
+  ARGS
+  POINT_INDEX_OR_RETURN;
+  constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
+  const double f = AT(0, 0, 0, 0);
+  double mf = 0.0, ef = 0.0;
+  if (f > 0.0) {
+    mf = f * AT(1, -ex, -ey, -ez);
+    ef = mf * AT(2, -ex, -ey, -ez);
+  } else if (f < 0.0) {
+    mf = f * AT(1, 0, 0, 0);
+    ef = mf * AT(2, 0, 0, 0);
+  }
+  AT(3, 0, 0, 0) = mf;
+  AT(4, 0, 0, 0) = ef;
+}
+
+// args: RW rho1, RW e1, R pre, R post, R mf, R ef
+template <int D>
+OOC_KERNEL(k_adv_cell) {
+  ARGS
+  POINT_INDEX_OR_RETURN;
+  constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
+  const double pm = AT(0, 0, 0, 0) * AT(2, 0, 0, 0);
+  const double post = pm + (AT(4, 0, 0, 0) - AT(4, ex, ey, ez));
+  const double pe = (AT(1, 0, 0, 0) * pm + (AT(5, 0, 0, 0) - AT(5, ex, ey, ez))) / post;
+  AT(0, 0, 0, 0) = post / AT(3, 0, 0, 0);
+  AT(1, 0, 0, 0) = pe;
+}
+
+// Dual-face mass flux of sweep D: an eighth of the 8 face mass fluxes on the
+// faces p and p + e_D, over the 4 cells around the node in the other two axes
+// (B the first of them, C the second).  args: R mf, W nf
+template <int D>
+OOC_KERNEL(k_nflux) {
+  ARGS
+  POINT_INDEX_OR_RETURN;
+  constexpr int B = D == 0 ? 1 : 0, C = D == 2 ? 1 : 2;
+  double t[2];
+#pragma unroll
+  for (int e = 0; e < 2; e++) {
+    double q[2][2];
+#pragma unroll
+    for (int y = 0; y < 2; y++)
+#pragma unroll
+      for (int x = 0; x < 2; x++) {
+        int o[3] = {0, 0, 0};
+        o[D] = e;
+        o[B] = -(1 - x);
+        o[C] = -(1 - y);
+        q[y][x] = AT(0, o[0], o[1], o[2]);
+      }
+    t[e] = (q[0][0] + q[0][1]) + (q[1][0] + q[1][1]);
+  }
+  AT(1, 0, 0, 0) = 0.125 * (t[0] + t[1]);
+}
+
+// node masses after the sweep (from the swept cells) and before it.
+// args: R rho1, R post, R nf, W nmpost, W nmpre
+template <int D>
+OOC_KERNEL(k_nmass) {
+  ARGS
+  POINT_INDEX_OR_RETURN;
+  constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
+#define CM(x, y, z) (AT(0, (x) - 1, (y) - 1, (z) - 1) * AT(1, (x) - 1, (y) - 1, (z) - 1))
+  const double post = 0.125 * (((CM(0, 0, 0) + CM(1, 0, 0)) + (CM(0, 1, 0) + CM(1, 1, 0))) +
+                               ((CM(0, 0, 1) + CM(1, 0, 1)) + (CM(0, 1, 1) + CM(1, 1, 1))));
+#undef CM
+  AT(3, 0, 0, 0) = post;
+  AT(4, 0, 0, 0) = post + (AT(2, 0, 0, 0) - AT(2, -ex, -ey, -ez));
+}
+
+// donor-cell momentum flux through the dual face between nodes p and p + e_D.
+// args: R nf, R vel, W mf
+template <int D>
+OOC_KERNEL(k_mflux) {
+  ARGS
+  POINT_INDEX_OR_RETURN;
+  constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
+  const double f = AT(0, 0, 0, 0);
+  double mf = 0.0;
+  if (f > 0.0) mf = f * AT(1, 0, 0, 0);
+  else if (f < 0.0) mf = f * AT(1, ex, ey, ez);
+  AT(2, 0, 0, 0) = mf;
+}
+
+// args: RW vel, R nmpre, R nmpost, R mf
+template <int D>
+OOC_KERNEL(k_vel) {
+  ARGS
+  POINT_INDEX_OR_RETURN;
+  constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
+  AT(0, 0, 0, 0) = (AT(0, 0, 0, 0) * AT(1, 0, 0, 0) + (AT(3, -ex, -ey, -ez) - AT(3, 0, 0, 0))) / AT(2, 0, 0, 0);
+}
+
+// largest absolute value of node field n over the cell's 8 nodes
+__device__ __forceinline__ double absmax8(const KArgs &a, int n, int i, int j, int k) {
+#define AV(x, y, z) fabs(AT(n, x, y, z))
+  return fmax(fmax(fmax(AV(0, 0, 0), AV(1, 0, 0)), fmax(AV(0, 1, 0), AV(1, 1, 0))),
+              fmax(fmax(AV(0, 0, 1), AV(1, 0, 1)), fmax(AV(0, 1, 1), AV(1, 1, 1))));
+#undef AV
+}
+
+// stable step of a cell, min-reduced.  args: R e0, R u0, R v0, R w0; CONST dx,
+// dy, dz; RED(MIN)
+OOC_KERNEL(k_dt) {
+  ARGS
+  POINT_INDEX_ACTIVE;
+  double t = INFINITY;
+  if (active) {
+    const double c2 = (kGamma * kGm1) * AT(0, 0, 0, 0);
+    const double d = (jump<0>(a, 1, i, j, k) + jump<1>(a, 2, i, j, k)) + jump<2>(a, 3, i, j, k);
+    double qr = 0.0;
+    if (d < 0.0) qr = (kCq2 * d) * d - (kCq1 * sqrt(c2)) * d;
+    const double ce = sqrt(c2 + 2.0 * qr);
+    t = fmin(t, a.c[0] / (ce + absmax8(a, 1, i, j, k)));
+    t = fmin(t, a.c[1] / (ce + absmax8(a, 2, i, j, k)));
+    t = fmin(t, a.c[2] / (ce + absmax8(a, 3, i, j, k)));
+    t = kCfl * t;
+  }
+  block_min_to(t, a.red[0]);
+}
+
+#define L(name, kern) \
+  void name(const KArgs &a, const KArgs *d, int nd, void *s) { launch_point(kern, a, d, nd, s); }
+L(l_visc, k_visc)
+L(l_pdv_pred, k_pdv<false>)
+L(l_pdv_corr, k_pdv<true>)
+L(l_accel, k_accel)
+L(l_flux_x, k_flux<0>)
+L(l_flux_y, k_flux<1>)
+L(l_flux_z, k_flux<2>)
+L(l_adv_vol_x, k_adv_vol_x)
+L(l_adv_vol_y, k_adv_vol_y)
+L(l_adv_vol_z, k_adv_vol_z)
+L(l_adv_flux_x, k_adv_flux<0>)
+L(l_adv_flux_y, k_adv_flux<1>)
+L(l_adv_flux_z, k_adv_flux<2>)
+L(l_adv_cell_x, k_adv_cell<0>)
+L(l_adv_cell_y, k_adv_cell<1>)
+L(l_adv_cell_z, k_adv_cell<2>)
+L(l_nflux_x, k_nflux<0>)
+L(l_nflux_y, k_nflux<1>)
+L(l_nflux_z, k_nflux<2>)
+L(l_nmass_x, k_nmass<0>)
+L(l_nmass_y, k_nmass<1>)
+L(l_nmass_z, k_nmass<2>)
+L(l_mflux_x, k_mflux<0>)
+L(l_mflux_y, k_mflux<1>)
+L(l_mflux_z, k_mflux<2>)
+L(l_vel_x, k_vel<0>)
+L(l_vel_y, k_vel<1>)
+L(l_vel_z, k_vel<2>)
+L(l_dt, k_dt)
+#undef L
+
+}  // namespace
+
+void register_hydro3d_kernels(KernelInfo *t) {
+  //                                   name            dat  dat const dev red
+  t[OOC_K_H3D_VISC] = {"h3d_visc", 6, 6, 0, 0, 0, kPointGrid, l_visc};
+  t[OOC_K_H3D_PDV_PRED] = {"h3d_pdv_pred", 13, 13, 0, 1, 0, kPointGrid, l_pdv_pred};
+  t[OOC_K_H3D_PDV_CORR] = {"h3d_pdv_corr", 16, 16, 0, 1, 0, kPointGrid, l_pdv_corr};
+  t[OOC_K_H3D_ACCEL] = {"h3d_accel", 13, 13, 3, 1, 0, kPointGrid, l_accel};
+  t[OOC_K_H3D_FLUX_X] = {"h3d_flux_x", 4, 4, 0, 1, 0, kPointGrid, l_flux_x};
+  t[OOC_K_H3D_FLUX_Y] = {"h3d_flux_y", 4, 4, 0, 1, 0, kPointGrid, l_flux_y};
+  t[OOC_K_H3D_FLUX_Z] = {"h3d_flux_z", 4, 4, 0, 1, 0, kPointGrid, l_flux_z};
+  t[OOC_K_H3D_ADV_VOL_X] = {"h3d_adv_vol_x", 6, 6, 0, 0, 0, kPointGrid, l_adv_vol_x};
+  t[OOC_K_H3D_ADV_VOL_Y] = {"h3d_adv_vol_y", 5, 5, 0, 0, 0, kPointGrid, l_adv_vol_y};
+  t[OOC_K_H3D_ADV_VOL_Z] = {"h3d_adv_vol_z", 4, 4, 0, 0, 0, kPointGrid, l_adv_vol_z};
+  t[OOC_K_H3D_ADV_FLUX_X] = {"h3d_adv_flux_x", 5, 5, 0, 0, 0, kPointGrid, l_adv_flux_x};
+  t[OOC_K_H3D_ADV_FLUX_Y] = {"h3d_adv_flux_y", 5, 5, 0, 0, 0, kPointGrid, l_adv_flux_y};
+  t[OOC_K_H3D_ADV_FLUX_Z] = {"h3d_adv_flux_z", 5, 5, 0, 0, 0, kPointGrid, l_adv_flux_z};
+  t[OOC_K_H3D_ADV_CELL_X] = {"h3d_adv_cell_x", 6, 6, 0, 0, 0, kPointGrid, l_adv_cell_x};
+  t[OOC_K_H3D_ADV_CELL_Y] = {"h3d_adv_cell_y", 6, 6, 0, 0, 0, kPointGrid, l_adv_cell_y};
+  t[OOC_K_H3D_ADV_CELL_Z] = {"h3d_adv_cell_z", 6, 6, 0, 0, 0, kPointGrid, l_adv_cell_z};
+  t[OOC_K_H3D_NFLUX_X] = {"h3d_nflux_x", 2, 2, 0, 0, 0, kPointGrid, l_nflux_x};
+  t[OOC_K_H3D_NFLUX_Y] = {"h3d_nflux_y", 2, 2, 0, 0, 0, kPointGrid, l_nflux_y};
+  t[OOC_K_H3D_NFLUX_Z] = {"h3d_nflux_z", 2, 2, 0, 0, 0, kPointGrid, l_nflux_z};
+  t[OOC_K_H3D_NMASS_X] = {"h3d_nmass_x", 5, 5, 0, 0, 0, kPointGrid, l_nmass_x};
+  t[OOC_K_H3D_NMASS_Y] = {"h3d_nmass_y", 5, 5, 0, 0, 0, kPointGrid, l_nmass_y};
+  t[OOC_K_H3D_NMASS_Z] = {"h3d_nmass_z", 5, 5, 0, 0, 0, kPointGrid, l_nmass_z};
+  t[OOC_K_H3D_MFLUX_X] = {"h3d_mflux_x", 3, 3, 0, 0, 0, kPointGrid, l_mflux_x};
+  t[OOC_K_H3D_MFLUX_Y] = {"h3d_mflux_y", 3, 3, 0, 0, 0, kPointGrid, l_mflux_y};
+  t[OOC_K_H3D_MFLUX_Z] = {"h3d_mflux_z", 3, 3, 0, 0, 0, kPointGrid, l_mflux_z};
+  t[OOC_K_H3D_VEL_X] = {"h3d_vel_x", 4, 4, 0, 0, 0, kPointGrid, l_vel_x};
+  t[OOC_K_H3D_VEL_Y] = {"h3d_vel_y", 4, 4, 0, 0, 0, kPointGrid, l_vel_y};
+  t[OOC_K_H3D_VEL_Z] = {"h3d_vel_z", 4, 4, 0, 0, 0, kPointGrid, l_vel_z};
+  t[OOC_K_H3D_DT] = {"h3d_dt", 4, 4, 3, 0, 1, kPointGrid, l_dt};
+}
+
+}  // namespace ooc

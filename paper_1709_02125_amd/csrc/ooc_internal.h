@@ -54,6 +54,7 @@ KernelInfo *kernel_table();
 void register_common_kernels(KernelInfo *t);
 void register_hydro2d_kernels(KernelInfo *t);
 void register_ns3d_kernels(KernelInfo *t);
+void register_hydro3d_kernels(KernelInfo *t);
 
 // Device helpers implemented in kernels_common.hip.
 struct CopySeg {

@@ -131,6 +131,7 @@ KernelInfo *table() {
     register_common_kernels(g_table);
     register_hydro2d_kernels(g_table);
     register_ns3d_kernels(g_table);
+    register_hydro3d_kernels(g_table);
   }
   return g_table;
 }
@@ -1052,6 +1053,7 @@ extern "C" {
 
 int ooc_create(ooc_ctx **out, int ndim, const int64_t dims[3], int halo, size_t budget, uint32_t flags) {
   if (!out || (ndim != 2 && ndim != 3) || !dims || halo < 0 || halo > 8) return OOC_E_ARG;
+  if (flags & OOC_FLAG_GRAPH) return OOC_E_ARG;  // switched off: see ooc_set_flags
   for (int d = 0; d < ndim; d++)
     if (dims[d] < 1 || dims[d] > (1 << 24)) return OOC_E_ARG;
   ooc_ctx *c = new (std::nothrow) ooc_ctx();
@@ -1237,6 +1239,10 @@ int ooc_set_flags(ooc_ctx *c, uint32_t set, uint32_t clear) {
   GUARD(c);
   const uint32_t fixed = OOC_FLAG_FP32_STREAM | OOC_FLAG_INCORE | OOC_FLAG_PLAN_ONLY;
   if ((set | clear) & fixed) return fail(c, OOC_E_STATE, "FP32_STREAM and INCORE are fixed at creation");
+  // Chain replay from a stream-captured graph is switched off: its first
+  // capture ended the process with a host segmentation fault whose cause has
+  // not been found in this library's code.
+  if (set & OOC_FLAG_GRAPH) return fail(c, OOC_E_ARG, "OOC_FLAG_GRAPH is switched off in this version");
   return guarded(c, [&]() -> int {
     int rc = flush(c);  // flags apply to chains queued from now on
     if (rc) return rc;

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from paper_1709_02125_amd import hydro2d as h2, ooc
-from gpu_util import STATE, gpu_hydro, oracle_hydro, rel_err, say
+from gpu_util import GRAPH_OFF, STATE, gpu_hydro, oracle_hydro, rel_err, say
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -41,8 +41,8 @@ def test_hydro2d_c1_config_matches_oracle():
 @pytest.mark.parametrize("tile_rows,slots,flags,cyclic", [
     (1, 2, 0, False), (2, 3, 0, True), (3, 3, ooc.FLAG_PREFETCH, True), (7, 4, 0, False),
     (16, 3, ooc.FLAG_DEBUG_POISON, True), (33, 2, ooc.FLAG_PREFETCH, False), (0, 3, ooc.FLAG_DEBUG_SYNC, True),
-    (6, 3, ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, True), (5, 3, ooc.FLAG_GRAPH, True),
-    (9, 2, ooc.FLAG_GRAPH | ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, True), (4, 3, ooc.FLAG_KERNEL_COPY, True),
+    (6, 3, ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, True), pytest.param(5, 3, ooc.FLAG_GRAPH, True, marks=GRAPH_OFF),
+    pytest.param(9, 2, ooc.FLAG_GRAPH | ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, True, marks=GRAPH_OFF), (4, 3, ooc.FLAG_KERNEL_COPY, True),
     (11, 3, ooc.FLAG_KERNEL_COPY | ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, False)])
 def test_hydro2d_tiled_equals_untiled_bit_exact(tile_rows, slots, flags, cyclic):
     nx, ny, steps = 40, 51, 5  # several chains: graph mode replays its capture

@@ -245,3 +245,13 @@ def test_single_hip_runtime_in_process():
     maps = open("/proc/self/maps").read()
     hips = set(re.findall(r"\S*libamdhip64\S*", maps))
     assert len(hips) == 1, hips
+
+
+def test_graph_replay_flag_is_refused():
+    # chain replay from a captured graph is switched off in this version
+    with pytest.raises(Exception):
+        ooc.Context(2, (8, 8), 1, 1 << 20, ooc.FLAG_GRAPH, bind=False)
+    c = ooc.Context(2, (8, 8), 1, 1 << 20, 0, bind=False)
+    with pytest.raises(Exception):
+        c.set_flags(ooc.FLAG_GRAPH, 0)
+    c.close()
