@@ -12,8 +12,8 @@ TOL = 1e-12
 
 def test_hydro3d_tiled_matches_oracle_step_by_step():
     # several z-tiles per chain with a ragged last tile; dt checked every step
-    n, steps = (40, 36, 50), 4
-    say("case: hydro3d 40x36x50 tiled 1/3 budget, dt per step")
+    n, steps = (40, 36, 160), 4
+    say("case: hydro3d 40x36x160 tiled 1/3 budget, dt per step")
     got, gdts, st, mass = gpu_hydro3d(n, steps, per_step_dt=True, flags=ooc.FLAG_PREFETCH)
     ref, odts, omass = oracle_hydro3d(n, steps)
     say("tiles", st["ntiles_last"], "rows", st["tile_rows"])
@@ -39,7 +39,7 @@ def test_hydro3d_incore_matches_oracle():
 
 @pytest.mark.parametrize("tile_rows,slots,flags,cyclic", [
     (1, 2, 0, False), (3, 3, ooc.FLAG_PREFETCH, True), (8, 4, ooc.FLAG_DEBUG_POISON, True),
-    (13, 2, ooc.FLAG_PREFETCH, False), (0, 3, ooc.FLAG_DEBUG_SYNC, True),
+    (13, 2, ooc.FLAG_PREFETCH, False), (4, 3, ooc.FLAG_DEBUG_SYNC, True),
     (5, 3, ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, True), pytest.param(6, 3, ooc.FLAG_GRAPH, True, marks=GRAPH_OFF),
     (7, 3, ooc.FLAG_KERNEL_COPY | ooc.FLAG_PREFETCH, True)])
 def test_hydro3d_tiled_equals_untiled_bit_exact(tile_rows, slots, flags, cyclic):
@@ -55,7 +55,7 @@ def test_hydro3d_tiled_equals_untiled_bit_exact(tile_rows, slots, flags, cyclic)
 
 
 def test_hydro3d_resident_geometry_bit_exact():
-    n, steps = (24, 20, 30), 2
+    n, steps = (24, 20, 60), 2
     say("case: hydro3d resident geometry")
     ref, _, _, _ = gpu_hydro3d(n, steps, incore=True)
     got, _, st, _ = gpu_hydro3d(n, steps, budget=h3.footprint_bytes(n) // 2, resident_geometry=True)
