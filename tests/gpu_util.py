@@ -93,9 +93,9 @@ def gpu_hydro3d(n, steps, budget=None, flags=0, tile_rows=0, slots=0, incore=Fal
         app.run(steps)
         dts.append(app.ctx.reduce(app.dt))
     out = {name: app.fetch(name) for name in STATE3}
+    st = app.ctx.stats()   # of the last step's chain
     app.queue_mass()
     mass = app.ctx.reduce(app.mass)
-    st = app.ctx.stats()
     app.close()
     return out, dts, st, mass
 

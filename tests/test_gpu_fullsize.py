@@ -6,7 +6,7 @@ sizes in a test's time)."""
 import numpy as np
 import pytest
 
-from paper_1709_02125_amd import hydro2d as h2, ns3d as N, ooc
+from paper_1709_02125_amd import hydro2d as h2, hydro3d as h3, ns3d as N, ooc
 from paper_1709_02125_amd.inputs import hydro_initial_state, tgv_initial_state
 from gpu_util import STATE, say
 
@@ -63,3 +63,32 @@ def test_ns3d_512_out_of_core_equals_in_core():
         app.close()
     for q in res[0]:
         assert np.array_equal(res[0][q], res[1][q]), q
+
+
+def test_hydro3d_640_out_of_core_equals_in_core():
+    n, steps = (640, 640, 640), 1
+    say("case: hydro3d 640^3 third-of-footprint budget vs in-core, 1 step")
+    rho, ene = hydro_initial_state(n)
+    res = []
+    for incore in (False, True):
+        flags = ooc.FLAG_INCORE if incore else ooc.FLAG_PREFETCH
+        budget = h3.device_footprint_bytes(n) if incore else h3.footprint_bytes(n) // 3
+        app = h3.Hydro3D(n, rho, ene, budget=budget, flags=flags)
+        app.initialise()
+        app.queue_mass()
+        m0 = app.ctx.reduce(app.mass)
+        app.run(steps)
+        app.queue_mass()
+        m1 = app.ctx.reduce(app.mass)
+        dt = app.ctx.reduce(app.dt)
+        planes = [0, 1, 2, 100, 319, 320, 500, 641, 642, 643]
+        out = {q: app.fetch(q)[planes] for q in ("rho0", "e0", "w0")}   # z extents 644 and 645
+        if not incore:
+            assert app.ctx.stats()["ntiles_last"] >= 3
+        app.close()
+        res.append((out, m0, m1, dt))
+    for q in res[0][0]:
+        assert np.array_equal(res[0][0][q], res[1][0][q]), q
+    assert res[0][1:] == res[1][1:]
+    m0, m1 = res[0][1], res[0][2]
+    assert abs(m1 - m0) <= 1e-12 * m0

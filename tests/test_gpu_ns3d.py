@@ -46,7 +46,8 @@ def test_ns3d_tiled_matches_oracle():
 
 @pytest.mark.parametrize("tile_rows,chain_steps,slots,flags", [
     (2, 1, 3, ooc.FLAG_PREFETCH), (3, 2, 2, ooc.FLAG_PREFETCH), (5, 2, 4, 0), (7, 3, 3, ooc.FLAG_PREFETCH),
-    (0, 1, 3, 0), pytest.param(4, 1, 3, ooc.FLAG_FUSE | ooc.FLAG_GRAPH, marks=GRAPH_OFF)])
+    (0, 1, 3, 0), (4, 1, 3, ooc.FLAG_FUSE), (6, 2, 3, ooc.FLAG_KERNEL_COPY | ooc.FLAG_PREFETCH),
+    pytest.param(4, 1, 3, ooc.FLAG_FUSE | ooc.FLAG_GRAPH, marks=GRAPH_OFF)])
 def test_ns3d_tiled_equals_incore(tile_rows, chain_steps, slots, flags):
     n, steps = 20, 3
     say("case: ns3d tiled vs in-core", tile_rows, chain_steps, slots, flags)
