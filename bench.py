@@ -59,7 +59,7 @@ class Hydro2DWork(Workload):
         self.budget = int(args.budget) if args.budget else 16_000_000_000
         log("generating input %dx%d" % (self.n, self.n))
         self.rho, self.ene = hydro_initial_state((self.n, self.n))
-        self.knames = dict(COMMON, **{100 + i: s for i, s in enumerate(H2D_NAMES)})
+        self.knames = {**COMMON, **{100 + i: s for i, s in enumerate(H2D_NAMES)}}
 
     def make(self, budget, flags, incore=False):
         h2 = self.mod
@@ -106,8 +106,8 @@ class Hydro3DWork(Workload):
         self.budget = int(args.budget) if args.budget else self.footprint // 3
         log("generating input %d^3" % self.n)
         self.rho, self.ene = hydro_initial_state(self.dims)
-        self.knames = dict(COMMON, **{100: "h2d_eos", 101: "h2d_eos_p"},
-                           **{300 + i: s for i, s in enumerate(H3D_NAMES)})
+        self.knames = {**COMMON, 100: "h2d_eos", 101: "h2d_eos_p",
+                       **{300 + i: s for i, s in enumerate(H3D_NAMES)}}
 
     def make(self, budget, flags, incore=False):
         h3 = self.mod
@@ -154,7 +154,7 @@ class NS3DWork(Workload):
         self.budget = int(args.budget) if args.budget else self.footprint // 3
         log("generating input %d^3" % self.n)
         self.prims = tgv_initial_state(self.n)
-        self.knames = dict(COMMON, **{200 + i: s for i, s in enumerate(NS_NAMES)})
+        self.knames = {**COMMON, **{200 + i: s for i, s in enumerate(NS_NAMES)}}
 
     def make(self, budget, flags, incore=False):
         N = self.mod
@@ -344,6 +344,7 @@ def main():
         "pct_of_incore": round(100.0 * ooc_rate / inc_rate, 2) if inc_rate else None,
         "incore_ms_per_step": round(inc_r["seconds"] / args.steps * 1e3, 3) if inc_r else None,
         "average_bandwidth_GBs": round(avg_bw, 1),
+        "alg_bytes_per_cell_step": round(ooc_r["bytes_hbm_alg"] / (w.cells * args.steps), 1),
         "roofline": roofline,
         "link": link,
         "cpu_baseline": cpu,
