@@ -72,7 +72,8 @@ def device_footprint_bytes(n) -> int:
     tot = 0
     for _, c in FIELDS:
         tot += ((n[2] + 2 * H + c[2]) * plane * 8 + 255) // 256 * 256
-    return tot + 64 * 1024 + ((n[2] + 2 * H + 1) * 8 + 255) // 256 * 256
+    # reduction buffers, and the SUM reduction's partials (one per y-z row)
+    return tot + 64 * 1024 + ((n[1] + 2 * H + 1) * (n[2] + 2 * H + 1) * 8 + 255) // 256 * 256
 
 
 def full_extent(n, centring, interior=None):

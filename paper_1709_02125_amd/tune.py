@@ -122,7 +122,60 @@ class CostModel:
             self.net.close()
 
 
+def default_schedule(records):
+    """The schedule the library uses without guidance: largest tile height
+    that fits (h = 0), one step per chain, 3 slots."""
+    for r in records:
+        if (r["h"], r["k"], r["S"]) == (0, 1, 3):
+            return r
+    return None
+
+
+def holdout_regret(records, train_frac=0.5, seed=1709, n_hidden=32, epochs=4000, lr=3e-3):
+    """Train the cost model on a seeded subset of the measured schedules and
+    let it pick among all of them (their features come from planning alone).
+    Returns a dict with the pick, its regret against the best measured
+    schedule, and its gain over the default schedule."""
+    rng = np.random.default_rng(seed)
+    idx = rng.permutation(len(records))
+    ntr = max(4, int(round(train_frac * len(records))))
+    train = [records[i] for i in idx[:ntr]]
+    model = CostModel(n_hidden=n_hidden, seed=seed)
+    try:
+        loss = model.fit(train, epochs=epochs, lr=lr)
+        (h, k, S), _ = model.propose([((r["h"], r["k"], r["S"]), r["features"]) for r in records])
+    finally:
+        model.close()
+    t = {(r["h"], r["k"], r["S"]): r["sec_per_cell_step"] for r in records}
+    best = min(t.values())
+    d = default_schedule(records)
+    return {"train": ntr, "of": len(records), "loss": loss, "pick": [h, k, S], "pick_in_train":
+            any((r["h"], r["k"], r["S"]) == (h, k, S) for r in train),
+            "regret": t[(h, k, S)] / best - 1.0,
+            "gain_over_default": (d["sec_per_cell_step"] / t[(h, k, S)]) if d else None}
+
+
 # ------------------------------------------------------------ workloads
+def hydro2d_workload(n: int, budget: int, flags: int = 0):
+    """The same for the 2D hydro proxy at n^2 (one step per chain: the time
+    step is a reduction read by the next step)."""
+    from . import hydro2d as h2
+    from .inputs import hydro_initial_state
+    rho, ene = hydro_initial_state((n, n))
+    app = h2.Hydro2D(n, n, rho, ene, budget=budget, flags=flags | ooc.FLAG_PREFETCH)
+    app.initialise()
+    planner = h2.Hydro2D(n, n, None, None, budget=budget, flags=flags, plan_only=True)
+    planner.ctx.set_flags(ooc.FLAG_CYCLIC, 0)
+
+    def queue_steps(k):
+        for _ in range(k):
+            planner.queue_step()
+
+    pitch = (n + 2 * h2.H + 1 + 31) // 32 * 32
+    row_bytes = pitch * (4 if flags & ooc.FLAG_FP32_STREAM else 8)
+    return app, planner.ctx, queue_steps, n * n, row_bytes
+
+
 def ns3d_workload(n: int, budget: int, flags: int = 0):
     """(live app, plan-only context, queue_steps, cells, row_bytes) for the
     Navier-Stokes proxy at n^3 (Taylor-Green input)."""
@@ -147,7 +200,8 @@ def main():
     import json
     import sys
     ap = argparse.ArgumentParser(description="exhaustive schedule sweep + cost model")
-    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--workload", choices=["ns3d", "hydro2d"], default="ns3d")
+    ap.add_argument("--n", type=int, default=0, help="cells per axis (default 512 for ns3d, 15360 for hydro2d)")
     ap.add_argument("--budget-frac", type=float, default=1.0 / 3.0)
     ap.add_argument("--hs", default="8,16,24,32,48,0")
     ap.add_argument("--ks", default="1,2,3")
@@ -156,20 +210,33 @@ def main():
     ap.add_argument("--fp32", action="store_true")
     ap.add_argument("--out", default="gpurun_out/tune_records.json")
     a = ap.parse_args()
-    from . import ns3d as N
-    budget = int(N.footprint_bytes(a.n) * a.budget_frac)
     flags = ooc.FLAG_FP32_STREAM if a.fp32 else 0
     log = lambda *x: print(*x, file=sys.stderr, flush=True)
-    app, plan_ctx, q, cells, rb = ns3d_workload(a.n, budget, flags)
+    if a.workload == "ns3d":
+        from . import ns3d as N
+        a.n = a.n or 512
+        budget = int(N.footprint_bytes(a.n) * a.budget_frac)
+        app, plan_ctx, q, cells, rb = ns3d_workload(a.n, budget, flags)
+    else:
+        from . import hydro2d as h2
+        a.n = a.n or 15360
+        budget = int(h2.footprint_bytes(a.n, a.n) * a.budget_frac)
+        app, plan_ctx, q, cells, rb = hydro2d_workload(a.n, budget, flags)
     cands = grid([int(x) for x in a.hs.split(",")], [int(x) for x in a.ks.split(",")],
                  [int(x) for x in a.ss.split(",")])
     recs = sweep(app, plan_ctx, q, cells, rb, budget, cands, a.chains, log)
-    with open(a.out, "w") as f:
-        json.dump({"n": a.n, "budget": budget, "fp32": a.fp32, "features": FEATURE_NAMES, "records": recs}, f)
+    app.close()
     best = min(recs, key=lambda r: r["sec_per_cell_step"])
     log("best h=%d k=%d S=%d %.3e s/cell-step (%.3g updates/s)" %
         (best["h"], best["k"], best["S"], best["sec_per_cell_step"], 1.0 / best["sec_per_cell_step"]))
-    app.close()
+    learned = [holdout_regret(recs, 0.5, seed) for seed in (1, 2, 3)]
+    for r in learned:
+        log("cost model (trained on %d of %d): pick h=%d k=%d S=%d, regret %.3f, gain over default %s" %
+            (r["train"], r["of"], *r["pick"], r["regret"],
+             "%.3f" % r["gain_over_default"] if r["gain_over_default"] else "n/a"))
+    with open(a.out, "w") as f:
+        json.dump({"workload": a.workload, "n": a.n, "budget": budget, "fp32": a.fp32, "features": FEATURE_NAMES,
+                   "records": recs, "best": [best["h"], best["k"], best["S"]], "learned": learned}, f)
 
 
 if __name__ == "__main__":
