@@ -67,7 +67,8 @@ class Hydro2DWork(Workload):
             return h2.Hydro2D(self.n, self.n, self.rho, self.ene, budget=h2.device_footprint_bytes(self.n, self.n),
                               flags=flags)
         return h2.Hydro2D(self.n, self.n, self.rho, self.ene, budget=budget, flags=flags,
-                          resident_geometry=self.args.resident_geometry, cyclic_after_init=not self.args.no_cyclic)
+                          resident_geometry=self.args.resident_geometry, cyclic_after_init=not self.args.no_cyclic,
+                          resident_state=self.args.resident_state)
 
     def describe(self):
         return ("hydro2d proxy %dx%d FP64, 25 fields, 55-loop chain per step, device budget %.3g B "
@@ -115,7 +116,8 @@ class Hydro3DWork(Workload):
             return h3.Hydro3D(self.dims, self.rho, self.ene, budget=h3.device_footprint_bytes(self.dims),
                               flags=flags)
         return h3.Hydro3D(self.dims, self.rho, self.ene, budget=budget, flags=flags,
-                          resident_geometry=self.args.resident_geometry, cyclic_after_init=not self.args.no_cyclic)
+                          resident_geometry=self.args.resident_geometry, cyclic_after_init=not self.args.no_cyclic,
+                          resident_state=self.args.resident_state)
 
     def describe(self):
         return ("hydro3d proxy %d^3 FP64, 30 fields, 82-loop chain per step, device budget %.3g B "
@@ -238,6 +240,8 @@ def main():
     ap.add_argument("--n", type=int, default=0, help="cells per axis (default: the workload's size)")
     ap.add_argument("--budget", type=float, default=0, help="device bytes (default: the workload's budget)")
     ap.add_argument("--resident-geometry", action="store_true")
+    ap.add_argument("--resident-state", action="store_true",
+                    help="hydro: keep geometry and state on the device; only temporaries are tiled")
     ap.add_argument("--fp32", action="store_true", help="store and stream fields as float32 on the host")
     ap.add_argument("--no-prefetch", action="store_true")
     ap.add_argument("--kernel-copy", action="store_true", help="host-link transfers by copy kernel")
@@ -329,7 +333,8 @@ def main():
     ms_step = ooc_r["seconds"] / args.steps * 1e3
     config = {"workload": w.describe(), "global_batch": w.cells, "seq_len": 1, "parallelism": "single-gpu",
               "prefetch": not args.no_prefetch, "cyclic": not args.no_cyclic,
-              "resident_geometry": args.resident_geometry, "fp32_stream": args.fp32,
+              "resident_geometry": args.resident_geometry, "resident_state": args.resident_state,
+              "fp32_stream": args.fp32,
               "kernel_copy": args.kernel_copy, "fuse": args.fuse, "tiles": ooc_r["ntiles"],
               "tile_rows": ooc_r["tile_rows"], "slots": args.slots or 3}
     if args.workload == "ns3d":

@@ -79,9 +79,10 @@ enum {
   OOC_FLAG_DEBUG_POISON = 64, /* fill every slot with NaN before use (finds missing uploads) */
   OOC_FLAG_DEBUG_SYNC = 128,  /* serialise the three streams (separates races from plan bugs) */
   OOC_FLAG_PLAN_ONLY = 256,   /* no host or device storage: for ooc_debug_plan only (schedule search) */
-  OOC_FLAG_KERNEL_COPY = 512  /* host-link transfers by a copy kernel on the pinned arrays' device
-                                 mapping (one launch per tile and direction; FP32 converted in flight)
-                                 instead of runtime memcpy calls */
+  OOC_FLAG_KERNEL_COPY = 512  /* uploads too by a copy kernel on the pinned arrays' device mapping
+                                 (one launch per tile; FP32 converted in flight) instead of runtime
+                                 memcpy calls.  Downloads always go by copy kernel when the host
+                                 arrays are device-mapped (pinned by ooc_bind_device) */
 };
 
 /* per-field flags for ooc_decl_field */

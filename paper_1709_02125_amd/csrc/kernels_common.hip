@@ -273,8 +273,11 @@ struct XferTable {
 };
 constexpr int64_t kXferChunk = 4096;  // elements per block
 
-__global__ void __launch_bounds__(256) k_xfer(XferTable t) {
-  const int64_t b = blockIdx.x;
+// A modest grid strides over the chunks: the copy is bound by the host link,
+// and a small grid leaves the compute units to the stencil kernels.
+constexpr int kXferMaxBlocks = 512;
+
+__device__ void xfer_chunk(const XferTable &t, int64_t b) {
   int s = 0;
   while (s + 1 < t.nseg && b >= t.blk0[s + 1]) s++;
   const int64_t base = (b - t.blk0[s]) * kXferChunk;
@@ -300,6 +303,10 @@ __global__ void __launch_bounds__(256) k_xfer(XferTable t) {
   }
 }
 
+__global__ void __launch_bounds__(256) k_xfer(XferTable t) {
+  for (int64_t b = blockIdx.x; b < t.blk0[t.nseg]; b += gridDim.x) xfer_chunk(t, b);
+}
+
 void launch_xfer_segments(const XferSeg *segs, int nseg, void *stream) {
   for (int s0 = 0; s0 < nseg; s0 += 32) {
     XferTable t{};
@@ -315,7 +322,8 @@ void launch_xfer_segments(const XferSeg *segs, int nseg, void *stream) {
       blocks += (g.n + kXferChunk - 1) / kXferChunk;
     }
     t.blk0[t.nseg] = blocks;
-    if (blocks) hipLaunchKernelGGL(k_xfer, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, t);
+    const int64_t grid = blocks < kXferMaxBlocks ? blocks : kXferMaxBlocks;
+    if (blocks) hipLaunchKernelGGL(k_xfer, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, t);
   }
 }
 

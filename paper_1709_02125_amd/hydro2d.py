@@ -29,6 +29,7 @@ FIELDS = [  # name, centring, streamed state?
     ("w_pre", NODE), ("w_post", NODE), ("w_ef", NODE), ("w_nf", NODE), ("w_nmpost", NODE),
     ("w_nmpre", NODE), ("w_mf", NODE)]
 GEOMETRY = ("vol", "xarea", "yarea")
+STATE = ("rho0", "e0", "u0", "v0")           # what persists from step to step
 N4 = ((0, 0), (1, 0), (0, 1), (1, 1))        # the four nodes of a cell
 C4 = ((-1, -1), (0, -1), (-1, 0), (0, 0))    # the four cells of a node
 
@@ -63,11 +64,13 @@ class Hydro2D:
 
     budget: device bytes for the context; flags: ooc.FLAG_*; resident_geometry
     keeps vol/xarea/yarea on the device (they are read-only after the init
-    chain)."""
+    chain); resident_state keeps the geometry and the state (rho0, e0, u0, v0)
+    on the device, so only the temporaries are tiled and nothing crosses the
+    host link between steps."""
 
     def __init__(self, nx: int, ny: int, rho: np.ndarray, ene: np.ndarray, budget: int, flags: int = 0,
                  resident_geometry: bool = False, cyclic_after_init: bool = True, bind: bool = True,
-                 arena_bytes: int | None = None, plan_only: bool = False):
+                 arena_bytes: int | None = None, plan_only: bool = False, resident_state: bool = False):
         self.nx, self.ny = nx, ny
         if plan_only:
             flags |= ooc.FLAG_PLAN_ONLY
@@ -83,7 +86,8 @@ class Hydro2D:
             elif name == "e0":
                 init = full_extent(nx, ny, c, ene)
             self.f[name] = self.ctx.decl_field(name, c + (0,), init,
-                                               resident=resident_geometry and name in GEOMETRY)
+                                               resident=(resident_geometry and name in GEOMETRY) or
+                                               (resident_state and name in GEOMETRY + STATE))
         self.centring = dict(FIELDS)
         self.dt = self.ctx.decl_reduction(ooc.RED_MIN)
         self.mass = self.ctx.decl_reduction(ooc.RED_SUM)

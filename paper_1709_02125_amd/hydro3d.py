@@ -37,6 +37,7 @@ FIELDS = [
     ("w_pre", NODE), ("w_post", NODE), ("w_ef", NODE), ("w_nf", NODE), ("w_nmpost", NODE),
     ("w_nmpre", NODE), ("w_mf", NODE)]
 GEOMETRY = ("vol", "xarea", "yarea", "zarea")
+STATE = ("rho0", "e0", "u0", "v0", "w0")     # what persists from step to step
 VEL0, VEL1 = ("u0", "v0", "w0"), ("u1", "v1", "w1")
 AREA, VF, MF = ("xarea", "yarea", "zarea"), ("vfx", "vfy", "vfz"), ("mfx", "mfy", "mfz")
 N8 = tuple(itertools.product((0, 1), repeat=3))          # the 8 nodes of a cell
@@ -86,11 +87,12 @@ def full_extent(n, centring, interior=None):
 class Hydro3D:
     """Drives one 3D hydro run through the library (arguments as the 2D
     proxy's: budget in device bytes, flags ooc.FLAG_*, resident_geometry keeps
-    the read-only vol and face areas on the device)."""
+    the read-only vol and face areas on the device, resident_state keeps the
+    geometry and the state so only the temporaries are tiled)."""
 
     def __init__(self, n, rho: np.ndarray, ene: np.ndarray, budget: int, flags: int = 0,
                  resident_geometry: bool = False, cyclic_after_init: bool = True, bind: bool = True,
-                 arena_bytes: int | None = None, plan_only: bool = False):
+                 arena_bytes: int | None = None, plan_only: bool = False, resident_state: bool = False):
         self.n = tuple(n)
         if plan_only:
             flags |= ooc.FLAG_PLAN_ONLY
@@ -103,7 +105,8 @@ class Hydro3D:
                 init = full_extent(self.n, c, rho)
             elif not plan_only and name == "e0":
                 init = full_extent(self.n, c, ene)
-            self.f[name] = self.ctx.decl_field(name, c, init, resident=resident_geometry and name in GEOMETRY)
+            res = (resident_geometry and name in GEOMETRY) or (resident_state and name in GEOMETRY + STATE)
+            self.f[name] = self.ctx.decl_field(name, c, init, resident=res)
         self.centring = dict(FIELDS)
         self.dt = self.ctx.decl_reduction(ooc.RED_MIN)
         self.mass = self.ctx.decl_reduction(ooc.RED_SUM)

@@ -27,7 +27,7 @@ def rel_err(g, o):
 
 
 def gpu_hydro(nx, ny, steps, budget=None, flags=0, tile_rows=0, slots=0, incore=False, rho=None, ene=None,
-              per_step_dt=False, resident_geometry=False, cyclic=True):
+              per_step_dt=False, resident_geometry=False, cyclic=True, resident_state=False):
     if rho is None:
         rho, ene = hydro_initial_state((nx, ny))
     if incore:
@@ -36,7 +36,7 @@ def gpu_hydro(nx, ny, steps, budget=None, flags=0, tile_rows=0, slots=0, incore=
     elif budget is None:
         budget = h2.footprint_bytes(nx, ny) // 3
     app = h2.Hydro2D(nx, ny, rho, ene, budget=budget, flags=flags, resident_geometry=resident_geometry,
-                     cyclic_after_init=cyclic)
+                     cyclic_after_init=cyclic, resident_state=resident_state)
     if tile_rows or slots:
         app.ctx.set_schedule(tile_rows=tile_rows, slots=slots)
     dts = [app.initialise()]

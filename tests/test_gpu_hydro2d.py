@@ -67,6 +67,18 @@ def test_hydro2d_incore_matches_oracle():
         assert rel_err(got[n], ref[n]) <= TOL, n
 
 
+def test_hydro2d_resident_state_bit_exact():
+    # geometry and state stay on the device; only temporaries are tiled
+    nx, ny, steps = 48, 90, 3
+    say("case: resident state")
+    ref, rdts, _ = gpu_hydro(nx, ny, steps, incore=True)
+    got, gdts, st = gpu_hydro(nx, ny, steps, budget=h2.footprint_bytes(nx, ny) // 2, resident_state=True)
+    assert st["ntiles_last"] >= 2 and st["last_bytes_h2d"] == 0 and st["last_bytes_d2h"] == 0
+    for n in STATE:
+        assert np.array_equal(got[n], ref[n]), n
+    assert gdts == rdts
+
+
 def test_hydro2d_resident_geometry_bit_exact():
     nx, ny, steps = 48, 60, 3
     say("case: resident geometry")
