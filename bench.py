@@ -61,14 +61,23 @@ class Hydro2DWork(Workload):
         self.rho, self.ene = hydro_initial_state((self.n, self.n))
         self.knames = {**COMMON, **{100 + i: s for i, s in enumerate(H2D_NAMES)}}
 
-    def make(self, budget, flags, incore=False):
+    def make(self, budget, flags, incore=False, **opts):
         h2 = self.mod
         if incore:
             return h2.Hydro2D(self.n, self.n, self.rho, self.ene, budget=h2.device_footprint_bytes(self.n, self.n),
                               flags=flags)
         return h2.Hydro2D(self.n, self.n, self.rho, self.ene, budget=budget, flags=flags,
-                          resident_geometry=self.args.resident_geometry, cyclic_after_init=not self.args.no_cyclic,
-                          resident_state=self.args.resident_state)
+                          resident_geometry=opts.get("resident_geometry", self.args.resident_geometry),
+                          cyclic_after_init=not self.args.no_cyclic,
+                          resident_state=opts.get("resident_state", self.args.resident_state))
+
+    def variants(self):
+        from paper_1709_02125_amd import ooc
+        pf = ooc.FLAG_PREFETCH
+        return [("fp32_stream_resident_geometry", pf | ooc.FLAG_FP32_STREAM, {"resident_geometry": True}),
+                ("resident_geometry", pf, {"resident_geometry": True}),
+                ("resident_state", pf, {"resident_state": True}),
+                ("resident_state_fused", pf | ooc.FLAG_FUSE, {"resident_state": True})]
 
     def describe(self):
         return ("hydro2d proxy %dx%d FP64, 25 fields, 55-loop chain per step, device budget %.3g B "
@@ -110,14 +119,21 @@ class Hydro3DWork(Workload):
         self.knames = {**COMMON, 100: "h2d_eos", 101: "h2d_eos_p",
                        **{300 + i: s for i, s in enumerate(H3D_NAMES)}}
 
-    def make(self, budget, flags, incore=False):
+    def make(self, budget, flags, incore=False, **opts):
         h3 = self.mod
         if incore:
             return h3.Hydro3D(self.dims, self.rho, self.ene, budget=h3.device_footprint_bytes(self.dims),
                               flags=flags)
         return h3.Hydro3D(self.dims, self.rho, self.ene, budget=budget, flags=flags,
-                          resident_geometry=self.args.resident_geometry, cyclic_after_init=not self.args.no_cyclic,
-                          resident_state=self.args.resident_state)
+                          resident_geometry=opts.get("resident_geometry", self.args.resident_geometry),
+                          cyclic_after_init=not self.args.no_cyclic,
+                          resident_state=opts.get("resident_state", self.args.resident_state))
+
+    def variants(self):
+        from paper_1709_02125_amd import ooc
+        pf = ooc.FLAG_PREFETCH
+        return [("fp32_stream_resident_geometry", pf | ooc.FLAG_FP32_STREAM, {"resident_geometry": True}),
+                ("resident_geometry", pf, {"resident_geometry": True})]
 
     def describe(self):
         return ("hydro3d proxy %d^3 FP64, 30 fields, 82-loop chain per step, device budget %.3g B "
@@ -158,16 +174,21 @@ class NS3DWork(Workload):
         self.prims = tgv_initial_state(self.n)
         self.knames = {**COMMON, **{200 + i: s for i, s in enumerate(NS_NAMES)}}
 
-    def make(self, budget, flags, incore=False):
+    def make(self, budget, flags, incore=False, **opts):
         N = self.mod
         if incore:
             return N.NS3D(self.n, self.prims, budget=N.device_footprint_bytes(self.n), flags=flags)
         app = N.NS3D(self.n, self.prims, budget=budget, flags=flags, cyclic_after_init=not self.args.no_cyclic)
+        app.ctx.set_schedule(tile_rows=opts.get("tile_rows", self.args.tile_rows),
+                             chain_steps=opts.get("chain_steps", self.args.chain_steps),
+                             slots=opts.get("slots", self.args.slots))
         return app
 
-    def schedule(self, app):
-        app.ctx.set_schedule(tile_rows=self.args.tile_rows, chain_steps=self.args.chain_steps,
-                             slots=self.args.slots)
+    def variants(self):
+        from paper_1709_02125_amd import ooc
+        pf = ooc.FLAG_PREFETCH
+        return [("chain_steps_1", pf, {"chain_steps": 1}), ("chain_steps_3", pf, {"chain_steps": 3}),
+                ("fp32_stream", pf | ooc.FLAG_FP32_STREAM, {})]
 
     def describe(self):
         return ("ns3d proxy %d^3 FP64 (Taylor-Green, Mach 0.1), 27 fields, 45 loops per step, chains of %d "
@@ -194,13 +215,14 @@ class NS3DWork(Workload):
 WORKLOADS = {"hydro2d": Hydro2DWork, "hydro3d": Hydro3DWork, "ns3d": NS3DWork}
 
 
-def timed_run(app, steps, warmup, timing):
+def timed_run(app, steps, warmup, knames, timing=True):
     """Warm up, then time `steps` steps with wall clock between device syncs.
-    With timing, a further pass of `timing` steps records every launch with
-    hipEvents on the compute stream (kept out of the timed region)."""
+    With timing, every kernel launch of the timed steps is bracketed by
+    hipEvents on the compute stream (the stream the loops run on), so the
+    per-kernel averages come from the same region as the throughput."""
     import torch
     app.run(warmup)
-    app.ctx.set_timing(False)
+    app.ctx.set_timing(timing)
     s0 = app.ctx.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -213,22 +235,79 @@ def timed_run(app, steps, warmup, timing):
     d["seconds"] = t1 - t0
     d["issue_ms"] = s1["last_issue_ms"]
     d["max_call_ms"] = s1["max_call_ms"]
-    if timing:
-        app.ctx.set_timing(True)
-        app.run(timing)
     d["ntiles"] = s1["ntiles_last"]
     d["tile_rows"] = s1["tile_rows"]
     d["slot_bytes"] = s1["slot_bytes"]
+    d["kernels"] = {}
+    if timing:
+        for kid in knames:
+            ms, n, b = app.ctx.kernel_stats(kid)
+            if n:
+                d["kernels"][kid] = (ms, n, b)
+        app.ctx.set_timing(False)
     return d
 
 
-def dominant_kernel(app, knames):
-    best = None
-    for kid in knames:
-        ms, n, b = app.ctx.kernel_stats(kid)
-        if n and (best is None or ms > best[1]):
-            best = (kid, ms, n, b)
-    return best
+def roofline_of(r, knames, where):
+    """Dominant kernel (most time) of a timed run: algorithmic bytes per
+    launch / average launch time, against the HBM peak."""
+    if not r["kernels"]:
+        return None
+    kid, (ms, n, b) = max(r["kernels"].items(), key=lambda kv: kv[1][0])
+    avg_s = ms / n / 1e3
+    achieved = b / n / avg_s / 1e9
+    return {"bound": "hbm", "kernel": knames.get(kid, str(kid)), "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": b // n, "avg_launch_us": round(avg_s * 1e6, 2), "launches": n,
+            "measured_in": where}
+
+
+def committed_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
+    used only while the kernel source still hashes to what was profiled."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_1709_02125_amd", "csrc", kv.get("source", ""))
+    if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != kv.get("source_sha1"):
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def link_probe(nbytes=1 << 30):
+    """Host-link peak as this machine delivers it: one pinned 1 GiB buffer copied
+    to the device, then back, by the runtime (GB/s each way)."""
+    import torch
+    h = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    d = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out = []
+    for dst, src in ((d, h), (h, d)):
+        dst.copy_(src, non_blocking=True)   # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        dst.copy_(src, non_blocking=True)
+        torch.cuda.synchronize()
+        out.append(round(nbytes / (time.perf_counter() - t) / 1e9, 2))
+    del h, d
+    return out
+
+
+def copy_probe(nbytes=1 << 30, reps=3):
+    """A plain device copy of known size (counter calibration for rocprofv3)."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def main():
@@ -252,6 +331,9 @@ def main():
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--chain-steps", type=int, default=2, help="ns3d: time steps per chain")
+    ap.add_argument("--no-variants", action="store_true", help="skip the other schedules of the same grid")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="end with a plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build's path runs on a single MI355X "
@@ -275,15 +357,11 @@ def main():
         flags |= ooc.FLAG_FUSE
     t = time.perf_counter()
     app = w.make(w.budget, flags)
-    if hasattr(w, "schedule"):
-        w.schedule(app)
-    elif args.slots or args.tile_rows:
+    if args.workload != "ns3d" and (args.slots or args.tile_rows):
         app.ctx.set_schedule(tile_rows=args.tile_rows, slots=args.slots)
     app.initialise()
     log("out-of-core setup %.1f s" % (time.perf_counter() - t))
-    ooc_r = timed_run(app, args.steps, args.warmup, timing=2)
-    ooc_dom = dominant_kernel(app, w.knames)
-    ooc_kernel_ms = {w.knames[k]: app.ctx.kernel_stats(k)[0] for k in w.knames}
+    ooc_r = timed_run(app, args.steps, args.warmup, w.knames)
     app.close()
     del app
     torch.cuda.empty_cache()
@@ -293,30 +371,51 @@ def main():
          ooc_r["max_call_ms"]))
 
     # ---- in core: same grid and kernels, every field resident
-    inc_rate, inc_r, dom = None, None, ooc_dom
+    inc_rate, inc_r = None, None
     if not args.no_incore:
         t = time.perf_counter()
         app = w.make(0, ooc.FLAG_INCORE, incore=True)
         app.initialise()
         log("in-core setup %.1f s" % (time.perf_counter() - t))
-        inc_r = timed_run(app, args.steps, args.warmup, timing=5)
-        dom = dominant_kernel(app, w.knames)
+        inc_r = timed_run(app, args.steps, args.warmup, w.knames)
         app.close()
         del app
         torch.cuda.empty_cache()
         inc_rate = w.cells * args.steps / inc_r["seconds"]
         log("in-core: %.3f s/step, %.3g upd/s" % (inc_r["seconds"] / args.steps, inc_rate))
 
-    kid, kms, kn, kbytes = dom
-    avg_s = kms / kn / 1e3
-    achieved = kbytes / kn / avg_s / 1e9
-    roofline = {"bound": "hbm", "kernel": w.knames.get(kid, str(kid)), "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_launch": kbytes // kn, "avg_launch_us": round(avg_s * 1e6, 2),
-                "launches": kn, "measured_in": "in-core" if inc_r else "out-of-core"}
+    # ---- other schedules of the same grid and budget (not the headline)
+    variants = {}
+    if not args.no_variants:
+        for vname, vflags, vopts in w.variants():
+            t = time.perf_counter()
+            app = w.make(w.budget, vflags, **vopts)
+            app.initialise()
+            r = timed_run(app, args.steps, args.warmup, w.knames, timing=False)
+            app.close()
+            del app
+            torch.cuda.empty_cache()
+            rate = w.cells * args.steps / r["seconds"]
+            variants[vname] = {"value": rate, "ms_per_step": round(r["seconds"] / args.steps * 1e3, 3),
+                               "pct_of_incore": round(100.0 * rate / inc_rate, 2) if inc_rate else None,
+                               "h2d_GBs": round(r["bytes_h2d"] / r["seconds"] / 1e9, 2),
+                               "d2h_GBs": round(r["bytes_d2h"] / r["seconds"] / 1e9, 2),
+                               "tiles": r["ntiles"], "tile_rows": r["tile_rows"]}
+            log("variant %s: %.3f s/step, %.3g upd/s (setup+run %.1f s)" %
+                (vname, r["seconds"] / args.steps, rate, time.perf_counter() - t))
+    if args.copy_probe:
+        copy_probe()
+
+    roofline = roofline_of(ooc_r, w.knames, "out-of-core timed steps")
+    if roofline:
+        roofline["traffic"] = committed_traffic(roofline["kernel"], args.workload)
+    incore_roofline = roofline_of(inc_r, w.knames, "in-core timed steps") if inc_r else None
+    probe_h2d, probe_d2h = link_probe()
     link = {"h2d_GBs": round(ooc_r["bytes_h2d"] / ooc_r["seconds"] / 1e9, 2),
             "d2h_GBs": round(ooc_r["bytes_d2h"] / ooc_r["seconds"] / 1e9, 2),
             "peak_per_direction_GBs": LINK_PEAK_GBS,
+            "probe_h2d_GBs": probe_h2d, "probe_d2h_GBs": probe_d2h,
+            "h2d_frac_of_probe": round(ooc_r["bytes_h2d"] / ooc_r["seconds"] / 1e9 / probe_h2d, 3),
             "h2d_bytes_per_step": ooc_r["bytes_h2d"] // args.steps,
             "d2h_bytes_per_step": ooc_r["bytes_d2h"] // args.steps,
             "edge_bytes_per_step": ooc_r["bytes_edge"] // args.steps}
@@ -351,9 +450,11 @@ def main():
         "average_bandwidth_GBs": round(avg_bw, 1),
         "alg_bytes_per_cell_step": round(ooc_r["bytes_hbm_alg"] / (w.cells * args.steps), 1),
         "roofline": roofline,
+        "incore_roofline": incore_roofline,
         "link": link,
+        "variants": variants,
         "cpu_baseline": cpu,
-        "ooc_kernel_ms": {k: round(v, 2) for k, v in ooc_kernel_ms.items() if v},
+        "ooc_kernel_ms": {w.knames[k]: round(v[0], 2) for k, v in ooc_r["kernels"].items()},
     }
     print(json.dumps(out), flush=True)
 
