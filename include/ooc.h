@@ -198,7 +198,10 @@ int ooc_set_schedule(ooc_ctx *ctx, int64_t tile_rows, int chain_steps, int slots
 int ooc_get_stats(ooc_ctx *ctx, ooc_stats *out);
 
 /* Enable per-launch timing with hipEvents (adds a little overhead); read the
- * summed kernel time of the last flush from ooc_stats.last_kernel_ms. */
+ * summed kernel time of the last flush from ooc_stats.last_kernel_ms.
+ * on = 1 times every loop launch; on = 2 + k times only launches of kernel
+ * id k (one kernel's figures with few events in flight); 0 turns it off.
+ * Every call clears the accumulated per-kernel figures. */
 int ooc_set_timing(ooc_ctx *ctx, int on);
 
 /* Accumulated timing of one kernel id over the flushes since timing was

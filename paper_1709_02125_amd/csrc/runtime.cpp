@@ -101,6 +101,7 @@ struct ooc_ctx {
   std::vector<int64_t> dbg_loop_rows, dbg_res, dbg_up, dbg_down, dbg_edge;
   ooc_stats st{};
   bool timing = false;
+  int timing_kid = -1;  // with timing: only this kernel id (-1: every loop)
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> tev_pool;
   size_t tev_next = 0;
@@ -496,7 +497,7 @@ KArgs make_kargs(ooc_ctx *c, const LoopRec &L, const Plan &P, int i, int t, char
 
 void launch_loop(ooc_ctx *c, int kid, const KArgs &a, const KArgs *dev, uint64_t bytes) {
   const KernelInfo &ki = table()[kid];
-  if (c->timing) {
+  if (c->timing && (c->timing_kid < 0 || c->timing_kid == kid)) {
     TimedLaunch tl{kid, bytes, timing_event(c), timing_event(c)};
     HIPCHK(hipEventRecord(tl.a, c->s_comp));
     ki.launch(a, dev, c->ndim, c->s_comp);
@@ -1282,7 +1283,9 @@ int ooc_get_stats(ooc_ctx *c, ooc_stats *out) {
 
 int ooc_set_timing(ooc_ctx *c, int on) {
   GUARD(c);
-  c->timing = on != 0;
+  if (on < 0 || on >= 2 + OOC_K_MAX_ID) return fail(c, OOC_E_ARG, "timing mode out of range");
+  c->timing = on != 0;  // read when loops are issued
+  c->timing_kid = on >= 2 ? on - 2 : -1;
   c->kstats.clear();
   return OOC_OK;
 }

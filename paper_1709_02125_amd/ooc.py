@@ -293,8 +293,10 @@ class Context:
     def set_schedule(self, tile_rows: int = 0, chain_steps: int = 0, slots: int = 0):
         self._check(self.lib.ooc_set_schedule(self._h, int(tile_rows), int(chain_steps), int(slots)))
 
-    def set_timing(self, on: bool):
-        self._check(self.lib.ooc_set_timing(self._h, int(on)))
+    def set_timing(self, on: bool, kernel_id: int | None = None):
+        """Per-launch hipEvent timing of every loop, or of one kernel id only."""
+        mode = 0 if not on else (1 if kernel_id is None else 2 + int(kernel_id))
+        self._check(self.lib.ooc_set_timing(self._h, mode))
 
     def stats(self) -> dict:
         s = ooc_stats()
