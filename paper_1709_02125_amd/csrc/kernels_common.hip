@@ -27,8 +27,9 @@ __device__ inline void mirror_point(const KArgs &a, int i, int j, int k) {
 
 OOC_KERNEL(k_mirror) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   mirror_point(a, i, j, k);
+  POINT_END
 }
 
 // Several independent mirror loops of one tile in a single launch: block b
@@ -49,10 +50,10 @@ __global__ void __launch_bounds__(256) k_mirror_batch(MirrorBatch mb) {
   const int lb = b - mb.blk0[s];
   const int bx = lb % mb.gx[s], by = (lb / mb.gx[s]) % mb.gy[s], bz = lb / (mb.gx[s] * mb.gy[s]);
   const int i = a.lo[0] + bx * 64 + (int)threadIdx.x;
-  const int j = a.lo[1] + by * 4 + (int)threadIdx.y;
+  const int j0 = a.lo[1] + by * kBlockRows + (int)threadIdx.y;
   const int k = a.lo[2] + bz;
-  if (i >= a.hi[0] || j >= a.hi[1]) return;
-  mirror_point(a, i, j, k);
+  if (i >= a.hi[0]) return;
+  for (int r = 0; r < kRowsPerThread && j0 + 4 * r < a.hi[1]; r++) mirror_point(a, i, j0 + 4 * r, k);
 }
 
 void launch_mirror_batch(const KArgs *const *host_args, const KArgs *const *dev_args, int n, int ndim,
@@ -76,30 +77,35 @@ void launch_mirror_batch(const KArgs *const *host_args, const KArgs *const *dev_
 
 OOC_KERNEL(k_fill_pt) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   AT(0, 0, 0, 0) = a.c[0];
+  POINT_END
 }
 
 // out = c0 * (sum over the stencil of in) / npts + c1, stencil summed in order
 OOC_KERNEL(k_avg) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   double s = 0.0;
   for (int q = 0; q < a.nst; q++) s += AT(1, a.st[q][0], a.st[q][1], a.st[q][2]);
   AT(0, 0, 0, 0) = a.c[0] * (s / (double)a.nst) + a.c[1];
+  POINT_END
 }
 
 OOC_KERNEL(k_inc_add) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   AT(0, 0, 0, 0) = AT(0, 0, 0, 0) + a.c[0] * AT(1, 0, 0, 0);
+  POINT_END
 }
 
 OOC_KERNEL(k_minmax) {
   ARGS
-  POINT_INDEX_ACTIVE;
-  double v = active ? AT(0, 0, 0, 0) : INFINITY;
-  double w = active ? AT(0, 0, 0, 0) : -INFINITY;
+  double v = INFINITY, w = -INFINITY;  // over this thread's points
+  POINT_BEGIN
+  v = fmin(v, AT(0, 0, 0, 0));
+  w = fmax(w, AT(0, 0, 0, 0));
+  POINT_END
   block_min_to(v, a.red[0]);
   block_max_to(w, a.red[1]);
 }

@@ -14,19 +14,40 @@ namespace ooc {
 #define OOC_KERNEL(name) __global__ void __launch_bounds__(256) name(const KArgs *__restrict__ ap)
 #define ARGS const KArgs &a = *ap;
 
-// Point kernels run 64 x 4 blocks: one wavefront per row segment of 64 x-points,
-// so every load of a field row is a coalesced 512-byte access.
-#define POINT_INDEX_OR_RETURN                                     \
-  const int i = a.lo[0] + (int)(blockIdx.x * 64 + threadIdx.x);   \
-  const int j = a.lo[1] + (int)(blockIdx.y * 4 + threadIdx.y);    \
-  const int k = a.lo[2] + (int)blockIdx.z;                        \
-  if (i >= a.hi[0] || j >= a.hi[1]) return;
+// Point kernels run 64 x 4 threads: one wavefront per row segment of 64
+// x-points, so every load of a field row is a coalesced 512-byte access.  Each
+// thread row walks kRowsPerThread rows 4 apart, so a block covers 64 x 16
+// points and the row above a wavefront's row is read by its neighbour wave on
+// the same CU at about the same time (the j+1 stencil reads hit L1/L2).
+// Workgroup ids are handed to the 8 XCDs round-robin; the block order is
+// remapped so each XCD gets a contiguous run of blocks, keeping the lines
+// that neighbouring blocks share in one L2.
+constexpr int kRowsPerThread = 4;
+constexpr int kBlockRows = 4 * kRowsPerThread;
+constexpr int kXcds = 8;
 
-#define POINT_INDEX_ACTIVE                                        \
-  const int i = a.lo[0] + (int)(blockIdx.x * 64 + threadIdx.x);   \
-  const int j = a.lo[1] + (int)(blockIdx.y * 4 + threadIdx.y);    \
-  const int k = a.lo[2] + (int)blockIdx.z;                        \
-  const bool active = i < a.hi[0] && j < a.hi[1];
+// bijection of [0, n): workgroup id -> logical block, contiguous per XCD
+__device__ __forceinline__ int xcd_block(int pid, int n) {
+  const int q = n / kXcds, r = n % kXcds, x = pid % kXcds, s = pid / kXcds;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
+}
+
+// Opens the per-point loop: i, j, k are the point's indices inside it.
+#define POINT_BEGIN                                                                        \
+  {                                                                                        \
+    const int n_ = (int)(gridDim.x * gridDim.y * gridDim.z);                               \
+    const int l_ = xcd_block((int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)), n_); \
+    const int bx_ = l_ % (int)gridDim.x, by_ = (l_ / (int)gridDim.x) % (int)gridDim.y;      \
+    const int i = a.lo[0] + bx_ * 64 + (int)threadIdx.x;                                   \
+    const int k = a.lo[2] + l_ / (int)(gridDim.x * gridDim.y);                              \
+    const int j0_ = a.lo[1] + by_ * kBlockRows + (int)threadIdx.y;                           \
+    if (i < a.hi[0])                                                                       \
+      for (int r_ = 0; r_ < kRowsPerThread; r_++) {                                        \
+        const int j = j0_ + 4 * r_;                                                        \
+        if (j >= a.hi[1]) break;
+#define POINT_END \
+  }               \
+  }
 
 // element (i+di, j+dj, k+dk) of DAT argument n
 #define AT(n, di, dj, dk) \
@@ -36,7 +57,7 @@ inline dim3 point_grid(const KArgs &a, int ndim) {
   const int nx = a.hi[0] - a.lo[0], ny = a.hi[1] - a.lo[1];
   const int nz = ndim == 3 ? a.hi[2] - a.lo[2] : 1;
   if (nx <= 0 || ny <= 0 || nz <= 0) return dim3(0, 0, 0);
-  return dim3((nx + 63) / 64, (ny + 3) / 4, nz);
+  return dim3((nx + 63) / 64, (ny + kBlockRows - 1) / kBlockRows, nz);
 }
 
 __device__ inline double wave_min(double v) {

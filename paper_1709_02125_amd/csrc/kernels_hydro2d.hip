@@ -1,6 +1,7 @@
-// 2D hydro proxy kernels (FP64, gfx950).  One kernel per loop of the chain; a
-// point per thread, 64 x 4 blocks so each wavefront reads 64 consecutive x of
-// a row.  The path is HBM-bound (well under 1 flop per byte), so there is no
+// 2D hydro proxy kernels (FP64, gfx950).  One kernel per loop of the chain;
+// 64 x 4 threads walking 4 rows each (the point loop of kernels_device.h), so
+// each wavefront reads 64 consecutive x of a row.  The path is HBM-bound (well
+// under 1 flop per byte), so there is no
 // MFMA here.  Expression order matches the plain program exactly (compiled
 // with -ffp-contract=off): tiled and untiled runs are bit-identical, and the
 // CPU oracle agrees to rounding.
@@ -27,29 +28,32 @@ constexpr double kCfl = 0.5;
 // p = (g-1) rho e ; cs = sqrt(g p / rho)
 OOC_KERNEL(k_eos) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double r = AT(0, 0, 0, 0);
   const double p = (kGm1 * r) * AT(1, 0, 0, 0);
   AT(2, 0, 0, 0) = p;
   AT(3, 0, 0, 0) = sqrt((kGamma * p) / r);
+  POINT_END
 }
 
 OOC_KERNEL(k_eos_p) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   AT(2, 0, 0, 0) = (kGm1 * AT(0, 0, 0, 0)) * AT(1, 0, 0, 0);
+  POINT_END
 }
 
 // q from the velocity jumps across the cell: compression d = du + dv < 0
 OOC_KERNEL(k_visc) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double du = 0.5 * ((AT(2, 1, 0, 0) + AT(2, 1, 1, 0)) - (AT(2, 0, 0, 0) + AT(2, 0, 1, 0)));
   const double dv = 0.5 * ((AT(3, 0, 1, 0) + AT(3, 1, 1, 0)) - (AT(3, 0, 0, 0) + AT(3, 1, 0, 0)));
   const double d = du + dv;
   double q = 0.0;
   if (d < 0.0) q = AT(0, 0, 0, 0) * ((kCq2 * d) * d - (kCq1 * AT(1, 0, 0, 0)) * d);
   AT(4, 0, 0, 0) = q;
+  POINT_END
 }
 
 // PdV: volume change from face fluxes (dt/4 times the summed node velocities of
@@ -58,7 +62,7 @@ OOC_KERNEL(k_visc) {
 template <bool kCorr>
 OOC_KERNEL(k_pdv) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double fac = 0.25 * a.ds[0][0];
   double ul, ur, vb, vt;
   if (kCorr) {
@@ -82,13 +86,14 @@ OOC_KERNEL(k_pdv) {
   constexpr int R1 = kCorr ? 11 : 9, E1 = kCorr ? 12 : 10;
   AT(R1, 0, 0, 0) = m / (vol + total);
   AT(E1, 0, 0, 0) = AT(1, 0, 0, 0) - ((AT(2, 0, 0, 0) + AT(3, 0, 0, 0)) * total) / m;
+  POINT_END
 }
 
 // Node acceleration from the pressure + viscosity of the four surrounding
 // cells; wall-normal velocity of wall nodes held at zero.
 OOC_KERNEL(k_accel) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double pbl = AT(2, -1, -1, 0) + AT(3, -1, -1, 0);
   const double pbr = AT(2, 0, -1, 0) + AT(3, 0, -1, 0);
   const double ptl = AT(2, -1, 0, 0) + AT(3, -1, 0, 0);
@@ -105,39 +110,43 @@ OOC_KERNEL(k_accel) {
   if (j == 0 || j == ny) v = 0.0;
   AT(8, 0, 0, 0) = u;
   AT(9, 0, 0, 0) = v;
+  POINT_END
 }
 
 // face volume flux of the step; D = 0: x-faces (nodes j, j+1), D = 1: y-faces
 template <int D>
 OOC_KERNEL(k_flux) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const int ex = D == 1, ey = D == 0;  // step to the face's second node
   const double fac = 0.25 * a.ds[0][0];
   AT(3, 0, 0, 0) = (fac * AT(0, 0, 0, 0)) * ((AT(1, 0, 0, 0) + AT(2, 0, 0, 0)) + (AT(1, ex, ey, 0) + AT(2, ex, ey, 0)));
+  POINT_END
 }
 
 OOC_KERNEL(k_adv_vol_x) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double dfx = AT(1, 1, 0, 0) - AT(1, 0, 0, 0);
   const double pre = AT(0, 0, 0, 0) + (dfx + (AT(2, 0, 1, 0) - AT(2, 0, 0, 0)));
   AT(3, 0, 0, 0) = pre;
   AT(4, 0, 0, 0) = pre - dfx;
+  POINT_END
 }
 
 OOC_KERNEL(k_adv_vol_y) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   AT(2, 0, 0, 0) = AT(0, 0, 0, 0) + (AT(1, 0, 1, 0) - AT(1, 0, 0, 0));
   AT(3, 0, 0, 0) = AT(0, 0, 0, 0);
+  POINT_END
 }
 
 // donor-cell mass and energy flux through the face between cells p-e and p
 template <int D>
 OOC_KERNEL(k_adv_flux) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const int ex = D == 0, ey = D == 1;
   const double f = AT(0, 0, 0, 0);
   double mf = 0.0, ef = 0.0;
@@ -150,71 +159,77 @@ OOC_KERNEL(k_adv_flux) {
   }
   AT(3, 0, 0, 0) = mf;
   AT(4, 0, 0, 0) = ef;
+  POINT_END
 }
 
 template <int D>
 OOC_KERNEL(k_adv_cell) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const int ex = D == 0, ey = D == 1;
   const double pm = AT(0, 0, 0, 0) * AT(2, 0, 0, 0);
   const double post = pm + (AT(4, 0, 0, 0) - AT(4, ex, ey, 0));
   const double pe = (AT(1, 0, 0, 0) * pm + (AT(5, 0, 0, 0) - AT(5, ex, ey, 0))) / post;
   AT(0, 0, 0, 0) = post / AT(3, 0, 0, 0);
   AT(1, 0, 0, 0) = pe;
+  POINT_END
 }
 
 // dual-face mass flux: mean of the four face mass fluxes around it
 template <int D>
 OOC_KERNEL(k_nflux) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   if (D == 0)
     AT(1, 0, 0, 0) = 0.25 * ((AT(0, 0, -1, 0) + AT(0, 0, 0, 0)) + (AT(0, 1, -1, 0) + AT(0, 1, 0, 0)));
   else
     AT(1, 0, 0, 0) = 0.25 * ((AT(0, -1, 0, 0) + AT(0, 0, 0, 0)) + (AT(0, -1, 1, 0) + AT(0, 0, 1, 0)));
+  POINT_END
 }
 
 // node masses after the sweep (from the swept cells) and before it
 template <int D>
 OOC_KERNEL(k_nmass) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const int ex = D == 0, ey = D == 1;
   const double post = 0.25 * ((AT(0, -1, -1, 0) * AT(1, -1, -1, 0) + AT(0, 0, -1, 0) * AT(1, 0, -1, 0)) +
                               (AT(0, -1, 0, 0) * AT(1, -1, 0, 0) + AT(0, 0, 0, 0) * AT(1, 0, 0, 0)));
   AT(3, 0, 0, 0) = post;
   AT(4, 0, 0, 0) = post + (AT(2, 0, 0, 0) - AT(2, -ex, -ey, 0));
+  POINT_END
 }
 
 // donor-cell momentum flux through the dual face between nodes p and p+e
 template <int D>
 OOC_KERNEL(k_mflux) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const int ex = D == 0, ey = D == 1;
   const double f = AT(0, 0, 0, 0);
   double mf = 0.0;
   if (f > 0.0) mf = f * AT(1, 0, 0, 0);
   else if (f < 0.0) mf = f * AT(1, ex, ey, 0);
   AT(2, 0, 0, 0) = mf;
+  POINT_END
 }
 
 template <int D>
 OOC_KERNEL(k_vel) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const int ex = D == 0, ey = D == 1;
   AT(0, 0, 0, 0) = (AT(0, 0, 0, 0) * AT(1, 0, 0, 0) + (AT(3, -ex, -ey, 0) - AT(3, 0, 0, 0))) / AT(2, 0, 0, 0);
+  POINT_END
 }
 
 // stable step of a cell, min-reduced: CFL * min over axes of spacing /
 // (sqrt(c^2 + 2 q / rho) + largest node speed along the axis)
 OOC_KERNEL(k_dt) {
   ARGS
-  POINT_INDEX_ACTIVE;
-  double t = INFINITY;
-  if (active) {
+  double t = INFINITY;  // smallest bound over this thread's points
+  POINT_BEGIN
+  {
     const double c2 = (kGamma * kGm1) * AT(0, 0, 0, 0);
     const double du = 0.5 * ((AT(1, 1, 0, 0) + AT(1, 1, 1, 0)) - (AT(1, 0, 0, 0) + AT(1, 0, 1, 0)));
     const double dv = 0.5 * ((AT(2, 0, 1, 0) + AT(2, 1, 1, 0)) - (AT(2, 0, 0, 0) + AT(2, 1, 0, 0)));
@@ -228,8 +243,9 @@ OOC_KERNEL(k_dt) {
                            fmax(fabs(AT(2, 0, 1, 0)), fabs(AT(2, 1, 1, 0))));
     const double tx = a.c[0] / (ce + um);
     const double ty = a.c[1] / (ce + vm);
-    t = kCfl * fmin(tx, ty);
+    t = fmin(t, kCfl * fmin(tx, ty));
   }
+  POINT_END
   block_min_to(t, a.red[0]);
 }
 

@@ -1,8 +1,9 @@
 // 3D hydro proxy kernels (FP64, gfx950): the three-dimensional form of the 2D
 // proxy -- 8-node cell stencils and 8-cell node stencils, donor-cell remap
 // sweeps x, y, z -- as the paper names CloverLeaf 3D (Section 5.1).  One kernel
-// per loop, a point per thread in 64 x 4 blocks (one wavefront per 64
-// consecutive x of a row), one block row of planes per z.  HBM-bound, no MFMA.
+// per loop over the point loop of kernels_device.h (one wavefront per 64
+// consecutive x of a row, 4 rows per thread, one grid layer per z-plane).
+// HBM-bound, no MFMA.
 // Expression order follows the plain program exactly (built without FP
 // contraction), so tiled and untiled runs are bit-identical.
 //
@@ -52,11 +53,12 @@ __device__ __forceinline__ double jump(const KArgs &a, int n, int i, int j, int 
 // args: R rho0, R cs, R u0, R v0, R w0, W q
 OOC_KERNEL(k_visc) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double d = (jump<0>(a, 2, i, j, k) + jump<1>(a, 3, i, j, k)) + jump<2>(a, 4, i, j, k);
   double q = 0.0;
   if (d < 0.0) q = AT(0, 0, 0, 0) * ((kCq2 * d) * d - (kCq1 * AT(1, 0, 0, 0)) * d);
   AT(5, 0, 0, 0) = q;
+  POINT_END
 }
 
 // PdV predictor / corrector.  args: 0 rho0, 1 e0, 2 p, 3 q, 4 vol, 5..7 x/y/z
@@ -74,7 +76,7 @@ __device__ __forceinline__ double pdv_df(const KArgs &a, int i, int j, int k, do
 template <bool kCorr>
 OOC_KERNEL(k_pdv) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double fac = 0.125 * a.ds[0][0];
   const double total = (pdv_df<kCorr, 0>(a, i, j, k, fac) + pdv_df<kCorr, 1>(a, i, j, k, fac)) +
                        pdv_df<kCorr, 2>(a, i, j, k, fac);
@@ -83,6 +85,7 @@ OOC_KERNEL(k_pdv) {
   constexpr int R1 = kCorr ? 14 : 11, E1 = kCorr ? 15 : 12;
   AT(R1, 0, 0, 0) = m / (vol + total);
   AT(E1, 0, 0, 0) = AT(1, 0, 0, 0) - ((AT(2, 0, 0, 0) + AT(3, 0, 0, 0)) * total) / m;
+  POINT_END
 }
 
 // Node acceleration: the force along each axis is a quarter of the sum, over
@@ -92,7 +95,7 @@ OOC_KERNEL(k_pdv) {
 // w1; CONST nx, ny, nz; DEVSCALAR dt
 OOC_KERNEL(k_accel) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   double P[2][2][2], M[2][2][2];
 #pragma unroll
   for (int c = 0; c < 2; c++)
@@ -121,15 +124,17 @@ OOC_KERNEL(k_accel) {
   AT(10, 0, 0, 0) = u;
   AT(11, 0, 0, 0) = v;
   AT(12, 0, 0, 0) = w;
+  POINT_END
 }
 
 // face volume flux along D.  args: R area, R vel0, R vel1, W vf; DEVSCALAR dt
 template <int D>
 OOC_KERNEL(k_flux) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double fac = 0.125 * a.ds[0][0];
   AT(3, 0, 0, 0) = (fac * AT(0, 0, 0, 0)) * face4_2<D>(a, 1, 2, i, j, k, 0);
+  POINT_END
 }
 
 // volume change through the faces normal to axis AX of field n
@@ -141,30 +146,33 @@ __device__ __forceinline__ double dflux(const KArgs &a, int n, int i, int j, int
 // volumes before / after the x sweep.  args: R vol, R vfx, R vfy, R vfz, W pre, W post
 OOC_KERNEL(k_adv_vol_x) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double dfx = dflux<0>(a, 1, i, j, k);
   const double pre = AT(0, 0, 0, 0) + ((dfx + dflux<1>(a, 2, i, j, k)) + dflux<2>(a, 3, i, j, k));
   AT(4, 0, 0, 0) = pre;
   AT(5, 0, 0, 0) = pre - dfx;
+  POINT_END
 }
 
 // y sweep.  args: R vol, R vfy, R vfz, W pre, W post
 OOC_KERNEL(k_adv_vol_y) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double vol = AT(0, 0, 0, 0);
   const double dfz = dflux<2>(a, 2, i, j, k);
   AT(3, 0, 0, 0) = vol + (dflux<1>(a, 1, i, j, k) + dfz);
   AT(4, 0, 0, 0) = vol + dfz;
+  POINT_END
 }
 
 // z sweep.  args: R vol, R vfz, W pre, W post
 OOC_KERNEL(k_adv_vol_z) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double vol = AT(0, 0, 0, 0);
   AT(2, 0, 0, 0) = vol + dflux<2>(a, 1, i, j, k);
   AT(3, 0, 0, 0) = vol;
+  POINT_END
 }
 
 // donor-cell mass / energy flux through the face between cells p - e_D and p.
@@ -172,7 +180,7 @@ OOC_KERNEL(k_adv_vol_z) {
 template <int D>
 OOC_KERNEL(k_adv_flux) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
   const double f = AT(0, 0, 0, 0);
   double mf = 0.0, ef = 0.0;
@@ -185,19 +193,21 @@ OOC_KERNEL(k_adv_flux) {
   }
   AT(3, 0, 0, 0) = mf;
   AT(4, 0, 0, 0) = ef;
+  POINT_END
 }
 
 // args: RW rho1, RW e1, R pre, R post, R mf, R ef
 template <int D>
 OOC_KERNEL(k_adv_cell) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
   const double pm = AT(0, 0, 0, 0) * AT(2, 0, 0, 0);
   const double post = pm + (AT(4, 0, 0, 0) - AT(4, ex, ey, ez));
   const double pe = (AT(1, 0, 0, 0) * pm + (AT(5, 0, 0, 0) - AT(5, ex, ey, ez))) / post;
   AT(0, 0, 0, 0) = post / AT(3, 0, 0, 0);
   AT(1, 0, 0, 0) = pe;
+  POINT_END
 }
 
 // Dual-face mass flux of sweep D: an eighth of the 8 face mass fluxes on the
@@ -206,7 +216,7 @@ OOC_KERNEL(k_adv_cell) {
 template <int D>
 OOC_KERNEL(k_nflux) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   constexpr int B = D == 0 ? 1 : 0, C = D == 2 ? 1 : 2;
   double t[2];
 #pragma unroll
@@ -225,6 +235,7 @@ OOC_KERNEL(k_nflux) {
     t[e] = (q[0][0] + q[0][1]) + (q[1][0] + q[1][1]);
   }
   AT(1, 0, 0, 0) = 0.125 * (t[0] + t[1]);
+  POINT_END
 }
 
 // node masses after the sweep (from the swept cells) and before it.
@@ -232,7 +243,7 @@ OOC_KERNEL(k_nflux) {
 template <int D>
 OOC_KERNEL(k_nmass) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
 #define CM(x, y, z) (AT(0, (x) - 1, (y) - 1, (z) - 1) * AT(1, (x) - 1, (y) - 1, (z) - 1))
   const double post = 0.125 * (((CM(0, 0, 0) + CM(1, 0, 0)) + (CM(0, 1, 0) + CM(1, 1, 0))) +
@@ -240,6 +251,7 @@ OOC_KERNEL(k_nmass) {
 #undef CM
   AT(3, 0, 0, 0) = post;
   AT(4, 0, 0, 0) = post + (AT(2, 0, 0, 0) - AT(2, -ex, -ey, -ez));
+  POINT_END
 }
 
 // donor-cell momentum flux through the dual face between nodes p and p + e_D.
@@ -247,22 +259,24 @@ OOC_KERNEL(k_nmass) {
 template <int D>
 OOC_KERNEL(k_mflux) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
   const double f = AT(0, 0, 0, 0);
   double mf = 0.0;
   if (f > 0.0) mf = f * AT(1, 0, 0, 0);
   else if (f < 0.0) mf = f * AT(1, ex, ey, ez);
   AT(2, 0, 0, 0) = mf;
+  POINT_END
 }
 
 // args: RW vel, R nmpre, R nmpost, R mf
 template <int D>
 OOC_KERNEL(k_vel) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
   AT(0, 0, 0, 0) = (AT(0, 0, 0, 0) * AT(1, 0, 0, 0) + (AT(3, -ex, -ey, -ez) - AT(3, 0, 0, 0))) / AT(2, 0, 0, 0);
+  POINT_END
 }
 
 // largest absolute value of node field n over the cell's 8 nodes
@@ -277,19 +291,21 @@ __device__ __forceinline__ double absmax8(const KArgs &a, int n, int i, int j, i
 // dy, dz; RED(MIN)
 OOC_KERNEL(k_dt) {
   ARGS
-  POINT_INDEX_ACTIVE;
-  double t = INFINITY;
-  if (active) {
+  double t = INFINITY;  // smallest bound over this thread's points
+  POINT_BEGIN
+  {
     const double c2 = (kGamma * kGm1) * AT(0, 0, 0, 0);
     const double d = (jump<0>(a, 1, i, j, k) + jump<1>(a, 2, i, j, k)) + jump<2>(a, 3, i, j, k);
     double qr = 0.0;
     if (d < 0.0) qr = (kCq2 * d) * d - (kCq1 * sqrt(c2)) * d;
     const double ce = sqrt(c2 + 2.0 * qr);
-    t = fmin(t, a.c[0] / (ce + absmax8(a, 1, i, j, k)));
-    t = fmin(t, a.c[1] / (ce + absmax8(a, 2, i, j, k)));
-    t = fmin(t, a.c[2] / (ce + absmax8(a, 3, i, j, k)));
-    t = kCfl * t;
+    double tc = INFINITY;
+    tc = fmin(tc, a.c[0] / (ce + absmax8(a, 1, i, j, k)));
+    tc = fmin(tc, a.c[1] / (ce + absmax8(a, 2, i, j, k)));
+    tc = fmin(tc, a.c[2] / (ce + absmax8(a, 3, i, j, k)));
+    t = fmin(t, kCfl * tc);
   }
+  POINT_END
   block_min_to(t, a.red[0]);
 }
 

@@ -25,7 +25,7 @@ __device__ inline double deriv(double m2, double m1, double p1, double p2, doubl
 
 OOC_KERNEL(k_ns_init) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double r = AT(0, 0, 0, 0), u = AT(1, 0, 0, 0), v = AT(2, 0, 0, 0), w = AT(3, 0, 0, 0);
   const double p = AT(4, 0, 0, 0);
   AT(5, 0, 0, 0) = r;
@@ -33,11 +33,12 @@ OOC_KERNEL(k_ns_init) {
   AT(7, 0, 0, 0) = r * v;
   AT(8, 0, 0, 0) = r * w;
   AT(9, 0, 0, 0) = p / kGm1 + 0.5 * r * ((u * u + v * v) + w * w);
+  POINT_END
 }
 
 OOC_KERNEL(k_ns_prims) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double r = AT(0, 0, 0, 0), ru = AT(1, 0, 0, 0), rv = AT(2, 0, 0, 0), rw = AT(3, 0, 0, 0);
   const double u = ru / r, v = rv / r, w = rw / r;
   AT(5, 0, 0, 0) = r;
@@ -45,6 +46,7 @@ OOC_KERNEL(k_ns_prims) {
   AT(7, 0, 0, 0) = v;
   AT(8, 0, 0, 0) = w;
   AT(9, 0, 0, 0) = kGm1 * (AT(4, 0, 0, 0) - 0.5 * ((ru * u + rv * v) + rw * w));
+  POINT_END
 }
 
 // T = gamma M^2 p / rho at an offset point
@@ -52,7 +54,7 @@ OOC_KERNEL(k_ns_prims) {
 
 OOC_KERNEL(k_ns_grads) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double inv = a.c[0], gm2 = a.c[1];
 #pragma unroll
   for (int c = 0; c < 3; c++) {
@@ -64,6 +66,7 @@ OOC_KERNEL(k_ns_grads) {
   AT(14, 0, 0, 0) = deriv(TEMP(-2, 0, 0), TEMP(-1, 0, 0), TEMP(1, 0, 0), TEMP(2, 0, 0), inv);
   AT(15, 0, 0, 0) = deriv(TEMP(0, -2, 0), TEMP(0, -1, 0), TEMP(0, 1, 0), TEMP(0, 2, 0), inv);
   AT(16, 0, 0, 0) = deriv(TEMP(0, 0, -2), TEMP(0, 0, -1), TEMP(0, 0, 1), TEMP(0, 0, 2), inv);
+  POINT_END
 }
 #undef TEMP
 
@@ -111,7 +114,7 @@ __device__ inline void ns_axis(const KArgs &a, int i, int j, int k, double mu, d
 template <bool kFirst>
 OOC_KERNEL(k_ns_rhs) {
   ARGS
-  POINT_INDEX_OR_RETURN;
+  POINT_BEGIN
   const double inv = a.c[0], mu = a.c[1], kappa = a.c[2], dt = a.c[3], A = a.c[4], B = a.c[5];
   double res[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   ns_axis<0>(a, i, j, k, mu, kappa, inv, res);
@@ -123,6 +126,7 @@ OOC_KERNEL(k_ns_rhs) {
     AT(DR + c, 0, 0, 0) = d;
     AT(QR + c, 0, 0, 0) = AT(QR + c, 0, 0, 0) + B * d;
   }
+  POINT_END
 }
 
 #define L(name, kern) \
