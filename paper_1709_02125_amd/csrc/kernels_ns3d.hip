@@ -111,22 +111,45 @@ __device__ inline void ns_axis(const KArgs &a, int i, int j, int k, double mu, d
   for (int c = 0; c < 5; c++) res[c] -= deriv(fm2[c], fm1[c], fp1[c], fp2[c], inv);
 }
 
+// Residual and RK update.  Each thread takes kZRows consecutive z-planes of
+// one (i, j) column (z-coarsened point loop), so the z-neighbours a point
+// reads (k-2..k+2) were mostly loaded for the thread's previous plane and hit
+// in cache instead of HBM; the block's 4 wavefronts cover 4 adjacent rows for
+// the y-neighbours.  Same arithmetic as a point-per-thread form.
+constexpr int kZRows = 4;
+
 template <bool kFirst>
-OOC_KERNEL(k_ns_rhs) {
+__global__ void __launch_bounds__(256) k_ns_rhs(const KArgs *__restrict__ ap) {
   ARGS
-  POINT_BEGIN
+  const int n_ = (int)(gridDim.x * gridDim.y * gridDim.z);
+  const int l_ = xcd_block((int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)), n_);
+  const int bx = l_ % (int)gridDim.x, by = (l_ / (int)gridDim.x) % (int)gridDim.y;
+  const int bz = l_ / (int)(gridDim.x * gridDim.y);
+  const int i = a.lo[0] + bx * 64 + (int)threadIdx.x;
+  const int j = a.lo[1] + by * 4 + (int)threadIdx.y;
+  if (i >= a.hi[0] || j >= a.hi[1]) return;
   const double inv = a.c[0], mu = a.c[1], kappa = a.c[2], dt = a.c[3], A = a.c[4], B = a.c[5];
-  double res[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  ns_axis<0>(a, i, j, k, mu, kappa, inv, res);
-  ns_axis<1>(a, i, j, k, mu, kappa, inv, res);
-  ns_axis<2>(a, i, j, k, mu, kappa, inv, res);
+  for (int r = 0; r < kZRows; r++) {
+    const int k = a.lo[2] + bz * kZRows + r;
+    if (k >= a.hi[2]) break;
+    double res[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    ns_axis<0>(a, i, j, k, mu, kappa, inv, res);
+    ns_axis<1>(a, i, j, k, mu, kappa, inv, res);
+    ns_axis<2>(a, i, j, k, mu, kappa, inv, res);
 #pragma unroll
-  for (int c = 0; c < 5; c++) {
-    const double d = kFirst ? dt * res[c] : A * AT(DR + c, 0, 0, 0) + dt * res[c];
-    AT(DR + c, 0, 0, 0) = d;
-    AT(QR + c, 0, 0, 0) = AT(QR + c, 0, 0, 0) + B * d;
+    for (int c = 0; c < 5; c++) {
+      const double d = kFirst ? dt * res[c] : A * AT(DR + c, 0, 0, 0) + dt * res[c];
+      AT(DR + c, 0, 0, 0) = d;
+      AT(QR + c, 0, 0, 0) = AT(QR + c, 0, 0, 0) + B * d;
+    }
   }
-  POINT_END
+}
+
+void launch_zrows(void (*kern)(const KArgs *), const KArgs &a, const KArgs *dev, int ndim, void *s) {
+  const int nx = a.hi[0] - a.lo[0], ny = a.hi[1] - a.lo[1], nz = ndim == 3 ? a.hi[2] - a.lo[2] : 1;
+  if (nx <= 0 || ny <= 0 || nz <= 0) return;
+  const dim3 grid((nx + 63) / 64, (ny + 3) / 4, (nz + kZRows - 1) / kZRows);
+  hipLaunchKernelGGL(kern, grid, dim3(64, 4, 1), 0, (hipStream_t)s, dev);
 }
 
 #define L(name, kern) \
@@ -134,8 +157,8 @@ OOC_KERNEL(k_ns_rhs) {
 L(l_init, k_ns_init)
 L(l_prims, k_ns_prims)
 L(l_grads, k_ns_grads)
-L(l_rhs_first, k_ns_rhs<true>)
-L(l_rhs, k_ns_rhs<false>)
+void l_rhs_first(const KArgs &a, const KArgs *d, int nd, void *s) { launch_zrows(k_ns_rhs<true>, a, d, nd, s); }
+void l_rhs(const KArgs &a, const KArgs *d, int nd, void *s) { launch_zrows(k_ns_rhs<false>, a, d, nd, s); }
 #undef L
 
 }  // namespace
