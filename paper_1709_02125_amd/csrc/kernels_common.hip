@@ -25,11 +25,31 @@ __device__ inline void mirror_point(const KArgs &a, int i, int j, int k) {
   }
 }
 
-OOC_KERNEL(k_mirror) {
+// Strip loops are often a wall layer one or a few points wide in x: their
+// points are numbered x-fastest and handed out 256 per block, so every lane
+// has work whatever the shape of the box (a 64-wide row mapping would leave
+// most lanes of a one-point-wide strip idle).
+__device__ inline void mirror_flat(const KArgs &a, int64_t e) {
+  const int64_t nx = a.hi[0] - a.lo[0], ny = a.hi[1] - a.lo[1];
+  const int64_t t = e / nx;
+  mirror_point(a, a.lo[0] + (int)(e - t * nx), a.lo[1] + (int)(t % ny), a.lo[2] + (int)(t / ny));
+}
+
+inline int64_t box_points(const KArgs &a, int ndim) {
+  const int64_t nx = a.hi[0] - a.lo[0], ny = a.hi[1] - a.lo[1];
+  const int64_t nz = ndim == 3 ? a.hi[2] - a.lo[2] : 1;
+  return nx > 0 && ny > 0 && nz > 0 ? nx * ny * nz : 0;
+}
+
+__global__ void __launch_bounds__(256) k_mirror(const KArgs *__restrict__ ap, int64_t npts) {
   ARGS
-  POINT_BEGIN
-  mirror_point(a, i, j, k);
-  POINT_END
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < npts) mirror_flat(a, e);
+}
+
+static void l_mirror(const KArgs &a, const KArgs *d, int nd, void *s) {
+  const int64_t npts = box_points(a, nd);
+  if (npts) hipLaunchKernelGGL(k_mirror, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, (hipStream_t)s, d, npts);
 }
 
 // Several independent mirror loops of one tile in a single launch: block b
@@ -37,7 +57,7 @@ OOC_KERNEL(k_mirror) {
 // runs exactly the single-loop body there.
 struct MirrorBatch {
   const KArgs *args[32];
-  int32_t gx[32], gy[32];
+  int64_t npts[32];
   int32_t blk0[33];
   int32_t n;
 };
@@ -46,14 +66,8 @@ __global__ void __launch_bounds__(256) k_mirror_batch(MirrorBatch mb) {
   const int b = blockIdx.x;
   int s = 0;
   while (s + 1 < mb.n && b >= mb.blk0[s + 1]) s++;
-  const KArgs &a = *mb.args[s];
-  const int lb = b - mb.blk0[s];
-  const int bx = lb % mb.gx[s], by = (lb / mb.gx[s]) % mb.gy[s], bz = lb / (mb.gx[s] * mb.gy[s]);
-  const int i = a.lo[0] + bx * 64 + (int)threadIdx.x;
-  const int j0 = a.lo[1] + by * kBlockRows + (int)threadIdx.y;
-  const int k = a.lo[2] + bz;
-  if (i >= a.hi[0]) return;
-  for (int r = 0; r < kRowsPerThread && j0 + 4 * r < a.hi[1]; r++) mirror_point(a, i, j0 + 4 * r, k);
+  const int64_t e = (int64_t)(b - mb.blk0[s]) * 256 + threadIdx.x;
+  if (e < mb.npts[s]) mirror_flat(*mb.args[s], e);
 }
 
 void launch_mirror_batch(const KArgs *const *host_args, const KArgs *const *dev_args, int n, int ndim,
@@ -63,15 +77,13 @@ void launch_mirror_batch(const KArgs *const *host_args, const KArgs *const *dev_
     mb.n = n - s0 < 32 ? n - s0 : 32;
     int blocks = 0;
     for (int q = 0; q < mb.n; q++) {
-      dim3 g = point_grid(*host_args[s0 + q], ndim);
       mb.args[q] = dev_args[s0 + q];
-      mb.gx[q] = (int)g.x;
-      mb.gy[q] = (int)g.y;
+      mb.npts[q] = box_points(*host_args[s0 + q], ndim);
       mb.blk0[q] = blocks;
-      blocks += (int)(g.x * g.y * g.z);
+      blocks += (int)((mb.npts[q] + 255) / 256);
     }
     mb.blk0[mb.n] = blocks;
-    if (blocks) hipLaunchKernelGGL(k_mirror_batch, dim3(blocks), dim3(64, 4, 1), 0, (hipStream_t)stream, mb);
+    if (blocks) hipLaunchKernelGGL(k_mirror_batch, dim3(blocks), dim3(256), 0, (hipStream_t)stream, mb);
   }
 }
 
@@ -143,7 +155,6 @@ void launch_rows(void (*k)(const KArgs *), const KArgs &a, const KArgs *dev, int
 
 #define POINT_LAUNCHER(name, kern) \
   static void name(const KArgs &a, const KArgs *d, int nd, void *s) { launch_point(kern, a, d, nd, s); }
-POINT_LAUNCHER(l_mirror, k_mirror)
 POINT_LAUNCHER(l_fill, k_fill_pt)
 POINT_LAUNCHER(l_avg, k_avg)
 POINT_LAUNCHER(l_inc_add, k_inc_add)
