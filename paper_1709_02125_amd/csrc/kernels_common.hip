@@ -290,9 +290,11 @@ struct XferTable {
 };
 constexpr int64_t kXferChunk = 4096;  // elements per block
 
-// A modest grid strides over the chunks: the copy is bound by the host link,
-// and a small grid leaves the compute units to the stencil kernels.
-constexpr int kXferMaxBlocks = 512;
+// A small grid strides over the chunks.  The copy is bound by the host link,
+// and its stores to host memory hold up other kernels' memory requests while
+// they are queued (measured: strip loops on the compute stream ran 30x slower
+// beside a 512-block copy), so only as many blocks run as keep the link busy.
+constexpr int kXferMaxBlocks = 64;
 
 __device__ void xfer_chunk(const XferTable &t, int64_t b) {
   int s = 0;
