@@ -111,37 +111,79 @@ __device__ inline void ns_axis(const KArgs &a, int i, int j, int k, double mu, d
   for (int c = 0; c < 5; c++) res[c] -= deriv(fm2[c], fm1[c], fp1[c], fp2[c], inv);
 }
 
-// Residual and RK update.  Each thread takes kZRows consecutive z-planes of
-// one (i, j) column (z-coarsened point loop), so the z-neighbours a point
-// reads (k-2..k+2) were mostly loaded for the thread's previous plane and hit
-// in cache instead of HBM; the block's 4 wavefronts cover 4 adjacent rows for
-// the y-neighbours.  Same arithmetic as a point-per-thread form.
+// Residual and RK update.  A block of 64 x 4 threads owns a 64 x 4 (x, y)
+// patch and walks kZRows consecutive z-planes.  Per plane, the x- and
+// y-fluxes of every point the patch's differences need (the patch plus two
+// columns / rows of halo each side) are evaluated once and staged in LDS, so
+// the 4-point differences along x and y read LDS instead of re-evaluating
+// neighbours' fluxes; the z-fluxes at k-2..k+2 are evaluated per point, their
+// inputs mostly still in cache from the previous plane.  Each flux is the
+// same function of the same inputs wherever it is evaluated, and the
+// differences are taken in the same order (x, y, then z, subtracted from
+// zero), so results equal a point-by-point evaluation exactly.
 constexpr int kZRows = 4;
 
 template <bool kFirst>
 __global__ void __launch_bounds__(256) k_ns_rhs(const KArgs *__restrict__ ap) {
   ARGS
+  __shared__ double sfx[5][4][68];  // x-flux, x = i0-2 .. i0+65, the patch's 4 rows
+  __shared__ double sfy[5][8][64];  // y-flux, y = j0-2 .. j0+5, the patch's 64 columns
   const int n_ = (int)(gridDim.x * gridDim.y * gridDim.z);
   const int l_ = xcd_block((int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)), n_);
   const int bx = l_ % (int)gridDim.x, by = (l_ / (int)gridDim.x) % (int)gridDim.y;
   const int bz = l_ / (int)(gridDim.x * gridDim.y);
-  const int i = a.lo[0] + bx * 64 + (int)threadIdx.x;
-  const int j = a.lo[1] + by * 4 + (int)threadIdx.y;
-  if (i >= a.hi[0] || j >= a.hi[1]) return;
+  const int tx = (int)threadIdx.x, ty = (int)threadIdx.y;
+  const int i0 = a.lo[0] + bx * 64, j0 = a.lo[1] + by * 4;
+  const int i = i0 + tx, j = j0 + ty;
+  const bool xin = i < a.hi[0], yin = j < a.hi[1];
+  // a flux is needed up to two points past the last point of the range
+  const int xend = a.hi[0] + 2, yend = a.hi[1] + 2;
+  // halo slots of this thread: x-halo column (tx < 4) and y-halo row (ty < 4)
+  const int hm = tx < 2 ? tx : 64 + tx, hx = i0 - 2 + hm;
+  const int hn = ty < 2 ? ty : 4 + ty, hy = j0 - 2 + hn;
   const double inv = a.c[0], mu = a.c[1], kappa = a.c[2], dt = a.c[3], A = a.c[4], B = a.c[5];
   for (int r = 0; r < kZRows; r++) {
     const int k = a.lo[2] + bz * kZRows + r;
-    if (k >= a.hi[2]) break;
-    double res[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    ns_axis<0>(a, i, j, k, mu, kappa, inv, res);
-    ns_axis<1>(a, i, j, k, mu, kappa, inv, res);
-    ns_axis<2>(a, i, j, k, mu, kappa, inv, res);
+    if (k >= a.hi[2]) break;  // the same for the whole block
+    double f[5];
+    if (yin && i < xend) {
+      ns_flux<0>(a, i, j, k, 0, 0, 0, mu, kappa, f);
 #pragma unroll
-    for (int c = 0; c < 5; c++) {
-      const double d = kFirst ? dt * res[c] : A * AT(DR + c, 0, 0, 0) + dt * res[c];
-      AT(DR + c, 0, 0, 0) = d;
-      AT(QR + c, 0, 0, 0) = AT(QR + c, 0, 0, 0) + B * d;
+      for (int c = 0; c < 5; c++) sfx[c][ty][tx + 2] = f[c];
     }
+    if (xin && j < yend) {
+      ns_flux<1>(a, i, j, k, 0, 0, 0, mu, kappa, f);
+#pragma unroll
+      for (int c = 0; c < 5; c++) sfy[c][ty + 2][tx] = f[c];
+    }
+    if (tx < 4 && yin && hx < xend) {
+      ns_flux<0>(a, hx, j, k, 0, 0, 0, mu, kappa, f);
+#pragma unroll
+      for (int c = 0; c < 5; c++) sfx[c][ty][hm] = f[c];
+    }
+    if (ty < 4 && xin && hy < yend) {
+      ns_flux<1>(a, i, hy, k, 0, 0, 0, mu, kappa, f);
+#pragma unroll
+      for (int c = 0; c < 5; c++) sfy[c][hn][tx] = f[c];
+    }
+    __syncthreads();
+    if (xin && yin) {
+      double res[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int c = 0; c < 5; c++)
+        res[c] -= deriv(sfx[c][ty][tx], sfx[c][ty][tx + 1], sfx[c][ty][tx + 3], sfx[c][ty][tx + 4], inv);
+#pragma unroll
+      for (int c = 0; c < 5; c++)
+        res[c] -= deriv(sfy[c][ty][tx], sfy[c][ty + 1][tx], sfy[c][ty + 3][tx], sfy[c][ty + 4][tx], inv);
+      ns_axis<2>(a, i, j, k, mu, kappa, inv, res);
+#pragma unroll
+      for (int c = 0; c < 5; c++) {
+        const double d = kFirst ? dt * res[c] : A * AT(DR + c, 0, 0, 0) + dt * res[c];
+        AT(DR + c, 0, 0, 0) = d;
+        AT(QR + c, 0, 0, 0) = AT(QR + c, 0, 0, 0) + B * d;
+      }
+    }
+    __syncthreads();  // the next plane overwrites the staged fluxes
   }
 }
 
