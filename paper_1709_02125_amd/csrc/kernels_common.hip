@@ -148,6 +148,12 @@ void launch_point(void (*k)(const KArgs *), const KArgs &a, const KArgs *dev, in
   if (grid.x && grid.y && grid.z) hipLaunchKernelGGL(k, grid, dim3(64, 4, 1), 0, (hipStream_t)s, dev);
 }
 
+void launch_point_z(void (*k)(const KArgs *), const KArgs &a, const KArgs *dev, int ndim, void *s) {
+  if (ndim != 3) return launch_point(k, a, dev, ndim, s);
+  dim3 grid = point_grid_z(a);
+  if (grid.x && grid.y && grid.z) hipLaunchKernelGGL(k, grid, dim3(64, 4, 1), 0, (hipStream_t)s, dev);
+}
+
 void launch_rows(void (*k)(const KArgs *), const KArgs &a, const KArgs *dev, int ndim, void *s) {
   dim3 grid(1, a.hi[1] - a.lo[1], ndim == 3 ? a.hi[2] - a.lo[2] : 1);
   if (grid.y && grid.z && a.hi[0] > a.lo[0]) hipLaunchKernelGGL(k, grid, dim3(256, 1, 1), 0, (hipStream_t)s, dev);

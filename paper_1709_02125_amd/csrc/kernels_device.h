@@ -49,9 +49,31 @@ __device__ __forceinline__ int xcd_block(int pid, int n) {
   }               \
   }
 
+// The same point loop walking kRowsPerThread consecutive z-planes instead of
+// rows (for stencils that reach along z: a thread's z-neighbours were mostly
+// loaded for its previous plane); launched with point_grid_z.
+#define POINT_BEGIN_Z                                                                      \
+  {                                                                                        \
+    const int n_ = (int)(gridDim.x * gridDim.y * gridDim.z);                               \
+    const int l_ = xcd_block((int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)), n_); \
+    const int bx_ = l_ % (int)gridDim.x, by_ = (l_ / (int)gridDim.x) % (int)gridDim.y;      \
+    const int i = a.lo[0] + bx_ * 64 + (int)threadIdx.x;                                   \
+    const int j = a.lo[1] + by_ * 4 + (int)threadIdx.y;                                    \
+    const int k0_ = a.lo[2] + (l_ / (int)(gridDim.x * gridDim.y)) * kRowsPerThread;         \
+    if (i < a.hi[0] && j < a.hi[1])                                                        \
+      for (int r_ = 0; r_ < kRowsPerThread; r_++) {                                        \
+        const int k = k0_ + r_;                                                            \
+        if (k >= a.hi[2]) break;
+
 // element (i+di, j+dj, k+dk) of DAT argument n
 #define AT(n, di, dj, dk) \
   a.p[n][(int64_t)(k + (dk)) * a.plane + (int64_t)(j + (dj)) * a.pitch + (i + (di))]
+
+inline dim3 point_grid_z(const KArgs &a) {
+  const int nx = a.hi[0] - a.lo[0], ny = a.hi[1] - a.lo[1], nz = a.hi[2] - a.lo[2];
+  if (nx <= 0 || ny <= 0 || nz <= 0) return dim3(0, 0, 0);
+  return dim3((nx + 63) / 64, (ny + 3) / 4, (nz + kRowsPerThread - 1) / kRowsPerThread);
+}
 
 inline dim3 point_grid(const KArgs &a, int ndim) {
   const int nx = a.hi[0] - a.lo[0], ny = a.hi[1] - a.lo[1];
@@ -123,6 +145,7 @@ __device__ inline double block_sum_fixed(double v) {
 }
 
 void launch_point(void (*k)(const KArgs *), const KArgs &a, const KArgs *dev, int ndim, void *s);
+void launch_point_z(void (*k)(const KArgs *), const KArgs &a, const KArgs *dev, int ndim, void *s);
 void launch_rows(void (*k)(const KArgs *), const KArgs &a, const KArgs *dev, int ndim, void *s);
 
 }  // namespace ooc

@@ -54,7 +54,7 @@ OOC_KERNEL(k_ns_prims) {
 
 OOC_KERNEL(k_ns_grads) {
   ARGS
-  POINT_BEGIN
+  POINT_BEGIN_Z
   const double inv = a.c[0], gm2 = a.c[1];
 #pragma unroll
   for (int c = 0; c < 3; c++) {
@@ -198,7 +198,7 @@ void launch_zrows(void (*kern)(const KArgs *), const KArgs &a, const KArgs *dev,
   void name(const KArgs &a, const KArgs *d, int nd, void *s) { launch_point(kern, a, d, nd, s); }
 L(l_init, k_ns_init)
 L(l_prims, k_ns_prims)
-L(l_grads, k_ns_grads)
+void l_grads(const KArgs &a, const KArgs *d, int nd, void *s) { launch_point_z(k_ns_grads, a, d, nd, s); }
 void l_rhs_first(const KArgs &a, const KArgs *d, int nd, void *s) { launch_zrows(k_ns_rhs<true>, a, d, nd, s); }
 void l_rhs(const KArgs &a, const KArgs *d, int nd, void *s) { launch_zrows(k_ns_rhs<false>, a, d, nd, s); }
 #undef L
