@@ -187,8 +187,10 @@ class NS3DWork(Workload):
     def variants(self):
         from paper_1709_02125_amd import ooc
         pf = ooc.FLAG_PREFETCH
-        return [("chain_steps_1", pf, {"chain_steps": 1}), ("chain_steps_3", pf, {"chain_steps": 3}),
-                ("fp32_stream", pf | ooc.FLAG_FP32_STREAM, {})]
+        return [("default_schedule_1_step_chains", pf, {"chain_steps": 1, "tile_rows": 0, "slots": 3}),
+                ("chains_of_2_steps_largest_tiles", pf, {"chain_steps": 2, "tile_rows": 0, "slots": 3}),
+                ("fp32_stream_swept_schedule", pf | ooc.FLAG_FP32_STREAM,
+                 {"chain_steps": 2, "tile_rows": 32, "slots": 2})]
 
     def describe(self):
         return ("ns3d proxy %d^3 FP64 (Taylor-Green, Mach 0.1), 27 fields, 45 loops per step, chains of %d "
@@ -337,9 +339,9 @@ def main():
     ap.add_argument("--no-cyclic", action="store_true")
     ap.add_argument("--no-incore", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--slots", type=int, default=0)
-    ap.add_argument("--tile-rows", type=int, default=0)
-    ap.add_argument("--chain-steps", type=int, default=2, help="ns3d: time steps per chain")
+    ap.add_argument("--slots", type=int, default=None, help="slot count (default 3; ns3d: 2)")
+    ap.add_argument("--tile-rows", type=int, default=None, help="tile height (default: largest that fits; ns3d: 24)")
+    ap.add_argument("--chain-steps", type=int, default=3, help="ns3d: time steps per chain")
     ap.add_argument("--no-variants", action="store_true", help="skip the other schedules of the same grid")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a plain 1 GiB device copy (counter calibration under rocprofv3)")
@@ -350,6 +352,14 @@ def main():
         sys.exit(2)
     if args.steps is None:
         args.steps = 20 if args.workload == "hydro2d" else 10
+    # ns3d runs the schedule the exhaustive sweep of this grid and budget found
+    # fastest (tile 24 planes, chains of 3 steps, 2 slots; the cost model's
+    # pick as well); the hydro proxies default to the largest tile and 3 slots
+    ns = args.workload == "ns3d"
+    if args.slots is None:
+        args.slots = 2 if ns else 0
+    if args.tile_rows is None:
+        args.tile_rows = 24 if ns else 0
 
     import torch
     from paper_1709_02125_amd import ooc
