@@ -286,9 +286,13 @@ def committed_traffic(kernel, workload):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_1709_02125_amd", "csrc", kv.get("source", ""))
-    if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != kv.get("source_sha1"):
-        return None
+    for key, hkey in (("source", "source_sha1"), ("point_loop_source", "point_loop_sha1")):
+        if key not in kv:
+            continue
+        src = os.path.join(ROOT, "paper_1709_02125_amd", "csrc", kv[key])
+        want = kv.get(hkey)
+        if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != want:
+            return None
     return float(kv["hbm_bytes_per_launch"])
 
 

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from paper_1709_02125_amd import ooc
-import mlp_ref
+import oracle.mlp as mlp_ref
 from gpu_util import say
 
 pytestmark = pytest.mark.gpu
@@ -46,4 +46,22 @@ def test_mlp_training_reduces_loss():
     _, l0 = m.gradient(X, y)
     l1 = m.train(X, y, epochs=2000, lr=3e-3)
     assert l1 < 0.05 * l0, (l0, l1)
+    m.close()
+
+
+def test_mlp_adam_training_matches_oracle():
+    # the device's full-batch Adam epochs against the oracle's, from the same
+    # starting parameters
+    D, H, N = 12, 32, 64
+    say("case: mlp adam vs oracle")
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((N, D))
+    y = rng.standard_normal(N)
+    m = ooc.Mlp(D, H, seed=13)
+    p0 = m.params()
+    l_dev = m.train(X, y, epochs=50, lr=1e-3)
+    p_dev = m.params()
+    p_ref, l_ref = mlp_ref.adam_train(p0, X, y, D, H, 50, 1e-3)
+    assert np.abs(p_dev - p_ref).max() <= 1e-9 * np.abs(p_ref).max()
+    assert abs(l_dev - l_ref) <= 1e-9 * l_ref
     m.close()
