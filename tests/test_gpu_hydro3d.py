@@ -62,3 +62,23 @@ def test_hydro3d_resident_geometry_bit_exact():
     assert st["ntiles_last"] >= 2
     for name in STATE3:
         assert np.array_equal(got[name], ref[name]), name
+
+
+def test_hydro3d_fp32_streaming_error_is_stated_and_tiling_independent():
+    # streamed fields stored and moved as float32; compute, dt and sums stay
+    # float64; every persistent row is rounded once per chain whatever the tiles
+    n, steps = (24, 20, 60), 5
+    say("case: hydro3d fp32 streaming")
+    flags = ooc.FLAG_FP32_STREAM | ooc.FLAG_PREFETCH
+    a, adts, st, _ = gpu_hydro3d(n, steps, flags=flags, resident_geometry=True, budget=h3.footprint_bytes(n) // 2)
+    b, bdts, _, _ = gpu_hydro3d(n, steps, flags=flags, resident_geometry=True, tile_rows=5, slots=4,
+                                budget=h3.footprint_bytes(n))
+    assert st["ntiles_last"] > 2
+    for name in STATE3:
+        assert np.array_equal(a[name], b[name]), name
+    assert adts == bdts
+    ref, _, _ = oracle_hydro3d(n, steps)
+    errs = {name: rel_err(a[name], ref[name]) for name in STATE3 if np.abs(ref[name]).max() > 0}
+    say("fp32 streaming max rel error after %d steps:" % steps, errs)
+    for name, e in errs.items():
+        assert e < 1e-4, (name, e)
