@@ -84,12 +84,12 @@ class Hydro2DWork(Workload):
                 "(footprint %.3g B, %.2fx oversubscribed), tiles along y" %
                 (self.n, self.n, self.budget, self.footprint, self.footprint / self.budget))
 
-    def cpu_baseline(self, target_s=12.0):
+    def cpu_baseline(self, target_s=15.0):
         import oracle
         import oracle.hydro2d as oh
         from paper_1709_02125_amd.inputs import hydro_initial_state
         oracle.build(force=False)
-        nx, ny = self.n, 1024
+        nx, ny = self.n, max(64, self.n // 2)
         rho, ene = hydro_initial_state((nx, ny))
         o = oh.Hydro2D(nx, ny)
         o.set_state(rho, ene)
@@ -140,12 +140,12 @@ class Hydro3DWork(Workload):
                 "(footprint %.3g B, %.2fx oversubscribed), tiles along z" %
                 (self.n, self.budget, self.footprint, self.footprint / self.budget))
 
-    def cpu_baseline(self, target_s=12.0):
+    def cpu_baseline(self, target_s=15.0):
         import oracle
         import oracle.hydro3d as oh
         from paper_1709_02125_amd.inputs import hydro_initial_state
         oracle.build(force=False)
-        dims = (self.n, self.n, 8)
+        dims = (self.n, self.n, max(8, self.n // 12))
         rho, ene = hydro_initial_state(dims)
         o = oh.Hydro3D(*dims)
         o.set_state(rho, ene)
@@ -197,12 +197,12 @@ class NS3DWork(Workload):
                 "steps, device budget %.3g B (footprint %.3g B, %.2fx oversubscribed), tiles along z" %
                 (self.n, self.args.chain_steps, self.budget, self.footprint, self.footprint / self.budget))
 
-    def cpu_baseline(self, target_s=12.0):
+    def cpu_baseline(self, target_s=15.0):
         import oracle
         import oracle.ns3d as on
         from paper_1709_02125_amd.inputs import tgv_initial_state
         oracle.build(force=False)
-        n = 128
+        n = max(16, self.n // 2)
         o = on.NS3D(n)
         o.set_primitives(*tgv_initial_state(n))
         dt = on.stable_dt(n)
