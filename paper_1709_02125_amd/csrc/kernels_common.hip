@@ -296,11 +296,29 @@ struct XferTable {
 };
 constexpr int64_t kXferChunk = 4096;  // elements per block
 
-// A small grid strides over the chunks.  The copy is bound by the host link,
-// and its stores to host memory hold up other kernels' memory requests while
-// they are queued (measured: strip loops on the compute stream ran 30x slower
-// beside a 512-block copy), so only as many blocks run as keep the link busy.
-constexpr int kXferMaxBlocks = 64;
+// A small grid strides over the chunks.  The copy is bound by the host link.
+// Its stores to host memory hold up other kernels' memory requests while they
+// sit in the queues towards the link (measured: a strip loop beside a
+// 64-block device-to-host copy took 0.6 ms instead of 8 us), so the writing
+// direction runs only a few wavefronts, each with several loads in flight
+// before its stores; the reading direction needs more wavefronts to cover
+// the link's read latency.
+constexpr int kXferWriteBlocks = 8;
+constexpr int kXferReadBlocks = 64;
+constexpr int kXferUnroll = 4;
+
+template <class S, class D, class F>
+__device__ __forceinline__ void xfer_range(const S *src, D *dst, int64_t e0, int64_t end, F conv) {
+  for (int64_t e = e0 + threadIdx.x; e < end; e += kXferUnroll * 256) {
+    S v[kXferUnroll];
+#pragma unroll
+    for (int u = 0; u < kXferUnroll; u++)
+      if (e + u * 256 < end) v[u] = src[e + u * 256];
+#pragma unroll
+    for (int u = 0; u < kXferUnroll; u++)
+      if (e + u * 256 < end) dst[e + u * 256] = conv(v[u]);
+  }
+}
 
 __device__ void xfer_chunk(const XferTable &t, int64_t b) {
   int s = 0;
@@ -308,23 +326,13 @@ __device__ void xfer_chunk(const XferTable &t, int64_t b) {
   const int64_t base = (b - t.blk0[s]) * kXferChunk;
   const int64_t end = base + kXferChunk < t.n[s] ? base + kXferChunk : t.n[s];
   if (t.mode[s] == 0) {
-    const double2 *src = (const double2 *)t.src[s];
-    double2 *dst = (double2 *)t.dst[s];
-    for (int64_t e = base + threadIdx.x; e < end; e += 256) dst[e] = src[e];
+    xfer_range((const double2 *)t.src[s], (double2 *)t.dst[s], base, end, [](double2 v) { return v; });
   } else if (t.mode[s] == 1) {  // float32 -> float64, 2 elements per lane step
-    const float2 *src = (const float2 *)t.src[s];
-    double2 *dst = (double2 *)t.dst[s];
-    for (int64_t e = base / 2 + threadIdx.x; e < end / 2; e += 256) {
-      const float2 v = src[e];
-      dst[e] = make_double2((double)v.x, (double)v.y);
-    }
+    xfer_range((const float2 *)t.src[s], (double2 *)t.dst[s], base / 2, end / 2,
+               [](float2 v) { return make_double2((double)v.x, (double)v.y); });
   } else {  // float64 -> float32 (round to nearest even)
-    const double2 *src = (const double2 *)t.src[s];
-    float2 *dst = (float2 *)t.dst[s];
-    for (int64_t e = base / 2 + threadIdx.x; e < end / 2; e += 256) {
-      const double2 v = src[e];
-      dst[e] = make_float2((float)v.x, (float)v.y);
-    }
+    xfer_range((const double2 *)t.src[s], (float2 *)t.dst[s], base / 2, end / 2,
+               [](double2 v) { return make_float2((float)v.x, (float)v.y); });
   }
 }
 
@@ -332,7 +340,7 @@ __global__ void __launch_bounds__(256) k_xfer(XferTable t) {
   for (int64_t b = blockIdx.x; b < t.blk0[t.nseg]; b += gridDim.x) xfer_chunk(t, b);
 }
 
-void launch_xfer_segments(const XferSeg *segs, int nseg, void *stream) {
+void launch_xfer_segments(const XferSeg *segs, int nseg, bool to_host, void *stream) {
   for (int s0 = 0; s0 < nseg; s0 += 32) {
     XferTable t{};
     t.nseg = nseg - s0 < 32 ? nseg - s0 : 32;
@@ -347,7 +355,8 @@ void launch_xfer_segments(const XferSeg *segs, int nseg, void *stream) {
       blocks += (g.n + kXferChunk - 1) / kXferChunk;
     }
     t.blk0[t.nseg] = blocks;
-    const int64_t grid = blocks < kXferMaxBlocks ? blocks : kXferMaxBlocks;
+    const int64_t cap = to_host ? kXferWriteBlocks : kXferReadBlocks;
+    const int64_t grid = blocks < cap ? blocks : cap;
     if (blocks) hipLaunchKernelGGL(k_xfer, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, t);
   }
 }

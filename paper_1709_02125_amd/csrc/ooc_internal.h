@@ -75,7 +75,8 @@ struct XferSeg {
   int64_t n;
   int mode;
 };
-void launch_xfer_segments(const XferSeg *segs, int nseg, void *stream);
+// to_host: the copy writes host memory (device-to-host), which takes a smaller grid
+void launch_xfer_segments(const XferSeg *segs, int nseg, bool to_host, void *stream);
 void launch_red_init(double *acc, double value, void *stream);
 void launch_red_commit(const double *acc, double *committed, void *stream);
 void launch_sum_finalize(const double *partials, int64_t n, double *committed, void *stream);

@@ -671,7 +671,7 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       }
     }
     if (!xup.empty()) {
-      timed_call(c, [&] { launch_xfer_segments(xup.data(), (int)xup.size(), c->s_up); }, kCallH2D);
+      timed_call(c, [&] { launch_xfer_segments(xup.data(), (int)xup.size(), false, c->s_up); }, kCallH2D);
       HIPCHK(hipGetLastError());
     }
     timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_up, c, g), c->s_up)); }, kCallRecord);
@@ -767,7 +767,7 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       }
     }
     if (!xdown.empty()) {
-      timed_call(c, [&] { launch_xfer_segments(xdown.data(), (int)xdown.size(), c->s_down); }, kCallD2H);
+      timed_call(c, [&] { launch_xfer_segments(xdown.data(), (int)xdown.size(), true, c->s_down); }, kCallD2H);
       HIPCHK(hipGetLastError());
     }
     timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_down, c, g), c->s_down)); }, kCallRecord);
