@@ -1,9 +1,10 @@
 // 3D hydro proxy kernels (FP64, gfx950): the three-dimensional form of the 2D
 // proxy -- 8-node cell stencils and 8-cell node stencils, donor-cell remap
 // sweeps x, y, z -- as the paper names CloverLeaf 3D (Section 5.1).  One kernel
-// per loop over the point loop of kernels_device.h (one wavefront per 64
-// consecutive x of a row, 4 rows per thread, one grid layer per z-plane).
-// HBM-bound, no MFMA.
+// per loop over the z-walking point loop of kernels_device.h (one wavefront
+// per 64 consecutive x of a row, the block's 4 wavefronts on 4 adjacent rows,
+// each thread walking 4 consecutive z-planes, so both the j+1 and the k+1
+// stencil reads mostly hit in cache).  HBM-bound, no MFMA.
 // Expression order follows the plain program exactly (built without FP
 // contraction), so tiled and untiled runs are bit-identical.
 //
@@ -53,7 +54,7 @@ __device__ __forceinline__ double jump(const KArgs &a, int n, int i, int j, int 
 // args: R rho0, R cs, R u0, R v0, R w0, W q
 OOC_KERNEL(k_visc) {
   ARGS
-  POINT_BEGIN
+  POINT_BEGIN_Z
   const double d = (jump<0>(a, 2, i, j, k) + jump<1>(a, 3, i, j, k)) + jump<2>(a, 4, i, j, k);
   double q = 0.0;
   if (d < 0.0) q = AT(0, 0, 0, 0) * ((kCq2 * d) * d - (kCq1 * AT(1, 0, 0, 0)) * d);
@@ -76,7 +77,7 @@ __device__ __forceinline__ double pdv_df(const KArgs &a, int i, int j, int k, do
 template <bool kCorr>
 OOC_KERNEL(k_pdv) {
   ARGS
-  POINT_BEGIN
+  POINT_BEGIN_Z
   const double fac = 0.125 * a.ds[0][0];
   const double total = (pdv_df<kCorr, 0>(a, i, j, k, fac) + pdv_df<kCorr, 1>(a, i, j, k, fac)) +
                        pdv_df<kCorr, 2>(a, i, j, k, fac);
@@ -95,7 +96,7 @@ OOC_KERNEL(k_pdv) {
 // w1; CONST nx, ny, nz; DEVSCALAR dt
 OOC_KERNEL(k_accel) {
   ARGS
-  POINT_BEGIN
+  POINT_BEGIN_Z
   double P[2][2][2], M[2][2][2];
 #pragma unroll
   for (int c = 0; c < 2; c++)
@@ -131,7 +132,7 @@ OOC_KERNEL(k_accel) {
 template <int D>
 OOC_KERNEL(k_flux) {
   ARGS
-  POINT_BEGIN
+  POINT_BEGIN_Z
   const double fac = 0.125 * a.ds[0][0];
   AT(3, 0, 0, 0) = (fac * AT(0, 0, 0, 0)) * face4_2<D>(a, 1, 2, i, j, k, 0);
   POINT_END
@@ -146,7 +147,7 @@ __device__ __forceinline__ double dflux(const KArgs &a, int n, int i, int j, int
 // volumes before / after the x sweep.  args: R vol, R vfx, R vfy, R vfz, W pre, W post
 OOC_KERNEL(k_adv_vol_x) {
   ARGS
-  POINT_BEGIN
+  POINT_BEGIN_Z
   const double dfx = dflux<0>(a, 1, i, j, k);
   const double pre = AT(0, 0, 0, 0) + ((dfx + dflux<1>(a, 2, i, j, k)) + dflux<2>(a, 3, i, j, k));
   AT(4, 0, 0, 0) = pre;
@@ -157,7 +158,7 @@ OOC_KERNEL(k_adv_vol_x) {
 // y sweep.  args: R vol, R vfy, R vfz, W pre, W post
 OOC_KERNEL(k_adv_vol_y) {
   ARGS
-  POINT_BEGIN
+  POINT_BEGIN_Z
   const double vol = AT(0, 0, 0, 0);
   const double dfz = dflux<2>(a, 2, i, j, k);
   AT(3, 0, 0, 0) = vol + (dflux<1>(a, 1, i, j, k) + dfz);
@@ -168,7 +169,7 @@ OOC_KERNEL(k_adv_vol_y) {
 // z sweep.  args: R vol, R vfz, W pre, W post
 OOC_KERNEL(k_adv_vol_z) {
   ARGS
-  POINT_BEGIN
+  POINT_BEGIN_Z
   const double vol = AT(0, 0, 0, 0);
   AT(2, 0, 0, 0) = vol + dflux<2>(a, 1, i, j, k);
   AT(3, 0, 0, 0) = vol;
@@ -180,7 +181,7 @@ OOC_KERNEL(k_adv_vol_z) {
 template <int D>
 OOC_KERNEL(k_adv_flux) {
   ARGS
-  POINT_BEGIN
+  POINT_BEGIN_Z
   constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
   const double f = AT(0, 0, 0, 0);
   double mf = 0.0, ef = 0.0;
@@ -200,7 +201,7 @@ OOC_KERNEL(k_adv_flux) {
 template <int D>
 OOC_KERNEL(k_adv_cell) {
   ARGS
-  POINT_BEGIN
+  POINT_BEGIN_Z
   constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
   const double pm = AT(0, 0, 0, 0) * AT(2, 0, 0, 0);
   const double post = pm + (AT(4, 0, 0, 0) - AT(4, ex, ey, ez));
@@ -216,7 +217,7 @@ OOC_KERNEL(k_adv_cell) {
 template <int D>
 OOC_KERNEL(k_nflux) {
   ARGS
-  POINT_BEGIN
+  POINT_BEGIN_Z
   constexpr int B = D == 0 ? 1 : 0, C = D == 2 ? 1 : 2;
   double t[2];
 #pragma unroll
@@ -243,7 +244,7 @@ OOC_KERNEL(k_nflux) {
 template <int D>
 OOC_KERNEL(k_nmass) {
   ARGS
-  POINT_BEGIN
+  POINT_BEGIN_Z
   constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
 #define CM(x, y, z) (AT(0, (x) - 1, (y) - 1, (z) - 1) * AT(1, (x) - 1, (y) - 1, (z) - 1))
   const double post = 0.125 * (((CM(0, 0, 0) + CM(1, 0, 0)) + (CM(0, 1, 0) + CM(1, 1, 0))) +
@@ -259,7 +260,7 @@ OOC_KERNEL(k_nmass) {
 template <int D>
 OOC_KERNEL(k_mflux) {
   ARGS
-  POINT_BEGIN
+  POINT_BEGIN_Z
   constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
   const double f = AT(0, 0, 0, 0);
   double mf = 0.0;
@@ -273,7 +274,7 @@ OOC_KERNEL(k_mflux) {
 template <int D>
 OOC_KERNEL(k_vel) {
   ARGS
-  POINT_BEGIN
+  POINT_BEGIN_Z
   constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
   AT(0, 0, 0, 0) = (AT(0, 0, 0, 0) * AT(1, 0, 0, 0) + (AT(3, -ex, -ey, -ez) - AT(3, 0, 0, 0))) / AT(2, 0, 0, 0);
   POINT_END
@@ -292,7 +293,7 @@ __device__ __forceinline__ double absmax8(const KArgs &a, int n, int i, int j, i
 OOC_KERNEL(k_dt) {
   ARGS
   double t = INFINITY;  // smallest bound over this thread's points
-  POINT_BEGIN
+  POINT_BEGIN_Z
   {
     const double c2 = (kGamma * kGm1) * AT(0, 0, 0, 0);
     const double d = (jump<0>(a, 1, i, j, k) + jump<1>(a, 2, i, j, k)) + jump<2>(a, 3, i, j, k);
@@ -310,7 +311,7 @@ OOC_KERNEL(k_dt) {
 }
 
 #define L(name, kern) \
-  void name(const KArgs &a, const KArgs *d, int nd, void *s) { launch_point(kern, a, d, nd, s); }
+  void name(const KArgs &a, const KArgs *d, int nd, void *s) { launch_point_z(kern, a, d, nd, s); }
 L(l_visc, k_visc)
 L(l_pdv_pred, k_pdv<false>)
 L(l_pdv_corr, k_pdv<true>)
