@@ -351,7 +351,7 @@ def main():
                     help="end with a plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build's path runs on a single MI355X "
+        print("bench.py measures one GPU: the pipeline runs on a single MI355X "
               "(the multi-GPU sharding is a design note only); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.steps is None:

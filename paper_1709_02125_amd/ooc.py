@@ -70,12 +70,12 @@ _lib = None
 
 
 def load_library() -> ctypes.CDLL:
-    """Load the in-tree libooc.so (built by __graft_entry__.build())."""
+    """Load the in-tree libooc.so (built by python -m paper_1709_02125_amd.build)."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libooc.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        raise ImportError("libooc.so is not built (%s); run python -m paper_1709_02125_amd.build" % LIB_PATH)
     # PyTorch-ROCm ships its own HIP runtime with the same soname as the system
     # one; load torch first so the library binds to that single runtime instead
     # of bringing a second HIP/HSA runtime into the process.

@@ -7,7 +7,7 @@ a plan-only context.  `sweep` is the exhaustive autotuner: it measures every
 feasible schedule on the device.  `CostModel` wraps the library's
 device-trained MLP (ooc_mlp_*): it learns log(seconds per cell-step) from the
 sweep's records and proposes the schedule with the lowest prediction; the
-exhaustive sweep is its fallback and the judge of its regret."""
+exhaustive sweep is its fallback and the yardstick of its regret."""
 from __future__ import annotations
 
 import math
@@ -208,7 +208,7 @@ def main():
     ap.add_argument("--ss", default="2,3,4")
     ap.add_argument("--chains", type=int, default=2)
     ap.add_argument("--fp32", action="store_true")
-    ap.add_argument("--out", default="gpurun_out/tune_records.json")
+    ap.add_argument("--out", default="tune_records.json")
     a = ap.parse_args()
     flags = ooc.FLAG_FP32_STREAM if a.fp32 else 0
     log = lambda *x: print(*x, file=sys.stderr, flush=True)

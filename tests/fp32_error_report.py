@@ -5,7 +5,7 @@ same seeded input, after 20 steps; per-field max relative error (max |g - o| /
 max |o| over the interior) printed as one JSON line.
 
 Not collected by pytest (a one-off measurement at the benchmark sizes, minutes
-of CPU time for the oracle).  On a GPU machine:
+of CPU time for the oracle).  On an MI355X:
     python tests/fp32_error_report.py --hydro2d   # 15360^2, budget 16e9 B
     python tests/fp32_error_report.py --ns3d      # 512^3, budget 1/3 of the fields
 """
