@@ -197,6 +197,15 @@ int ooc_set_schedule(ooc_ctx *ctx, int64_t tile_rows, int chain_steps, int slots
 
 int ooc_get_stats(ooc_ctx *ctx, ooc_stats *out);
 
+/* Storage layout shared by every field of the context (host and device
+ * copies alike): element (i, j, k) of a field (logical indices, the field's
+ * lower bound being -halo on every axis) lies at
+ * (k + halo) * plane + (j + halo) * pitch + (i + x_origin) elements from the
+ * start of its storage; in 2D the k term is absent and plane is 0.  x_origin
+ * (16) puts x = 0 on a 128-byte boundary of every row.  Returns OOC_E_ARG on a
+ * null pointer. */
+int ooc_get_layout(ooc_ctx *ctx, int64_t *pitch, int64_t *plane, int64_t *x_origin);
+
 /* Enable per-launch timing with hipEvents (adds a little overhead); read the
  * summed kernel time of the last flush from ooc_stats.last_kernel_ms.
  * on = 1 times every loop launch; on = 2 + k times only launches of kernel
@@ -233,8 +242,8 @@ typedef struct {
 
 int ooc_debug_plan(ooc_ctx *ctx, ooc_plan_info *out);
 
-/* Field geometry: logical lower bound, extent per axis and the row pitch (in
- * elements) of the library's layout. */
+/* Field geometry: logical lower bound and extent per axis (the storage
+ * layout is given by ooc_get_layout). */
 int ooc_field_shape(ooc_ctx *ctx, ooc_field f, int64_t lo[3], int64_t n[3]);
 
 /* ------------------------------------------------------- schedule cost model
@@ -242,7 +251,7 @@ int ooc_field_shape(ooc_ctx *ctx, ooc_field f, int64_t lo[3], int64_t n[3]);
  * mean-squared-error loss) trained on the device by the library's own forward,
  * backward and Adam kernels.  It learns log time per cell-step of a schedule
  * (tile height, chain length, buffer depth) from features of the plan, and
- * proposes schedules; the exhaustive sweep is its fallback and judge.  This is
+ * proposes schedules; the exhaustive sweep is its fallback and yardstick.  This is
  * an extension, not part of the paper.  X is row-major N x n_inputs (host);
  * all buffers are the caller's and copied. */
 typedef struct ooc_mlp ooc_mlp;

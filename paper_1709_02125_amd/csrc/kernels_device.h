@@ -25,6 +25,15 @@ namespace ooc {
 constexpr int kRowsPerThread = 4;
 constexpr int kBlockRows = 4 * kRowsPerThread;
 constexpr int kXcds = 8;
+// consecutive z-planes one thread of the z-walking point loop covers (8 and
+// 16 were measured to read more from HBM on 640^3, not less)
+constexpr int kPlanesPerThread = 4;
+
+// x of a launch's first block column: the range start rounded down to a
+// multiple of 16 points.  With x = 0 stored on a 128-byte boundary, every
+// 64-point row segment a wavefront touches is then four whole 128-byte lines
+// (threads left of the range start idle).
+__host__ __device__ inline int x_origin(int lo) { return lo & ~15; }
 
 // bijection of [0, n): workgroup id -> logical block, contiguous per XCD
 __device__ __forceinline__ int xcd_block(int pid, int n) {
@@ -38,10 +47,10 @@ __device__ __forceinline__ int xcd_block(int pid, int n) {
     const int n_ = (int)(gridDim.x * gridDim.y * gridDim.z);                               \
     const int l_ = xcd_block((int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)), n_); \
     const int bx_ = l_ % (int)gridDim.x, by_ = (l_ / (int)gridDim.x) % (int)gridDim.y;      \
-    const int i = a.lo[0] + bx_ * 64 + (int)threadIdx.x;                                   \
+    const int i = x_origin(a.lo[0]) + bx_ * 64 + (int)threadIdx.x;                         \
     const int k = a.lo[2] + l_ / (int)(gridDim.x * gridDim.y);                              \
     const int j0_ = a.lo[1] + by_ * kBlockRows + (int)threadIdx.y;                           \
-    if (i < a.hi[0])                                                                       \
+    if (i >= a.lo[0] && i < a.hi[0])                                                       \
       for (int r_ = 0; r_ < kRowsPerThread; r_++) {                                        \
         const int j = j0_ + 4 * r_;                                                        \
         if (j >= a.hi[1]) break;
@@ -49,7 +58,7 @@ __device__ __forceinline__ int xcd_block(int pid, int n) {
   }               \
   }
 
-// The same point loop walking kRowsPerThread consecutive z-planes instead of
+// The same point loop walking kPlanesPerThread consecutive z-planes instead of
 // rows (for stencils that reach along z: a thread's z-neighbours were mostly
 // loaded for its previous plane); launched with point_grid_z.
 #define POINT_BEGIN_Z                                                                      \
@@ -57,28 +66,35 @@ __device__ __forceinline__ int xcd_block(int pid, int n) {
     const int n_ = (int)(gridDim.x * gridDim.y * gridDim.z);                               \
     const int l_ = xcd_block((int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)), n_); \
     const int bx_ = l_ % (int)gridDim.x, by_ = (l_ / (int)gridDim.x) % (int)gridDim.y;      \
-    const int i = a.lo[0] + bx_ * 64 + (int)threadIdx.x;                                   \
+    const int i = x_origin(a.lo[0]) + bx_ * 64 + (int)threadIdx.x;                         \
     const int j = a.lo[1] + by_ * 4 + (int)threadIdx.y;                                    \
-    const int k0_ = a.lo[2] + (l_ / (int)(gridDim.x * gridDim.y)) * kRowsPerThread;         \
-    if (i < a.hi[0] && j < a.hi[1])                                                        \
-      for (int r_ = 0; r_ < kRowsPerThread; r_++) {                                        \
+    const int k0_ = a.lo[2] + (l_ / (int)(gridDim.x * gridDim.y)) * kPlanesPerThread;       \
+    if (i >= a.lo[0] && i < a.hi[0] && j < a.hi[1])                                        \
+      for (int r_ = 0; r_ < kPlanesPerThread; r_++) {                                      \
         const int k = k0_ + r_;                                                            \
         if (k >= a.hi[2]) break;
 
+// Field storage is device global memory, but its pointers come from the
+// argument table in memory, so the compiler cannot tell and would emit flat
+// accesses -- which share the LDS wait counter, making every wait for an LDS
+// result also wait for all outstanding HBM loads.  Accesses go through gp().
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ gdouble *gp(double *p) { return (gdouble *)p; }
+
 // element (i+di, j+dj, k+dk) of DAT argument n
 #define AT(n, di, dj, dk) \
-  a.p[n][(int64_t)(k + (dk)) * a.plane + (int64_t)(j + (dj)) * a.pitch + (i + (di))]
+  gp(a.p[n])[(int64_t)(k + (dk)) * a.plane + (int64_t)(j + (dj)) * a.pitch + (i + (di))]
 
 inline dim3 point_grid_z(const KArgs &a) {
-  const int nx = a.hi[0] - a.lo[0], ny = a.hi[1] - a.lo[1], nz = a.hi[2] - a.lo[2];
-  if (nx <= 0 || ny <= 0 || nz <= 0) return dim3(0, 0, 0);
-  return dim3((nx + 63) / 64, (ny + 3) / 4, (nz + kRowsPerThread - 1) / kRowsPerThread);
+  const int nx = a.hi[0] - x_origin(a.lo[0]), ny = a.hi[1] - a.lo[1], nz = a.hi[2] - a.lo[2];
+  if (a.hi[0] <= a.lo[0] || ny <= 0 || nz <= 0) return dim3(0, 0, 0);
+  return dim3((nx + 63) / 64, (ny + 3) / 4, (nz + kPlanesPerThread - 1) / kPlanesPerThread);
 }
 
 inline dim3 point_grid(const KArgs &a, int ndim) {
-  const int nx = a.hi[0] - a.lo[0], ny = a.hi[1] - a.lo[1];
+  const int nx = a.hi[0] - x_origin(a.lo[0]), ny = a.hi[1] - a.lo[1];
   const int nz = ndim == 3 ? a.hi[2] - a.lo[2] : 1;
-  if (nx <= 0 || ny <= 0 || nz <= 0) return dim3(0, 0, 0);
+  if (a.hi[0] <= a.lo[0] || ny <= 0 || nz <= 0) return dim3(0, 0, 0);
   return dim3((nx + 63) / 64, (ny + kBlockRows - 1) / kBlockRows, nz);
 }
 

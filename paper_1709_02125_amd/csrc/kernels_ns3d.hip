@@ -49,39 +49,142 @@ OOC_KERNEL(k_ns_prims) {
   POINT_END
 }
 
-// T = gamma M^2 p / rho at an offset point
-#define TEMP(di, dj, dk) ((gm2 * AT(4, di, dj, dk)) / AT(0, di, dj, dk))
+// Launch shape of the z-marching kernels below: a block of 64 x PH threads
+// owns a 64 x PH (x, y) patch of the range and walks a run of consecutive
+// z-planes of it; grid.z cuts each patch's column into segments of at least
+// kMinSegPlanes planes, as many as bring the launch to about kTargetThreads
+// threads (every segment re-reads the 4 planes of stencil reach around it).
+// Taller patches re-read fewer halo rows per point, but measured on 512^3 they
+// were no faster (8 and 12 rows for the residual, 8 and 16 for the
+// gradients: the residual is bound by the dependent load round trips of each
+// plane, not by bytes), so both use 4.
+constexpr int kRhsRows = 4;
+constexpr int kGradRows = 4;
+constexpr int kMinSegPlanes = 8;
+constexpr int kTargetThreads = 2048 * 256;
 
-OOC_KERNEL(k_ns_grads) {
-  ARGS
-  POINT_BEGIN_Z
-  const double inv = a.c[0], gm2 = a.c[1];
-#pragma unroll
-  for (int c = 0; c < 3; c++) {
-    const int f = 1 + c;
-    AT(5 + 3 * c, 0, 0, 0) = deriv(AT(f, -2, 0, 0), AT(f, -1, 0, 0), AT(f, 1, 0, 0), AT(f, 2, 0, 0), inv);
-    AT(6 + 3 * c, 0, 0, 0) = deriv(AT(f, 0, -2, 0), AT(f, 0, -1, 0), AT(f, 0, 1, 0), AT(f, 0, 2, 0), inv);
-    AT(7 + 3 * c, 0, 0, 0) = deriv(AT(f, 0, 0, -2), AT(f, 0, 0, -1), AT(f, 0, 0, 1), AT(f, 0, 0, 2), inv);
-  }
-  AT(14, 0, 0, 0) = deriv(TEMP(-2, 0, 0), TEMP(-1, 0, 0), TEMP(1, 0, 0), TEMP(2, 0, 0), inv);
-  AT(15, 0, 0, 0) = deriv(TEMP(0, -2, 0), TEMP(0, -1, 0), TEMP(0, 1, 0), TEMP(0, 2, 0), inv);
-  AT(16, 0, 0, 0) = deriv(TEMP(0, 0, -2), TEMP(0, 0, -1), TEMP(0, 0, 1), TEMP(0, 0, 2), inv);
-  POINT_END
+template <int PH>
+void launch_zmarch(void (*kern)(const KArgs *), const KArgs &a, const KArgs *dev, int ndim, void *s) {
+  const int nx = a.hi[0] - x_origin(a.lo[0]), ny = a.hi[1] - a.lo[1], nz = ndim == 3 ? a.hi[2] - a.lo[2] : 1;
+  if (a.hi[0] <= a.lo[0] || ny <= 0 || nz <= 0) return;
+  const int gx = (nx + 63) / 64, gy = (ny + PH - 1) / PH;
+  const int per = gx * gy * 64 * PH;
+  const int want = (kTargetThreads + per - 1) / per;
+  const int most = (nz + kMinSegPlanes - 1) / kMinSegPlanes;
+  const int nseg = want < most ? want : most;
+  hipLaunchKernelGGL(kern, dim3(gx, gy, nseg > 1 ? nseg : 1), dim3(64, PH, 1), 0, (hipStream_t)s, dev);
 }
-#undef TEMP
 
-// total flux (convective minus viscous) along axis A at offset point (di,dj,dk)
+// Common prologue of the z-marching kernels (PH rows per patch): the block's
+// patch origin (i0, j0), the thread's point (i, j), its z-segment [kb, ke),
+// and which columns are needed: `own` (inside the two-point stencil reach of
+// the range, so its values feed a neighbour's difference) and `out` (inside
+// the range).  Block columns start at x_origin(lo), so threads left of the
+// range idle.
+#define ZMARCH_BEGIN(PH)                                                                         \
+  const int n_ = (int)(gridDim.x * gridDim.y * gridDim.z);                                       \
+  const int l_ = xcd_block((int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)), n_); \
+  const int bx = l_ % (int)gridDim.x, by = (l_ / (int)gridDim.x) % (int)gridDim.y;               \
+  const int bz = l_ / (int)(gridDim.x * gridDim.y);                                              \
+  const int tx = (int)threadIdx.x, ty = (int)threadIdx.y;                                        \
+  const int i0 = x_origin(a.lo[0]) + bx * 64, j0 = a.lo[1] + by * (PH);                          \
+  const int i = i0 + tx, j = j0 + ty;                                                            \
+  const int nz_ = a.hi[2] - a.lo[2], seg_ = (nz_ + (int)gridDim.z - 1) / (int)gridDim.z;         \
+  const int kb = a.lo[2] + bz * seg_, ke = kb + seg_ < a.hi[2] ? kb + seg_ : a.hi[2];            \
+  if (kb >= ke) return; /* the same for the whole block */                                       \
+  const int xs = a.lo[0] - 2, xe = a.hi[0] + 2, ye = a.hi[1] + 2;                                \
+  const bool own = i >= xs && i < xe && j < ye, out = i >= a.lo[0] && i < a.hi[0] && j < a.hi[1]; \
+  const int64_t col = (int64_t)j * a.pitch + i;                                                  \
+  /* halo slots: threads of rows ty < 4 load the y-halo rows j0-2, j0-1,     */                  \
+  /* j0+PH, j0+PH+1 (LDS rows hn); threads tx < 4 of every row the x-halo    */                  \
+  /* columns i0-2, i0-1, i0+64, i0+65 (LDS columns hm)                       */                  \
+  const bool yhalo = ty < 4;                                                                     \
+  const int hn = ty < 2 ? ty : (PH) + ty, hy = j0 - 2 + hn;                                      \
+  const int hm = tx < 2 ? tx : 64 + tx, hx = i0 - 2 + hm;
+
+// Stored first derivatives, marching along z.  Each thread keeps u, v, w and
+// T = gamma M^2 p / rho of its own column for planes k-2 .. k+2 in registers,
+// so every plane of the inputs is loaded once and T is evaluated once per
+// point; the plane-k values of the patch plus two columns / rows of halo are
+// staged in LDS for the x and y differences.  The values and the difference
+// formula are those of a point-by-point evaluation, so results are identical.
+template <int PH>
+__global__ void __launch_bounds__(64 * PH) k_ns_grads(const KArgs *__restrict__ ap) {
+  ARGS
+  __shared__ double sv[4][PH + 4][68];  // u, v, w, T at plane k: y = j0-2 .. j0+PH+1, x = i0-2 .. i0+65
+  ZMARCH_BEGIN(PH)
+  const double inv = a.c[0], gm2 = a.c[1];
+  auto load = [&](int64_t o, double v[4]) {
+    v[0] = gp(a.p[1])[o];
+    v[1] = gp(a.p[2])[o];
+    v[2] = gp(a.p[3])[o];
+    v[3] = (gm2 * gp(a.p[4])[o]) / gp(a.p[0])[o];
+  };
+  double rg[5][4];  // own column, planes k-2 .. k+2
+  if (own)
+#pragma unroll
+    for (int q = 0; q < 4; q++) load((int64_t)(kb - 2 + q) * a.plane + col, rg[q]);
+#pragma unroll 1
+  for (int k = kb; k < ke; k++) {
+    const int64_t pk = (int64_t)k * a.plane;
+    if (own) {
+      load(pk + 2 * a.plane + col, rg[4]);
+#pragma unroll
+      for (int f = 0; f < 4; f++) sv[f][ty + 2][tx + 2] = rg[2][f];
+    }
+    if (yhalo && i >= a.lo[0] && i < a.hi[0] && hy < ye) {
+      double v[4];
+      load(pk + (int64_t)hy * a.pitch + i, v);
+#pragma unroll
+      for (int f = 0; f < 4; f++) sv[f][hn][tx + 2] = v[f];
+    }
+    if (tx < 4 && j < a.hi[1] && hx >= xs && hx < xe) {
+      double v[4];
+      load(pk + (int64_t)j * a.pitch + hx, v);
+#pragma unroll
+      for (int f = 0; f < 4; f++) sv[f][ty + 2][hm] = v[f];
+    }
+    __syncthreads();
+    if (out) {
+      const int64_t o = pk + col;
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        gp(a.p[5 + 3 * c])[o] = deriv(sv[c][ty + 2][tx], sv[c][ty + 2][tx + 1], sv[c][ty + 2][tx + 3],
+                                  sv[c][ty + 2][tx + 4], inv);
+        gp(a.p[6 + 3 * c])[o] = deriv(sv[c][ty][tx + 2], sv[c][ty + 1][tx + 2], sv[c][ty + 3][tx + 2],
+                                  sv[c][ty + 4][tx + 2], inv);
+        gp(a.p[7 + 3 * c])[o] = deriv(rg[0][c], rg[1][c], rg[3][c], rg[4][c], inv);
+      }
+      gp(a.p[14])[o] = deriv(sv[3][ty + 2][tx], sv[3][ty + 2][tx + 1], sv[3][ty + 2][tx + 3], sv[3][ty + 2][tx + 4], inv);
+      gp(a.p[15])[o] = deriv(sv[3][ty][tx + 2], sv[3][ty + 1][tx + 2], sv[3][ty + 3][tx + 2], sv[3][ty + 4][tx + 2], inv);
+      gp(a.p[16])[o] = deriv(rg[0][3], rg[1][3], rg[3][3], rg[4][3], inv);
+    }
+    __syncthreads();  // the next plane overwrites the staged values
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+      for (int f = 0; f < 4; f++) rg[q][f] = rg[q + 1][f];
+  }
+}
+
+// the 17 inputs of a flux at one point: rho, u, v, w, p, the 9 velocity
+// gradients (u_x u_y u_z v_x ... w_z) and the 3 temperature gradients
+__device__ inline void ns_load(const KArgs &a, int64_t o, double v[17]) {
+#pragma unroll
+  for (int f = 0; f < 17; f++) v[f] = gp(a.p[PR + f])[o];
+}
+
+// total flux (convective minus viscous) along axis A from a point's inputs
 template <int A>
-__device__ inline void ns_flux(const KArgs &a, int i, int j, int k, int di, int dj, int dk, double mu,
-                               double kappa, double out[5]) {
-  const double r = AT(PR, di, dj, dk), p = AT(PP, di, dj, dk);
-  const double u[3] = {AT(PU, di, dj, dk), AT(PV, di, dj, dk), AT(PW, di, dj, dk)};
+__device__ inline void ns_flux(const double v[17], double mu, double kappa, double out[5]) {
+  const double r = v[PR], p = v[PP];
+  const double u[3] = {v[PU], v[PV], v[PW]};
   const double ua = u[A];
   double g[3][3];
 #pragma unroll
   for (int c = 0; c < 3; c++)
 #pragma unroll
-    for (int b = 0; b < 3; b++) g[c][b] = AT(GUX + 3 * c + b, di, dj, dk);
+    for (int b = 0; b < 3; b++) g[c][b] = v[GUX + 3 * c + b];
   const double div = (g[0][0] + g[1][1]) + g[2][2];
   double tau[3];
 #pragma unroll
@@ -90,7 +193,7 @@ __device__ inline void ns_flux(const KArgs &a, int i, int j, int k, int di, int 
     if (c == A) t -= (2.0 / 3.0) * div;
     tau[c] = mu * t;
   }
-  const double dT = AT(GTX + A, di, dj, dk);
+  const double dT = v[GTX + A];
   const double rE = p / kGm1 + 0.5 * r * ((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
   out[0] = r * ua;
 #pragma unroll
@@ -98,109 +201,104 @@ __device__ inline void ns_flux(const KArgs &a, int i, int j, int k, int di, int 
   out[4] = (rE + p) * ua - ((u[0] * tau[0] + u[1] * tau[1]) + u[2] * tau[2]) - kappa * dT;
 }
 
-template <int A>
-__device__ inline void ns_axis(const KArgs &a, int i, int j, int k, double mu, double kappa, double inv,
-                               double res[5]) {
-  constexpr int ex = A == 0, ey = A == 1, ez = A == 2;
-  double fm2[5], fm1[5], fp1[5], fp2[5];
-  ns_flux<A>(a, i, j, k, -2 * ex, -2 * ey, -2 * ez, mu, kappa, fm2);
-  ns_flux<A>(a, i, j, k, -ex, -ey, -ez, mu, kappa, fm1);
-  ns_flux<A>(a, i, j, k, ex, ey, ez, mu, kappa, fp1);
-  ns_flux<A>(a, i, j, k, 2 * ex, 2 * ey, 2 * ez, mu, kappa, fp2);
-#pragma unroll
-  for (int c = 0; c < 5; c++) res[c] -= deriv(fm2[c], fm1[c], fp1[c], fp2[c], inv);
-}
-
-// Residual and RK update.  A block of 64 x 4 threads owns a 64 x 4 (x, y)
-// patch and walks kZRows consecutive z-planes.  Per plane, the x- and
-// y-fluxes of every point the patch's differences need (the patch plus two
-// columns / rows of halo each side) are evaluated once and staged in LDS, so
-// the 4-point differences along x and y read LDS instead of re-evaluating
-// neighbours' fluxes; the z-fluxes at k-2..k+2 are evaluated per point, their
-// inputs mostly still in cache from the previous plane.  Each flux is the
-// same function of the same inputs wherever it is evaluated, and the
-// differences are taken in the same order (x, y, then z, subtracted from
-// zero), so results equal a point-by-point evaluation exactly.
-constexpr int kZRows = 4;
-
-template <bool kFirst>
-__global__ void __launch_bounds__(256) k_ns_rhs(const KArgs *__restrict__ ap) {
+// Residual and RK update, marching along z.  Every flux is evaluated once, at
+// the leading plane m = k + 2 of the march: the thread's own point gives its
+// x-, y- and z-flux from one load of its 17 inputs; the x- and y-fluxes of the
+// patch plus two columns / rows of halo are staged in LDS and differenced at
+// once into the plane's x/y part of the residual, (0 - d/dx) - d/dy, which
+// waits two planes in registers; the z-fluxes of planes k-2 .. k+2 wait in a
+// register ring.  At plane k the z difference is subtracted and the
+// low-storage Runge-Kutta update applied.  Each flux is the same function of
+// the same inputs wherever it is evaluated and the differences are taken in
+// the same order (x, y, then z, from zero), so results equal a point-by-point
+// evaluation exactly.
+template <bool kFirst, int PH>
+__global__ void __launch_bounds__(64 * PH) k_ns_rhs(const KArgs *__restrict__ ap) {
   ARGS
-  __shared__ double sfx[5][4][68];  // x-flux, x = i0-2 .. i0+65, the patch's 4 rows
-  __shared__ double sfy[5][8][64];  // y-flux, y = j0-2 .. j0+5, the patch's 64 columns
-  const int n_ = (int)(gridDim.x * gridDim.y * gridDim.z);
-  const int l_ = xcd_block((int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)), n_);
-  const int bx = l_ % (int)gridDim.x, by = (l_ / (int)gridDim.x) % (int)gridDim.y;
-  const int bz = l_ / (int)(gridDim.x * gridDim.y);
-  const int tx = (int)threadIdx.x, ty = (int)threadIdx.y;
-  const int i0 = a.lo[0] + bx * 64, j0 = a.lo[1] + by * 4;
-  const int i = i0 + tx, j = j0 + ty;
-  const bool xin = i < a.hi[0], yin = j < a.hi[1];
-  // a flux is needed up to two points past the last point of the range
-  const int xend = a.hi[0] + 2, yend = a.hi[1] + 2;
-  // halo slots of this thread: x-halo column (tx < 4) and y-halo row (ty < 4)
-  const int hm = tx < 2 ? tx : 64 + tx, hx = i0 - 2 + hm;
-  const int hn = ty < 2 ? ty : 4 + ty, hy = j0 - 2 + hn;
+  __shared__ double sfx[5][PH][68];      // x-flux at plane m, x = i0-2 .. i0+65, the patch's rows
+  __shared__ double sfy[5][PH + 4][64];  // y-flux at plane m, y = j0-2 .. j0+PH+1, the patch's columns
+  ZMARCH_BEGIN(PH)
   const double inv = a.c[0], mu = a.c[1], kappa = a.c[2], dt = a.c[3], A = a.c[4], B = a.c[5];
-  for (int r = 0; r < kZRows; r++) {
-    const int k = a.lo[2] + bz * kZRows + r;
-    if (k >= a.hi[2]) break;  // the same for the whole block
-    double f[5];
-    if (yin && i < xend) {
-      ns_flux<0>(a, i, j, k, 0, 0, 0, mu, kappa, f);
+  double fz[5][5];   // own column's z-flux, planes k-2 .. k+2
+  double rxy[3][5];  // own column's x/y residual part, planes k .. k+2
+#pragma unroll 1
+  for (int m = kb - 2; m < ke + 2; m++) {
+    const int64_t pm = (int64_t)m * a.plane;
+    const bool xy = m >= kb && m < ke;  // the same for the whole block
+    if (own) {
+      double v[17];
+      ns_load(a, pm + col, v);
+      ns_flux<2>(v, mu, kappa, fz[4]);
+      if (xy) {
+        double f[5];
+        ns_flux<0>(v, mu, kappa, f);
 #pragma unroll
-      for (int c = 0; c < 5; c++) sfx[c][ty][tx + 2] = f[c];
-    }
-    if (xin && j < yend) {
-      ns_flux<1>(a, i, j, k, 0, 0, 0, mu, kappa, f);
+        for (int c = 0; c < 5; c++) sfx[c][ty][tx + 2] = f[c];
+        ns_flux<1>(v, mu, kappa, f);
 #pragma unroll
-      for (int c = 0; c < 5; c++) sfy[c][ty + 2][tx] = f[c];
-    }
-    if (tx < 4 && yin && hx < xend) {
-      ns_flux<0>(a, hx, j, k, 0, 0, 0, mu, kappa, f);
-#pragma unroll
-      for (int c = 0; c < 5; c++) sfx[c][ty][hm] = f[c];
-    }
-    if (ty < 4 && xin && hy < yend) {
-      ns_flux<1>(a, i, hy, k, 0, 0, 0, mu, kappa, f);
-#pragma unroll
-      for (int c = 0; c < 5; c++) sfy[c][hn][tx] = f[c];
-    }
-    __syncthreads();
-    if (xin && yin) {
-      double res[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int c = 0; c < 5; c++)
-        res[c] -= deriv(sfx[c][ty][tx], sfx[c][ty][tx + 1], sfx[c][ty][tx + 3], sfx[c][ty][tx + 4], inv);
-#pragma unroll
-      for (int c = 0; c < 5; c++)
-        res[c] -= deriv(sfy[c][ty][tx], sfy[c][ty + 1][tx], sfy[c][ty + 3][tx], sfy[c][ty + 4][tx], inv);
-      ns_axis<2>(a, i, j, k, mu, kappa, inv, res);
-#pragma unroll
-      for (int c = 0; c < 5; c++) {
-        const double d = kFirst ? dt * res[c] : A * AT(DR + c, 0, 0, 0) + dt * res[c];
-        AT(DR + c, 0, 0, 0) = d;
-        AT(QR + c, 0, 0, 0) = AT(QR + c, 0, 0, 0) + B * d;
+        for (int c = 0; c < 5; c++) sfy[c][ty + 2][tx] = f[c];
       }
     }
-    __syncthreads();  // the next plane overwrites the staged fluxes
+    if (xy) {
+      if (yhalo && i >= a.lo[0] && i < a.hi[0] && hy < ye) {
+        double v[17], f[5];
+        ns_load(a, pm + (int64_t)hy * a.pitch + i, v);
+        ns_flux<1>(v, mu, kappa, f);
+#pragma unroll
+        for (int c = 0; c < 5; c++) sfy[c][hn][tx] = f[c];
+      }
+      if (tx < 4 && j < a.hi[1] && hx >= xs && hx < xe) {
+        double v[17], f[5];
+        ns_load(a, pm + (int64_t)j * a.pitch + hx, v);
+        ns_flux<0>(v, mu, kappa, f);
+#pragma unroll
+        for (int c = 0; c < 5; c++) sfx[c][ty][hm] = f[c];
+      }
+      __syncthreads();
+      if (out) {
+#pragma unroll
+        for (int c = 0; c < 5; c++) {
+          double r = 0.0;
+          r -= deriv(sfx[c][ty][tx], sfx[c][ty][tx + 1], sfx[c][ty][tx + 3], sfx[c][ty][tx + 4], inv);
+          r -= deriv(sfy[c][ty][tx], sfy[c][ty + 1][tx], sfy[c][ty + 3][tx], sfy[c][ty + 4][tx], inv);
+          rxy[2][c] = r;
+        }
+      }
+      __syncthreads();  // the next plane overwrites the staged fluxes
+    }
+    if (m >= kb + 2 && out) {
+      const int64_t o = pm - 2 * a.plane + col;  // plane k = m - 2
+#pragma unroll
+      for (int c = 0; c < 5; c++) {
+        const double res = rxy[0][c] - deriv(fz[0][c], fz[1][c], fz[3][c], fz[4][c], inv);
+        const double d = kFirst ? dt * res : A * gp(a.p[DR + c])[o] + dt * res;
+        gp(a.p[DR + c])[o] = d;
+        gp(a.p[QR + c])[o] = gp(a.p[QR + c])[o] + B * d;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 5; c++) {
+#pragma unroll
+      for (int q = 0; q < 4; q++) fz[q][c] = fz[q + 1][c];
+      rxy[0][c] = rxy[1][c];
+      rxy[1][c] = rxy[2][c];
+    }
   }
-}
-
-void launch_zrows(void (*kern)(const KArgs *), const KArgs &a, const KArgs *dev, int ndim, void *s) {
-  const int nx = a.hi[0] - a.lo[0], ny = a.hi[1] - a.lo[1], nz = ndim == 3 ? a.hi[2] - a.lo[2] : 1;
-  if (nx <= 0 || ny <= 0 || nz <= 0) return;
-  const dim3 grid((nx + 63) / 64, (ny + 3) / 4, (nz + kZRows - 1) / kZRows);
-  hipLaunchKernelGGL(kern, grid, dim3(64, 4, 1), 0, (hipStream_t)s, dev);
 }
 
 #define L(name, kern) \
   void name(const KArgs &a, const KArgs *d, int nd, void *s) { launch_point(kern, a, d, nd, s); }
 L(l_init, k_ns_init)
 L(l_prims, k_ns_prims)
-void l_grads(const KArgs &a, const KArgs *d, int nd, void *s) { launch_point_z(k_ns_grads, a, d, nd, s); }
-void l_rhs_first(const KArgs &a, const KArgs *d, int nd, void *s) { launch_zrows(k_ns_rhs<true>, a, d, nd, s); }
-void l_rhs(const KArgs &a, const KArgs *d, int nd, void *s) { launch_zrows(k_ns_rhs<false>, a, d, nd, s); }
+void l_grads(const KArgs &a, const KArgs *d, int nd, void *s) {
+  launch_zmarch<kGradRows>(k_ns_grads<kGradRows>, a, d, nd, s);
+}
+void l_rhs_first(const KArgs &a, const KArgs *d, int nd, void *s) {
+  launch_zmarch<kRhsRows>(k_ns_rhs<true, kRhsRows>, a, d, nd, s);
+}
+void l_rhs(const KArgs &a, const KArgs *d, int nd, void *s) {
+  launch_zmarch<kRhsRows>(k_ns_rhs<false, kRhsRows>, a, d, nd, s);
+}
 #undef L
 
 }  // namespace

@@ -16,6 +16,8 @@ constexpr int kMaxConst = 12;
 constexpr int kMaxDev = 2;
 constexpr int kMaxRed = 2;
 constexpr int kMaxStencil = 32;
+// storage element of x = 0 within every field row (a multiple of 16 elements)
+constexpr int64_t kXOrigin = 16;
 
 // Argument block handed by value to every kernel.  Field pointers are rebased
 // so that logical index (i, j[, k]) of a field is p[k*plane + j*pitch + i]

@@ -209,7 +209,9 @@ void free_host(void *p, bool pinned) {
 }
 
 // Storage layout of a field: every field shares the row pitch (x) and, in 3D,
-// the plane size (x * y), so kernels index all fields alike.
+// the plane size (x * y), so kernels index all fields alike.  Within a row, x
+// = 0 is element kXOrigin (a 128-byte boundary when the row starts on one):
+// a 64-point row segment starting at a multiple of 16 is four whole lines.
 void layout_field(ooc_ctx *c, Field &f) {
   for (int a = 0; a < 3; a++) {
     if (a < c->ndim) {
@@ -231,7 +233,7 @@ void copy_extent(ooc_ctx *c, Field &f, double *dst, const double *src, bool to_u
   const int64_t nz = c->ndim == 3 ? f.n[2] : 1;
   for (int64_t k = 0; k < nz; k++)
     for (int64_t j = 0; j < ny; j++) {
-      int64_t so = c->ndim == 3 ? k * c->plane + j * c->pitch : j * c->pitch;
+      int64_t so = (c->ndim == 3 ? k * c->plane + j * c->pitch : j * c->pitch) + kXOrigin + f.lo[0];
       int64_t uo = (k * ny + j) * nx;
       if (f.fp32) {
         float *h = (float *)f.host + so;
@@ -447,7 +449,7 @@ double *field_ptr(ooc_ctx *c, int f, const Plan &P, int t, char *slot) {
     base = slot + P.slab_off[f];
     A = P.resA[(size_t)f * P.T + t];
   }
-  int64_t shift = -A * fd.row_elems - fd.lo[0] - fd.lo[1] * c->pitch;
+  int64_t shift = -A * fd.row_elems + kXOrigin - fd.lo[1] * c->pitch;
   if (c->ndim == 3) shift -= fd.lo[2] * c->plane;
   return (double *)(base + shift * 8);
 }
@@ -1068,7 +1070,7 @@ int ooc_create(ooc_ctx **out, int ndim, const int64_t dims[3], int halo, size_t 
   for (int d = 0; d < 3; d++) c->dims[d] = d < ndim ? dims[d] : 1;
   c->budget = budget;
   c->flags = flags;
-  c->pitch = (dims[0] + 2 * halo + 1 + 31) / 32 * 32;
+  c->pitch = (kXOrigin + dims[0] + halo + 1 + 31) / 32 * 32;
   c->plane = ndim == 3 ? c->pitch * (dims[1] + 2 * halo + 1) : 0;
   *out = c;
   return OOC_OK;
@@ -1273,6 +1275,14 @@ int ooc_set_schedule(ooc_ctx *c, int64_t tile_rows, int chain_steps, int slots) 
     c->plans.clear();
     return OOC_OK;
   });
+}
+
+int ooc_get_layout(ooc_ctx *c, int64_t *pitch, int64_t *plane, int64_t *x_origin) {
+  if (!c || !pitch || !plane || !x_origin) return OOC_E_ARG;
+  *pitch = c->pitch;
+  *plane = c->plane;
+  *x_origin = kXOrigin;
+  return OOC_OK;
 }
 
 int ooc_get_stats(ooc_ctx *c, ooc_stats *out) {

@@ -44,8 +44,8 @@ def footprint_bytes(nx: int, ny: int) -> int:
 
 def device_footprint_bytes(nx: int, ny: int) -> int:
     """Device bytes to hold every field resident in the library's padded
-    layout (row pitch rounded up to 32 elements), plus reduction buffers."""
-    pitch = (nx + 2 * H + 1 + 31) // 32 * 32
+    layout (ooc.row_pitch elements per row), plus reduction buffers."""
+    pitch = ooc.row_pitch(nx, H)
     tot = 0
     for _, (dx, dy) in FIELDS:
         tot += ((ny + 2 * H + dy) * pitch * 8 + 255) // 256 * 256

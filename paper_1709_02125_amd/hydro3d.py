@@ -68,7 +68,7 @@ def footprint_bytes(n) -> int:
 
 
 def device_footprint_bytes(n) -> int:
-    pitch = (n[0] + 2 * H + 1 + 31) // 32 * 32
+    pitch = ooc.row_pitch(n[0], H)
     plane = pitch * (n[1] + 2 * H + 1)
     tot = 0
     for _, c in FIELDS:

@@ -40,7 +40,7 @@ def footprint_bytes(n: int) -> int:
 
 
 def device_footprint_bytes(n: int) -> int:
-    pitch = (n + 2 * NH + 1 + 31) // 32 * 32
+    pitch = ooc.row_pitch(n, NH)
     plane = pitch * (n + 2 * NH + 1)
     per = ((n + 2 * NH) * plane * 8 + 255) // 256 * 256
     return len(FIELDS) * per + (1 << 20)

@@ -62,7 +62,7 @@ class ooc_plan_info(ctypes.Structure):
 EXPORTS = ["ooc_create", "ooc_bind_device", "ooc_decl_field", "ooc_decl_reduction", "ooc_set_reduction",
            "ooc_par_loop", "ooc_mark_step", "ooc_discard_queue", "ooc_execute", "ooc_submit", "ooc_reduce", "ooc_fetch_field",
            "ooc_set_field", "ooc_set_flags", "ooc_set_schedule", "ooc_get_stats", "ooc_set_timing",
-           "ooc_kernel_stats", "ooc_last_error", "ooc_destroy", "ooc_debug_plan", "ooc_field_shape",
+           "ooc_kernel_stats", "ooc_last_error", "ooc_destroy", "ooc_debug_plan", "ooc_field_shape", "ooc_get_layout",
            "ooc_mlp_create", "ooc_mlp_num_params", "ooc_mlp_get_params", "ooc_mlp_set_params",
            "ooc_mlp_predict", "ooc_mlp_gradient", "ooc_mlp_train", "ooc_mlp_destroy"]
 
@@ -103,6 +103,7 @@ def load_library() -> ctypes.CDLL:
         "ooc_set_flags": [P, U32, U32],
         "ooc_set_schedule": [P, I64, I, I],
         "ooc_get_stats": [P, ctypes.POINTER(ooc_stats)],
+        "ooc_get_layout": [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)],
         "ooc_set_timing": [P, I],
         "ooc_kernel_stats": [P, I, DP, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
         "ooc_last_error": [P],
@@ -127,6 +128,17 @@ def load_library() -> ctypes.CDLL:
 
 
 # ------------------------------------------------------------- arguments
+# element of x = 0 within every stored row (ooc_get_layout's x_origin)
+X_ORIGIN = 16
+
+
+def row_pitch(nx: int, halo: int) -> int:
+    """Elements per stored row for nx interior points and the given halo:
+    x = -halo .. nx + halo (one extra for node-centred fields) from X_ORIGIN,
+    rounded up to 32 elements (ooc_get_layout's pitch)."""
+    return (X_ORIGIN + nx + halo + 1 + 31) // 32 * 32
+
+
 class Dat:
     __slots__ = ("field", "access", "offsets")
 
@@ -297,6 +309,12 @@ class Context:
         """Per-launch hipEvent timing of every loop, or of one kernel id only."""
         mode = 0 if not on else (1 if kernel_id is None else 2 + int(kernel_id))
         self._check(self.lib.ooc_set_timing(self._h, mode))
+
+    def layout(self):
+        """(pitch, plane, x_origin) of the storage layout, in elements."""
+        v = [ctypes.c_int64() for _ in range(3)]
+        self._check(self.lib.ooc_get_layout(self._h, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def stats(self) -> dict:
         s = ooc_stats()

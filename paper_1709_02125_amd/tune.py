@@ -171,7 +171,7 @@ def hydro2d_workload(n: int, budget: int, flags: int = 0):
         for _ in range(k):
             planner.queue_step()
 
-    pitch = (n + 2 * h2.H + 1 + 31) // 32 * 32
+    pitch = ooc.row_pitch(n, h2.H)
     row_bytes = pitch * (4 if flags & ooc.FLAG_FP32_STREAM else 8)
     return app, planner.ctx, queue_steps, n * n, row_bytes
 
@@ -190,7 +190,7 @@ def ns3d_workload(n: int, budget: int, flags: int = 0):
         for _ in range(k):
             planner.queue_step()
 
-    pitch = (n + 2 * N.NH + 1 + 31) // 32 * 32
+    pitch = ooc.row_pitch(n, N.NH)
     row_bytes = pitch * (n + 2 * N.NH + 1) * (4 if flags & ooc.FLAG_FP32_STREAM else 8)
     return app, planner.ctx, queue_steps, n ** 3, row_bytes
 

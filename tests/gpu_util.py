@@ -34,7 +34,7 @@ def gpu_hydro(nx, ny, steps, budget=None, flags=0, tile_rows=0, slots=0, incore=
         flags |= ooc.FLAG_INCORE
         budget = h2.device_footprint_bytes(nx, ny)
     elif budget is None:
-        budget = h2.footprint_bytes(nx, ny) // 3
+        budget = h2.device_footprint_bytes(nx, ny) // 3
     app = h2.Hydro2D(nx, ny, rho, ene, budget=budget, flags=flags, resident_geometry=resident_geometry,
                      cyclic_after_init=cyclic, resident_state=resident_state)
     if tile_rows or slots:
@@ -79,7 +79,7 @@ def gpu_hydro3d(n, steps, budget=None, flags=0, tile_rows=0, slots=0, incore=Fal
         flags |= ooc.FLAG_INCORE
         budget = h3.device_footprint_bytes(n)
     elif budget is None:
-        budget = h3.footprint_bytes(n) // 3
+        budget = h3.device_footprint_bytes(n) // 3
     app = h3.Hydro3D(n, rho, ene, budget=budget, flags=flags, resident_geometry=resident_geometry,
                      cyclic_after_init=cyclic)
     if tile_rows or slots:

@@ -72,7 +72,7 @@ def test_hydro2d_resident_state_bit_exact():
     nx, ny, steps = 48, 90, 3
     say("case: resident state")
     ref, rdts, _ = gpu_hydro(nx, ny, steps, incore=True)
-    got, gdts, st = gpu_hydro(nx, ny, steps, budget=h2.footprint_bytes(nx, ny) // 2, resident_state=True)
+    got, gdts, st = gpu_hydro(nx, ny, steps, budget=h2.device_footprint_bytes(nx, ny) // 2, resident_state=True)
     assert st["ntiles_last"] >= 2 and st["last_bytes_h2d"] == 0 and st["last_bytes_d2h"] == 0
     for n in STATE:
         assert np.array_equal(got[n], ref[n]), n
@@ -83,7 +83,7 @@ def test_hydro2d_resident_geometry_bit_exact():
     nx, ny, steps = 48, 60, 3
     say("case: resident geometry")
     ref, _, _ = gpu_hydro(nx, ny, steps, incore=True)
-    got, _, st = gpu_hydro(nx, ny, steps, budget=h2.footprint_bytes(nx, ny) // 2, resident_geometry=True)
+    got, _, st = gpu_hydro(nx, ny, steps, budget=h2.device_footprint_bytes(nx, ny) // 2, resident_geometry=True)
     for n in STATE:
         assert np.array_equal(got[n], ref[n]), n
 
@@ -93,11 +93,11 @@ def test_hydro2d_transfer_bytes_match_plan():
     say("case: transfer bytes vs plan")
     from paper_1709_02125_amd.inputs import hydro_initial_state
     rho, ene = hydro_initial_state((nx, ny))
-    app = h2.Hydro2D(nx, ny, rho, ene, budget=h2.footprint_bytes(nx, ny) // 3)
+    app = h2.Hydro2D(nx, ny, rho, ene, budget=h2.device_footprint_bytes(nx, ny) // 3)
     app.initialise()
     app.queue_step()
     p = app.ctx.debug_plan()
-    pitch = (nx + 5 + 31) // 32 * 32
+    pitch = app.ctx.layout()[0]
     up = int((p["up"][:, 3] - p["up"][:, 2]).sum()) * pitch * 8
     down = int((p["down"][:, 3] - p["down"][:, 2]).sum()) * pitch * 8
     app.ctx.execute()
@@ -117,7 +117,7 @@ def test_hydro2d_mass_sum_is_tiling_independent_and_conserved():
     masses = []
     for incore in (True, False):
         flags = ooc.FLAG_INCORE if incore else 0
-        budget = h2.device_footprint_bytes(nx, ny) if incore else h2.footprint_bytes(nx, ny) // 3
+        budget = h2.device_footprint_bytes(nx, ny) if incore else h2.device_footprint_bytes(nx, ny) // 3
         app = h2.Hydro2D(nx, ny, rho, ene, budget=budget, flags=flags)
         app.initialise()
         app.queue_mass()
@@ -143,7 +143,7 @@ def test_cyclic_before_init_is_refused():
     say("case: cyclic before init")
     from paper_1709_02125_amd.inputs import hydro_initial_state
     rho, ene = hydro_initial_state((nx, ny))
-    app = h2.Hydro2D(nx, ny, rho, ene, budget=h2.footprint_bytes(nx, ny), flags=ooc.FLAG_CYCLIC)
+    app = h2.Hydro2D(nx, ny, rho, ene, budget=h2.device_footprint_bytes(nx, ny), flags=ooc.FLAG_CYCLIC)
     app.queue_init()
     app.ctx.execute()
     app.queue_step()
@@ -163,14 +163,14 @@ def test_hydro2d_fp32_streaming_error_is_stated_and_tiling_independent():
     say("case: fp32 streaming")
     flags = ooc.FLAG_FP32_STREAM | ooc.FLAG_PREFETCH
     a, adts, st = gpu_hydro(nx, ny, steps, flags=flags, resident_geometry=True,
-                            budget=h2.footprint_bytes(nx, ny) // 3)
+                            budget=h2.device_footprint_bytes(nx, ny) // 3)
     b, bdts, _ = gpu_hydro(nx, ny, steps, flags=flags, resident_geometry=True, tile_rows=5, slots=4,
-                           budget=h2.footprint_bytes(nx, ny))
+                           budget=h2.device_footprint_bytes(nx, ny))
     for n in STATE:
         assert np.array_equal(a[n], b[n]), n
     assert st["ntiles_last"] > 2
     c, _, _ = gpu_hydro(nx, ny, steps, flags=flags | ooc.FLAG_KERNEL_COPY, resident_geometry=True,
-                        tile_rows=7, budget=h2.footprint_bytes(nx, ny))
+                        tile_rows=7, budget=h2.device_footprint_bytes(nx, ny))
     for n in STATE:   # conversion in the copy kernel == staging + convert kernels
         assert np.array_equal(a[n], c[n]), n
     ref, odts = oracle_hydro(nx, ny, steps)

@@ -58,7 +58,7 @@ def test_hydro3d_resident_geometry_bit_exact():
     n, steps = (24, 20, 60), 2
     say("case: hydro3d resident geometry")
     ref, _, _, _ = gpu_hydro3d(n, steps, incore=True)
-    got, _, st, _ = gpu_hydro3d(n, steps, budget=h3.footprint_bytes(n) // 2, resident_geometry=True)
+    got, _, st, _ = gpu_hydro3d(n, steps, budget=h3.device_footprint_bytes(n) // 2, resident_geometry=True)
     assert st["ntiles_last"] >= 2
     for name in STATE3:
         assert np.array_equal(got[name], ref[name]), name
@@ -70,9 +70,9 @@ def test_hydro3d_fp32_streaming_error_is_stated_and_tiling_independent():
     n, steps = (24, 20, 60), 5
     say("case: hydro3d fp32 streaming")
     flags = ooc.FLAG_FP32_STREAM | ooc.FLAG_PREFETCH
-    a, adts, st, _ = gpu_hydro3d(n, steps, flags=flags, resident_geometry=True, budget=h3.footprint_bytes(n) // 2)
+    a, adts, st, _ = gpu_hydro3d(n, steps, flags=flags, resident_geometry=True, budget=h3.device_footprint_bytes(n) // 2)
     b, bdts, _, _ = gpu_hydro3d(n, steps, flags=flags, resident_geometry=True, tile_rows=5, slots=4,
-                                budget=h3.footprint_bytes(n))
+                                budget=h3.device_footprint_bytes(n))
     assert st["ntiles_last"] > 2
     for name in STATE3:
         assert np.array_equal(a[name], b[name]), name

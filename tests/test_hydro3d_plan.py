@@ -20,7 +20,7 @@ def test_hydro3d_chain_classification():
     # read-only geometry is uploaded but never downloaded; write-first data is
     # never uploaded; with Cyclic the write-first temporaries stay on the device
     n = (16, 12, 120)
-    app = _app(n, h3.footprint_bytes(n) // 3)
+    app = _app(n, h3.device_footprint_bytes(n) // 3)
     p = app.ctx.debug_plan()
     assert p["nloops"] == 82
     names = [x for x, _ in h3.FIELDS]
@@ -36,7 +36,7 @@ def test_hydro3d_chain_classification():
 
 def test_hydro3d_without_cyclic_downloads_temporaries():
     n = (16, 12, 120)
-    app = _app(n, h3.footprint_bytes(n) // 2, cyclic=False)
+    app = _app(n, h3.device_footprint_bytes(n) // 2, cyclic=False)
     p = app.ctx.debug_plan()
     names = [x for x, _ in h3.FIELDS]
     down = {names[f] for f in p["down"][:, 0]}

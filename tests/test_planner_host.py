@@ -255,3 +255,20 @@ def test_graph_replay_flag_is_refused():
     with pytest.raises(Exception):
         c.set_flags(ooc.FLAG_GRAPH, 0)
     c.close()
+
+
+@pytest.mark.parametrize("ndim,dims,halo", [(2, (7, 5), 1), (2, (100, 9), 2), (3, (13, 6, 5), 4),
+                                            (3, (30, 4, 3), 2)])
+def test_storage_layout_and_host_round_trip(ndim, dims, halo):
+    c = ooc.Context(ndim, dims, halo, 1 << 30, 0, bind=False)
+    pitch, plane, xo = c.layout()
+    # x = 0 on a 128-byte boundary, rows a multiple of 256 bytes holding x = -halo .. nx + halo
+    assert xo == ooc.X_ORIGIN and xo % 16 == 0 and xo >= halo
+    assert pitch == ooc.row_pitch(dims[0], halo) and pitch % 32 == 0 and pitch >= xo + dims[0] + halo + 1
+    assert plane == (pitch * (dims[1] + 2 * halo + 1) if ndim == 3 else 0)
+    rng = np.random.default_rng(len(dims) + dims[0])
+    for cen in [(0,) * ndim, (1,) * ndim]:
+        init = rng.standard_normal(c.field_shape_for(cen))
+        f = c.decl_field("f%d" % cen[0], cen, init)
+        assert np.array_equal(c.fetch_field(f, cen), init)
+    c.close()
