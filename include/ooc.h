@@ -112,6 +112,9 @@ typedef struct {
   double last_kernel_ms;                       /* summed kernel time of the last flush (if timed) */
   double last_issue_ms;                        /* host time spent issuing the last flush's chains */
   double max_call_ms;                          /* longest single runtime call while issuing */
+  uint64_t host_pinned_bytes, host_pageable_bytes; /* host field storage pinned / left pageable
+                                                     (pinning failed): transfers of pageable rows
+                                                     are synchronous with the host */
 } ooc_stats;
 
 /* Create a context for a grid of ndim (2 or 3) axes with dims[a] interior cells

@@ -345,6 +345,9 @@ void setup_device(ooc_ctx *c) {
     c->pinned[k] = pin;
     if (pin) map_host(f);
   }
+  c->st.host_pinned_bytes = c->st.host_pageable_bytes = 0;
+  for (size_t k = 0; k < c->fields.size(); k++)
+    (c->pinned[k] ? c->st.host_pinned_bytes : c->st.host_pageable_bytes) += c->fields[k].host_bytes();
   const size_t budget = std::min(c->budget, c->arena_bytes);
   uint64_t off = 0;
   grow_argtab(c, kArgTableBytes / sizeof(KArgs));
@@ -749,9 +752,11 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       const char *src = slot + P.slab_off[r->f] + (r->lo - A) * f.row_bytes_dev();
       const size_t nb = (size_t)(r->hi - r->lo) * f.row_bytes_host();
       char *dst = (char *)f.host + r->lo * f.row_bytes_host();
-      // Downloads go by copy kernel into the device-mapped host rows: the
-      // runtime's own device-to-host path was measured at ~10 GB/s when it
-      // picked the DMA engine, against ~50 GB/s for a kernel.
+      // Downloads go by copy kernel into the device-mapped host rows.  DMA
+      // downloads (runtime memcpy) ran faster in short runs, but once many
+      // tiles were queued the runtime blocked the host inside launches and
+      // both link directions fell to about half rate; the copy kernel holds
+      // its rate however far ahead the host issues.
       if (kcopy || f.host_dev) {
         if (!f.host_dev) throw DeviceError("kernel copy needs device-mapped pinned host arrays");
         char *hdst = (char *)f.host_dev + r->lo * f.row_bytes_host();

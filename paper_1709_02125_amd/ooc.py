@@ -47,7 +47,8 @@ class ooc_stats(ctypes.Structure):
                 ("tile_rows", ctypes.c_int64), ("ntiles_last", ctypes.c_int32),
                 ("slots", ctypes.c_int32), ("slot_bytes", ctypes.c_uint64),
                 ("last_flush_ms", ctypes.c_double), ("last_kernel_ms", ctypes.c_double),
-                ("last_issue_ms", ctypes.c_double), ("max_call_ms", ctypes.c_double)]
+                ("last_issue_ms", ctypes.c_double), ("max_call_ms", ctypes.c_double),
+                ("host_pinned_bytes", ctypes.c_uint64), ("host_pageable_bytes", ctypes.c_uint64)]
 
 
 class ooc_plan_info(ctypes.Structure):
