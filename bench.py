@@ -151,7 +151,7 @@ class Hydro3DWork(Workload):
         o.set_state(rho, ene)
         dt = o.dt()
         steps, t0 = 0, time.perf_counter()
-        while steps < 10 and (time.perf_counter() - t0) < target_s:
+        while steps < 40 and (time.perf_counter() - t0) < target_s:
             dt = o.step(dt)
             steps += 1
         sec = time.perf_counter() - t0
@@ -207,7 +207,7 @@ class NS3DWork(Workload):
         o.set_primitives(*tgv_initial_state(n))
         dt = on.stable_dt(n)
         steps, t0 = 0, time.perf_counter()
-        while steps < 10 and (time.perf_counter() - t0) < target_s:
+        while steps < 40 and (time.perf_counter() - t0) < target_s:
             o.step(dt)
             steps += 1
         sec = time.perf_counter() - t0
