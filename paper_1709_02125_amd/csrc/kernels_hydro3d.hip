@@ -62,70 +62,135 @@ OOC_KERNEL(k_visc) {
   POINT_END
 }
 
+// The z-walk of the point loop with values carried from one plane to the
+// next: the same block and thread mapping as POINT_BEGIN_Z (64 x 4 threads,
+// each walking kPlanesPerThread consecutive z-planes of its (i, j) column),
+// opened as a plain scope so a kernel can keep what plane k loaded for its
+// upper half (k+1 side) and use it as plane k+1's lower half instead of
+// loading it again.  The values are the same loads the point form makes, so
+// the results are identical.
+#define ZWALK_BEGIN                                                                               \
+  const int n_ = (int)(gridDim.x * gridDim.y * gridDim.z);                                        \
+  const int l_ = xcd_block((int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)), n_); \
+  const int bx_ = l_ % (int)gridDim.x, by_ = (l_ / (int)gridDim.x) % (int)gridDim.y;              \
+  const int i = x_origin(a.lo[0]) + bx_ * 64 + (int)threadIdx.x;                                  \
+  const int j = a.lo[1] + by_ * 4 + (int)threadIdx.y;                                             \
+  const int k0 = a.lo[2] + (l_ / (int)(gridDim.x * gridDim.y)) * kPlanesPerThread;                \
+  const int k1 = k0 + kPlanesPerThread < a.hi[2] ? k0 + kPlanesPerThread : a.hi[2];               \
+  if (i < a.lo[0] || i >= a.hi[0] || j >= a.hi[1] || k0 >= k1) return;
+
 // PdV predictor / corrector.  args: 0 rho0, 1 e0, 2 p, 3 q, 4 vol, 5..7 x/y/z
 // area, 8..10 u0 v0 w0, [corrector: 11..13 u1 v1 w1], then W rho1, W e1.
-template <bool kCorr, int AX>
-__device__ __forceinline__ double pdv_df(const KArgs &a, int i, int j, int k, double fac) {
-  const int v0 = 8 + AX, v1 = 11 + AX, ar = 5 + AX;
-  const double sl = kCorr ? face4_2<AX>(a, v0, v1, i, j, k, 0) : face4<AX>(a, v0, i, j, k, 0);
-  const double sh = kCorr ? face4_2<AX>(a, v0, v1, i, j, k, 1) : face4<AX>(a, v0, i, j, k, 1);
-  const double fl = (fac * AT(ar, 0, 0, 0)) * sl;
-  const double fh = (fac * AT(ar, AX == 0, AX == 1, AX == 2)) * sh;
-  return fh - fl;
-}
-
+// Per cell, the volume change is the sum over axes of area x (sum of the 4
+// face-node velocities) on the upper face minus the same on the lower face.
+// Walking z, the x- and y-face sums split into their node pairs at the
+// cell's lower and upper z (the upper pair is the next plane's lower pair),
+// and the z-face sum and area of the upper face are the next plane's lower
+// ones, so each plane loads only the nodes and areas of its upper z.
 template <bool kCorr>
-OOC_KERNEL(k_pdv) {
+__global__ void __launch_bounds__(256) k_pdv(const KArgs *__restrict__ ap) {
   ARGS
-  POINT_BEGIN_Z
+  int k;
+  ZWALK_BEGIN
   const double fac = 0.125 * a.ds[0][0];
-  const double total = (pdv_df<kCorr, 0>(a, i, j, k, fac) + pdv_df<kCorr, 1>(a, i, j, k, fac)) +
-                       pdv_df<kCorr, 2>(a, i, j, k, fac);
-  const double vol = AT(4, 0, 0, 0);
-  const double m = AT(0, 0, 0, 0) * vol;
+  // node velocity along axis f at (i+di, j+dj, k+dk): start value, or start
+  // plus end value for the corrector
+  auto nv = [&](int f, int di, int dj, int dk) -> double {
+    return kCorr ? AT(8 + f, di, dj, dk) + AT(11 + f, di, dj, dk) : AT(8 + f, di, dj, dk);
+  };
+  // x faces (e = lower / upper x): pair of nodes at one z; y faces likewise;
+  // z face: the 4 nodes at one z
+  auto xpair = [&](int e, int dk) { return nv(0, e, 0, dk) + nv(0, e, 1, dk); };
+  auto ypair = [&](int e, int dk) { return nv(1, 0, e, dk) + nv(1, 1, e, dk); };
+  auto zsum = [&](int dk) { return (nv(2, 0, 0, dk) + nv(2, 1, 0, dk)) + (nv(2, 0, 1, dk) + nv(2, 1, 1, dk)); };
+  k = k0;
+  double xl0 = xpair(0, 0), xh0 = xpair(1, 0), yl0 = ypair(0, 0), yh0 = ypair(1, 0);
+  double zlo = zsum(0), azlo = AT(7, 0, 0, 0);
   constexpr int R1 = kCorr ? 14 : 11, E1 = kCorr ? 15 : 12;
-  AT(R1, 0, 0, 0) = m / (vol + total);
-  AT(E1, 0, 0, 0) = AT(1, 0, 0, 0) - ((AT(2, 0, 0, 0) + AT(3, 0, 0, 0)) * total) / m;
-  POINT_END
+  for (; k < k1; k++) {
+    const double xl1 = xpair(0, 1), xh1 = xpair(1, 1), yl1 = ypair(0, 1), yh1 = ypair(1, 1);
+    const double zhi = zsum(1), azhi = AT(7, 0, 0, 1);
+    const double dfx = (fac * AT(5, 1, 0, 0)) * (xh0 + xh1) - (fac * AT(5, 0, 0, 0)) * (xl0 + xl1);
+    const double dfy = (fac * AT(6, 0, 1, 0)) * (yh0 + yh1) - (fac * AT(6, 0, 0, 0)) * (yl0 + yl1);
+    const double dfz = (fac * azhi) * zhi - (fac * azlo) * zlo;
+    const double total = (dfx + dfy) + dfz;
+    const double vol = AT(4, 0, 0, 0);
+    const double m = AT(0, 0, 0, 0) * vol;
+    AT(R1, 0, 0, 0) = m / (vol + total);
+    AT(E1, 0, 0, 0) = AT(1, 0, 0, 0) - ((AT(2, 0, 0, 0) + AT(3, 0, 0, 0)) * total) / m;
+    xl0 = xl1;
+    xh0 = xh1;
+    yl0 = yl1;
+    yh0 = yh1;
+    zlo = zhi;
+    azlo = azhi;
+  }
 }
 
 // Node acceleration: the force along each axis is a quarter of the sum, over
 // the 4 faces normal to it around the node, of area x (P lower - P upper),
 // the adjoint of the PdV volume change; node mass an eighth of its 8 cells.
 // args: 0 rho0, 1 vol, 2 p, 3 q, 4..6 x/y/z area, 7..9 u0 v0 w0, 10..12 u1 v1
-// w1; CONST nx, ny, nz; DEVSCALAR dt
-OOC_KERNEL(k_accel) {
+// w1; CONST nx, ny, nz; DEVSCALAR dt.  Walking z, a node's upper cells
+// (pressure p + q, mass rho vol) and the x- and y-face areas at its upper z
+// are the next node's lower ones and are carried, not loaded again.
+__global__ void __launch_bounds__(256) k_accel(const KArgs *__restrict__ ap) {
   ARGS
-  POINT_BEGIN_Z
-  double P[2][2][2], M[2][2][2];
+  int k;
+  ZWALK_BEGIN
+  const double dt = a.ds[0][0];
+  double P0[2][2], M0[2][2], ax0[2], ay0[2];  // cells below the node's plane: [b = y][e = x]
+  k = k0;
 #pragma unroll
-  for (int c = 0; c < 2; c++)
+  for (int b = 0; b < 2; b++) {
 #pragma unroll
-    for (int b = 0; b < 2; b++)
+    for (int e = 0; e < 2; e++) {
+      P0[b][e] = AT(2, e - 1, b - 1, -1) + AT(3, e - 1, b - 1, -1);
+      M0[b][e] = AT(0, e - 1, b - 1, -1) * AT(1, e - 1, b - 1, -1);
+    }
+    ax0[b] = AT(4, 0, b - 1, -1);
+    ay0[b] = AT(5, b - 1, 0, -1);
+  }
+  for (; k < k1; k++) {
+    double P1[2][2], M1[2][2], ax1[2], ay1[2];
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
 #pragma unroll
       for (int e = 0; e < 2; e++) {
-        P[c][b][e] = AT(2, e - 1, b - 1, c - 1) + AT(3, e - 1, b - 1, c - 1);
-        M[c][b][e] = AT(0, e - 1, b - 1, c - 1) * AT(1, e - 1, b - 1, c - 1);
+        P1[b][e] = AT(2, e - 1, b - 1, 0) + AT(3, e - 1, b - 1, 0);
+        M1[b][e] = AT(0, e - 1, b - 1, 0) * AT(1, e - 1, b - 1, 0);
       }
-  const double mass = 0.125 * (((M[0][0][0] + M[0][0][1]) + (M[0][1][0] + M[0][1][1])) +
-                               ((M[1][0][0] + M[1][0][1]) + (M[1][1][0] + M[1][1][1])));
-  const double fx = 0.25 * ((AT(4, 0, -1, -1) * (P[0][0][0] - P[0][0][1]) + AT(4, 0, 0, -1) * (P[0][1][0] - P[0][1][1])) +
-                            (AT(4, 0, -1, 0) * (P[1][0][0] - P[1][0][1]) + AT(4, 0, 0, 0) * (P[1][1][0] - P[1][1][1])));
-  const double fy = 0.25 * ((AT(5, -1, 0, -1) * (P[0][0][0] - P[0][1][0]) + AT(5, 0, 0, -1) * (P[0][0][1] - P[0][1][1])) +
-                            (AT(5, -1, 0, 0) * (P[1][0][0] - P[1][1][0]) + AT(5, 0, 0, 0) * (P[1][0][1] - P[1][1][1])));
-  const double fz = 0.25 * ((AT(6, -1, -1, 0) * (P[0][0][0] - P[1][0][0]) + AT(6, 0, -1, 0) * (P[0][0][1] - P[1][0][1])) +
-                            (AT(6, -1, 0, 0) * (P[0][1][0] - P[1][1][0]) + AT(6, 0, 0, 0) * (P[0][1][1] - P[1][1][1])));
-  const double dt = a.ds[0][0];
-  double u = AT(7, 0, 0, 0) + (dt * fx) / mass;
-  double v = AT(8, 0, 0, 0) + (dt * fy) / mass;
-  double w = AT(9, 0, 0, 0) + (dt * fz) / mass;
-  if (i == 0 || i == (int)a.c[0]) u = 0.0;
-  if (j == 0 || j == (int)a.c[1]) v = 0.0;
-  if (k == 0 || k == (int)a.c[2]) w = 0.0;
-  AT(10, 0, 0, 0) = u;
-  AT(11, 0, 0, 0) = v;
-  AT(12, 0, 0, 0) = w;
-  POINT_END
+      ax1[b] = AT(4, 0, b - 1, 0);
+      ay1[b] = AT(5, b - 1, 0, 0);
+    }
+    const double mass = 0.125 * (((M0[0][0] + M0[0][1]) + (M0[1][0] + M0[1][1])) +
+                                 ((M1[0][0] + M1[0][1]) + (M1[1][0] + M1[1][1])));
+    const double fx = 0.25 * ((ax0[0] * (P0[0][0] - P0[0][1]) + ax0[1] * (P0[1][0] - P0[1][1])) +
+                              (ax1[0] * (P1[0][0] - P1[0][1]) + ax1[1] * (P1[1][0] - P1[1][1])));
+    const double fy = 0.25 * ((ay0[0] * (P0[0][0] - P0[1][0]) + ay0[1] * (P0[0][1] - P0[1][1])) +
+                              (ay1[0] * (P1[0][0] - P1[1][0]) + ay1[1] * (P1[0][1] - P1[1][1])));
+    const double fz = 0.25 * ((AT(6, -1, -1, 0) * (P0[0][0] - P1[0][0]) + AT(6, 0, -1, 0) * (P0[0][1] - P1[0][1])) +
+                              (AT(6, -1, 0, 0) * (P0[1][0] - P1[1][0]) + AT(6, 0, 0, 0) * (P0[1][1] - P1[1][1])));
+    double u = AT(7, 0, 0, 0) + (dt * fx) / mass;
+    double v = AT(8, 0, 0, 0) + (dt * fy) / mass;
+    double w = AT(9, 0, 0, 0) + (dt * fz) / mass;
+    if (i == 0 || i == (int)a.c[0]) u = 0.0;
+    if (j == 0 || j == (int)a.c[1]) v = 0.0;
+    if (k == 0 || k == (int)a.c[2]) w = 0.0;
+    AT(10, 0, 0, 0) = u;
+    AT(11, 0, 0, 0) = v;
+    AT(12, 0, 0, 0) = w;
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+#pragma unroll
+      for (int e = 0; e < 2; e++) {
+        P0[b][e] = P1[b][e];
+        M0[b][e] = M1[b][e];
+      }
+      ax0[b] = ax1[b];
+      ay0[b] = ay1[b];
+    }
+  }
 }
 
 // face volume flux along D.  args: R area, R vel0, R vel1, W vf; DEVSCALAR dt
