@@ -4,7 +4,10 @@
 // per loop over the z-walking point loop of kernels_device.h (one wavefront
 // per 64 consecutive x of a row, the block's 4 wavefronts on 4 adjacent rows,
 // each thread walking 4 consecutive z-planes, so both the j+1 and the k+1
-// stencil reads mostly hit in cache).  HBM-bound, no MFMA.
+// stencil reads mostly hit in cache).  The kernels with 8-point stencils
+// (viscosity, PdV, acceleration, node mass, time step) keep what one plane
+// loads for its upper z side in registers as the next plane's lower side.
+// HBM-bound, no MFMA.
 // Expression order follows the plain program exactly (built without FP
 // contraction), so tiled and untiled runs are bit-identical.
 //
@@ -26,16 +29,9 @@ constexpr double kCq2 = 1.0;
 constexpr double kCq1 = 0.5;
 constexpr double kCfl = 0.5;
 
-// Sum of node field n over the 4 nodes of the face normal to axis AX, at
-// offset e along AX (0 = the cell's lower face, 1 = its upper face).
-template <int AX>
-__device__ __forceinline__ double face4(const KArgs &a, int n, int i, int j, int k, int e) {
-  if (AX == 0) return (AT(n, e, 0, 0) + AT(n, e, 1, 0)) + (AT(n, e, 0, 1) + AT(n, e, 1, 1));
-  if (AX == 1) return (AT(n, 0, e, 0) + AT(n, 1, e, 0)) + (AT(n, 0, e, 1) + AT(n, 1, e, 1));
-  return (AT(n, 0, 0, e) + AT(n, 1, 0, e)) + (AT(n, 0, 1, e) + AT(n, 1, 1, e));
-}
-
-// the same with start-plus-end values (fields n0, n1) at every node
+// Sum over the 4 nodes of the face normal to axis AX, at offset e along AX
+// (0 = the cell's lower face, 1 = its upper face), of start-plus-end values
+// (node fields n0, n1)
 template <int AX>
 __device__ __forceinline__ double face4_2(const KArgs &a, int n0, int n1, int i, int j, int k, int e) {
 #define P2(di, dj, dk) (AT(n0, di, dj, dk) + AT(n1, di, dj, dk))
@@ -43,23 +39,6 @@ __device__ __forceinline__ double face4_2(const KArgs &a, int n0, int n1, int i,
   if (AX == 1) return (P2(0, e, 0) + P2(1, e, 0)) + (P2(0, e, 1) + P2(1, e, 1));
   return (P2(0, 0, e) + P2(1, 0, e)) + (P2(0, 1, e) + P2(1, 1, e));
 #undef P2
-}
-
-// mean velocity jump across the cell along AX (node field n)
-template <int AX>
-__device__ __forceinline__ double jump(const KArgs &a, int n, int i, int j, int k) {
-  return 0.25 * (face4<AX>(a, n, i, j, k, 1) - face4<AX>(a, n, i, j, k, 0));
-}
-
-// args: R rho0, R cs, R u0, R v0, R w0, W q
-OOC_KERNEL(k_visc) {
-  ARGS
-  POINT_BEGIN_Z
-  const double d = (jump<0>(a, 2, i, j, k) + jump<1>(a, 3, i, j, k)) + jump<2>(a, 4, i, j, k);
-  double q = 0.0;
-  if (d < 0.0) q = AT(0, 0, 0, 0) * ((kCq2 * d) * d - (kCq1 * AT(1, 0, 0, 0)) * d);
-  AT(5, 0, 0, 0) = q;
-  POINT_END
 }
 
 // The z-walk of the point loop with values carried from one plane to the
@@ -78,6 +57,51 @@ OOC_KERNEL(k_visc) {
   const int k0 = a.lo[2] + (l_ / (int)(gridDim.x * gridDim.y)) * kPlanesPerThread;                \
   const int k1 = k0 + kPlanesPerThread < a.hi[2] ? k0 + kPlanesPerThread : a.hi[2];               \
   if (i < a.lo[0] || i >= a.hi[0] || j >= a.hi[1] || k0 >= k1) return;
+
+// Velocity jumps across a cell, walking z: each axis' jump is a quarter of
+// (upper-face sum - lower-face sum) of the 4 face-node values, and the x- and
+// y-face sums are split into node pairs at the cell's lower and upper z; the
+// upper pairs and the upper z-face sum are the next plane's lower ones.
+struct JumpCarry {
+  double xl, xh, yl, yh, z;  // x pairs (lower / upper x face), y pairs, z-face sum, at one z
+};
+
+// node pairs and z sum at node plane k + dk of velocity fields nu, nv, nw
+__device__ __forceinline__ JumpCarry jump_plane(const KArgs &a, int nu, int nv, int nw, int i, int j, int k,
+                                                int dk) {
+  JumpCarry c;
+  c.xl = AT(nu, 0, 0, dk) + AT(nu, 0, 1, dk);
+  c.xh = AT(nu, 1, 0, dk) + AT(nu, 1, 1, dk);
+  c.yl = AT(nv, 0, 0, dk) + AT(nv, 1, 0, dk);
+  c.yh = AT(nv, 0, 1, dk) + AT(nv, 1, 1, dk);
+  c.z = (AT(nw, 0, 0, dk) + AT(nw, 1, 0, dk)) + (AT(nw, 0, 1, dk) + AT(nw, 1, 1, dk));
+  return c;
+}
+
+// (jump x + jump y) + jump z of a cell from its lower (lo) and upper (hi) planes
+__device__ __forceinline__ double jump_sum(const JumpCarry &lo, const JumpCarry &hi) {
+  const double jx = 0.25 * ((lo.xh + hi.xh) - (lo.xl + hi.xl));
+  const double jy = 0.25 * ((lo.yh + hi.yh) - (lo.yl + hi.yl));
+  const double jz = 0.25 * (hi.z - lo.z);
+  return (jx + jy) + jz;
+}
+
+// args: R rho0, R cs, R u0, R v0, R w0, W q
+__global__ void __launch_bounds__(256) k_visc(const KArgs *__restrict__ ap) {
+  ARGS
+  int k;
+  ZWALK_BEGIN
+  k = k0;
+  JumpCarry lo = jump_plane(a, 2, 3, 4, i, j, k, 0);
+  for (; k < k1; k++) {
+    const JumpCarry hi = jump_plane(a, 2, 3, 4, i, j, k, 1);
+    const double d = jump_sum(lo, hi);
+    double q = 0.0;
+    if (d < 0.0) q = AT(0, 0, 0, 0) * ((kCq2 * d) * d - (kCq1 * AT(1, 0, 0, 0)) * d);
+    AT(5, 0, 0, 0) = q;
+    lo = hi;
+  }
+}
 
 // PdV predictor / corrector.  args: 0 rho0, 1 e0, 2 p, 3 q, 4 vol, 5..7 x/y/z
 // area, 8..10 u0 v0 w0, [corrector: 11..13 u1 v1 w1], then W rho1, W e1.
@@ -305,19 +329,28 @@ OOC_KERNEL(k_nflux) {
 }
 
 // node masses after the sweep (from the swept cells) and before it.
-// args: R rho1, R post, R nf, W nmpost, W nmpre
+// args: R rho1, R post, R nf, W nmpost, W nmpre.  Walking z, the summed
+// masses of the 4 cells above a node are those below the next node.
 template <int D>
-OOC_KERNEL(k_nmass) {
+__global__ void __launch_bounds__(256) k_nmass(const KArgs *__restrict__ ap) {
   ARGS
-  POINT_BEGIN_Z
+  int k;
+  ZWALK_BEGIN
   constexpr int ex = D == 0, ey = D == 1, ez = D == 2;
-#define CM(x, y, z) (AT(0, (x) - 1, (y) - 1, (z) - 1) * AT(1, (x) - 1, (y) - 1, (z) - 1))
-  const double post = 0.125 * (((CM(0, 0, 0) + CM(1, 0, 0)) + (CM(0, 1, 0) + CM(1, 1, 0))) +
-                               ((CM(0, 0, 1) + CM(1, 0, 1)) + (CM(0, 1, 1) + CM(1, 1, 1))));
+  // the 4 cells around the node at cell plane k + dk - 1
+#define CM(x, y, dk) (AT(0, (x) - 1, (y) - 1, (dk) - 1) * AT(1, (x) - 1, (y) - 1, (dk) - 1))
+#define GROUP(dk) ((CM(0, 0, dk) + CM(1, 0, dk)) + (CM(0, 1, dk) + CM(1, 1, dk)))
+  k = k0;
+  double g0 = GROUP(0);
+  for (; k < k1; k++) {
+    const double g1 = GROUP(1);
+    const double post = 0.125 * (g0 + g1);
+    AT(3, 0, 0, 0) = post;
+    AT(4, 0, 0, 0) = post + (AT(2, 0, 0, 0) - AT(2, -ex, -ey, -ez));
+    g0 = g1;
+  }
+#undef GROUP
 #undef CM
-  AT(3, 0, 0, 0) = post;
-  AT(4, 0, 0, 0) = post + (AT(2, 0, 0, 0) - AT(2, -ex, -ey, -ez));
-  POINT_END
 }
 
 // donor-cell momentum flux through the dual face between nodes p and p + e_D.
@@ -345,33 +378,48 @@ OOC_KERNEL(k_vel) {
   POINT_END
 }
 
-// largest absolute value of node field n over the cell's 8 nodes
-__device__ __forceinline__ double absmax8(const KArgs &a, int n, int i, int j, int k) {
-#define AV(x, y, z) fabs(AT(n, x, y, z))
-  return fmax(fmax(fmax(AV(0, 0, 0), AV(1, 0, 0)), fmax(AV(0, 1, 0), AV(1, 1, 0))),
-              fmax(fmax(AV(0, 0, 1), AV(1, 0, 1)), fmax(AV(0, 1, 1), AV(1, 1, 1))));
-#undef AV
+// largest |value| of node field n over the 4 nodes of the cell's face at z + dk
+__device__ __forceinline__ double absmax4(const KArgs &a, int n, int i, int j, int k, int dk) {
+  return fmax(fmax(fabs(AT(n, 0, 0, dk)), fabs(AT(n, 1, 0, dk))), fmax(fabs(AT(n, 0, 1, dk)), fabs(AT(n, 1, 1, dk))));
 }
 
 // stable step of a cell, min-reduced.  args: R e0, R u0, R v0, R w0; CONST dx,
-// dy, dz; RED(MIN)
-OOC_KERNEL(k_dt) {
+// dy, dz; RED(MIN).  Walking z, the velocity jumps and the largest node speeds
+// split into the cell's lower and upper node planes; the upper ones are the
+// next cell's lower ones.  Every thread reaches the block reduction.
+__global__ void __launch_bounds__(256) k_dt(const KArgs *__restrict__ ap) {
   ARGS
   double t = INFINITY;  // smallest bound over this thread's points
-  POINT_BEGIN_Z
-  {
-    const double c2 = (kGamma * kGm1) * AT(0, 0, 0, 0);
-    const double d = (jump<0>(a, 1, i, j, k) + jump<1>(a, 2, i, j, k)) + jump<2>(a, 3, i, j, k);
-    double qr = 0.0;
-    if (d < 0.0) qr = (kCq2 * d) * d - (kCq1 * sqrt(c2)) * d;
-    const double ce = sqrt(c2 + 2.0 * qr);
-    double tc = INFINITY;
-    tc = fmin(tc, a.c[0] / (ce + absmax8(a, 1, i, j, k)));
-    tc = fmin(tc, a.c[1] / (ce + absmax8(a, 2, i, j, k)));
-    tc = fmin(tc, a.c[2] / (ce + absmax8(a, 3, i, j, k)));
-    t = fmin(t, kCfl * tc);
+  const int n_ = (int)(gridDim.x * gridDim.y * gridDim.z);
+  const int l_ = xcd_block((int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)), n_);
+  const int bx_ = l_ % (int)gridDim.x, by_ = (l_ / (int)gridDim.x) % (int)gridDim.y;
+  const int i = x_origin(a.lo[0]) + bx_ * 64 + (int)threadIdx.x;
+  const int j = a.lo[1] + by_ * 4 + (int)threadIdx.y;
+  const int k0 = a.lo[2] + (l_ / (int)(gridDim.x * gridDim.y)) * kPlanesPerThread;
+  const int k1 = k0 + kPlanesPerThread < a.hi[2] ? k0 + kPlanesPerThread : a.hi[2];
+  if (i >= a.lo[0] && i < a.hi[0] && j < a.hi[1] && k0 < k1) {
+    int k = k0;
+    JumpCarry lo = jump_plane(a, 1, 2, 3, i, j, k, 0);
+    double mu = absmax4(a, 1, i, j, k, 0), mv = absmax4(a, 2, i, j, k, 0), mw = absmax4(a, 3, i, j, k, 0);
+    for (; k < k1; k++) {
+      const JumpCarry hi = jump_plane(a, 1, 2, 3, i, j, k, 1);
+      const double hu = absmax4(a, 1, i, j, k, 1), hv = absmax4(a, 2, i, j, k, 1), hw = absmax4(a, 3, i, j, k, 1);
+      const double c2 = (kGamma * kGm1) * AT(0, 0, 0, 0);
+      const double d = jump_sum(lo, hi);
+      double qr = 0.0;
+      if (d < 0.0) qr = (kCq2 * d) * d - (kCq1 * sqrt(c2)) * d;
+      const double ce = sqrt(c2 + 2.0 * qr);
+      double tc = INFINITY;
+      tc = fmin(tc, a.c[0] / (ce + fmax(mu, hu)));
+      tc = fmin(tc, a.c[1] / (ce + fmax(mv, hv)));
+      tc = fmin(tc, a.c[2] / (ce + fmax(mw, hw)));
+      t = fmin(t, kCfl * tc);
+      lo = hi;
+      mu = hu;
+      mv = hv;
+      mw = hw;
+    }
   }
-  POINT_END
   block_min_to(t, a.red[0]);
 }
 
