@@ -302,8 +302,11 @@ constexpr int64_t kXferChunk = 4096;  // elements per block
 // 64-block device-to-host copy took 0.6 ms instead of 8 us), so the writing
 // direction runs only a few wavefronts, each with several loads in flight
 // before its stores; the reading direction needs more wavefronts to cover
-// the link's read latency.
+// the link's read latency.  When the uploads bound the pipeline, the writing
+// direction narrows further (its stores in flight also slow the concurrent
+// DMA uploads).
 constexpr int kXferWriteBlocks = 8;
+constexpr int kXferWriteBlocksNarrow = 2;
 constexpr int kXferReadBlocks = 64;
 constexpr int kXferUnroll = 4;
 
@@ -340,7 +343,7 @@ __global__ void __launch_bounds__(256) k_xfer(XferTable t) {
   for (int64_t b = blockIdx.x; b < t.blk0[t.nseg]; b += gridDim.x) xfer_chunk(t, b);
 }
 
-void launch_xfer_segments(const XferSeg *segs, int nseg, bool to_host, void *stream) {
+void launch_xfer_segments(const XferSeg *segs, int nseg, bool to_host, bool narrow, void *stream) {
   for (int s0 = 0; s0 < nseg; s0 += 32) {
     XferTable t{};
     t.nseg = nseg - s0 < 32 ? nseg - s0 : 32;
@@ -355,7 +358,7 @@ void launch_xfer_segments(const XferSeg *segs, int nseg, bool to_host, void *str
       blocks += (g.n + kXferChunk - 1) / kXferChunk;
     }
     t.blk0[t.nseg] = blocks;
-    const int64_t cap = to_host ? kXferWriteBlocks : kXferReadBlocks;
+    const int64_t cap = to_host ? (narrow ? kXferWriteBlocksNarrow : kXferWriteBlocks) : kXferReadBlocks;
     const int64_t grid = blocks < cap ? blocks : cap;
     if (blocks) hipLaunchKernelGGL(k_xfer, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, t);
   }

@@ -78,7 +78,9 @@ struct XferSeg {
   int mode;
 };
 // to_host: the copy writes host memory (device-to-host), which takes a smaller grid
-void launch_xfer_segments(const XferSeg *segs, int nseg, bool to_host, void *stream);
+// to_host: writing host memory (downloads); narrow: the smallest grid for that
+// direction, for chains whose downloads are well under their uploads
+void launch_xfer_segments(const XferSeg *segs, int nseg, bool to_host, bool narrow, void *stream);
 void launch_red_init(double *acc, double value, void *stream);
 void launch_red_commit(const double *acc, double *committed, void *stream);
 void launch_sum_finalize(const double *partials, int64_t n, double *committed, void *stream);

@@ -609,16 +609,25 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
     c->argtab_cache.emplace(akey, abase);
   }
   // transfer byte counts (known from the plan)
+  uint64_t chain_up = 0, chain_down = 0;
   for (const Run &r : P.up) {
     const uint64_t nb = (uint64_t)(r.hi - r.lo) * c->fields[r.f].row_bytes_host();
     c->st.bytes_h2d += nb;
     c->st.last_bytes_h2d += nb;
+    chain_up += nb;
   }
   for (const Run &r : P.down) {
     const uint64_t nb = (uint64_t)(r.hi - r.lo) * c->fields[r.f].row_bytes_host();
     c->st.bytes_d2h += nb;
     c->st.last_bytes_d2h += nb;
+    chain_down += nb;
   }
+  // A chain that moves at most 60 % as much down as up is bound by its
+  // uploads; its download kernel then runs on a narrow grid, since host
+  // stores in flight slow the concurrent DMA uploads (measured on C2: 2
+  // blocks 239 ms per step, 8 blocks 270 ms).  Otherwise the wider grid
+  // finishes each download sooner (C4: 8 blocks 111 ms, 2 blocks 121 ms).
+  const bool narrow_down = chain_down * 5 <= chain_up * 3;
   for (const Run &r : P.edge) c->st.bytes_edge += (uint64_t)(r.hi - r.lo) * c->fields[r.f].row_elems * 8;
   const uint64_t launches0 = c->st.launches;
 
@@ -676,7 +685,7 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       }
     }
     if (!xup.empty()) {
-      timed_call(c, [&] { launch_xfer_segments(xup.data(), (int)xup.size(), false, c->s_up); }, kCallH2D);
+      timed_call(c, [&] { launch_xfer_segments(xup.data(), (int)xup.size(), false, false, c->s_up); }, kCallH2D);
       HIPCHK(hipGetLastError());
     }
     timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_up, c, g), c->s_up)); }, kCallRecord);
@@ -774,7 +783,8 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       }
     }
     if (!xdown.empty()) {
-      timed_call(c, [&] { launch_xfer_segments(xdown.data(), (int)xdown.size(), true, c->s_down); }, kCallD2H);
+      timed_call(c, [&] { launch_xfer_segments(xdown.data(), (int)xdown.size(), true, narrow_down, c->s_down); },
+                 kCallD2H);
       HIPCHK(hipGetLastError());
     }
     timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_down, c, g), c->s_down)); }, kCallRecord);
