@@ -49,6 +49,9 @@ def gpu_hydro(nx, ny, steps, budget=None, flags=0, tile_rows=0, slots=0, incore=
         dts.append(app.ctx.reduce(app.dt))
     out = {n: app.fetch(n) for n in STATE}
     st = app.ctx.stats()
+    # a bound context pins all of its host storage (pageable rows would make
+    # every transfer of them synchronous)
+    assert st["host_pageable_bytes"] == 0 and st["host_pinned_bytes"] > 0, st
     app.close()
     return out, dts, st
 
