@@ -221,7 +221,10 @@ class Hydro2D:
         self.steps_queued += 1
 
     def queue_mass(self):
-        """Diagnostic chain: order-fixed sum of rho0 * vol over the interior."""
+        """Field summary: order-fixed sum of rho0 * vol over the interior.
+        Queued after a step and before the flush, it joins that step's chain
+        (its reduction is not read in the chain) and moves no extra bytes;
+        queued alone it is a chain of its own that uploads rho0 and vol."""
         self._loop(K_SUM_PROD, ((0, self.nx), (0, self.ny)), self.d("rho0"), self.d("vol"), Red(self.mass))
 
     # ---------------------------------------------------------------- driver

@@ -275,6 +275,8 @@ class Hydro3D:
         self.ctx.mark_step()
 
     def queue_mass(self):
+        """Field summary: order-fixed sum of rho0 * vol over the interior;
+        queued after a step, before the flush, it joins that step's chain."""
         n = self.n
         self._loop(K_SUM_PROD, ((0, n[0]), (0, n[1]), (0, n[2])), self.d("rho0"), self.d("vol"), Red(self.mass))
 

@@ -178,3 +178,39 @@ def test_hydro2d_fp32_streaming_error_is_stated_and_tiling_independent():
     say("fp32 streaming max rel error after %d steps:" % steps, errs)
     for n, e in errs.items():
         assert e < 1e-4, (n, e)
+
+
+def test_hydro2d_field_summary_folded_into_the_step_chain():
+    # the mass summary queued after the last step joins that step's chain:
+    # the flush moves exactly the step's bytes, where a summary chain of its
+    # own uploads rho0 and vol again; the sum (order-fixed per row) and the
+    # state are the same either way
+    nx, ny, steps = 64, 90, 3
+    say("case: mass summary folded into the step chain", nx, ny)
+    from paper_1709_02125_amd.inputs import hydro_initial_state
+    rho, ene = hydro_initial_state((nx, ny))
+
+    def make():
+        app = h2.Hydro2D(nx, ny, rho, ene, budget=h2.device_footprint_bytes(nx, ny) // 3)
+        app.initialise()
+        app.run(steps - 1)
+        return app
+
+    a = make()
+    a.queue_step()
+    a.ctx.execute()
+    step_bytes = a.ctx.stats()["last_bytes_h2d"]
+    a.queue_mass()
+    ma = a.ctx.reduce(a.mass)
+    summary_bytes = a.ctx.stats()["last_bytes_h2d"]
+    b = make()
+    b.queue_step()
+    b.queue_mass()
+    mb = b.ctx.reduce(b.mass)
+    folded_bytes = b.ctx.stats()["last_bytes_h2d"]
+    assert folded_bytes == step_bytes and summary_bytes > 0
+    assert ma == mb
+    for n in STATE:
+        assert np.array_equal(a.fetch(n), b.fetch(n)), n
+    a.close()
+    b.close()

@@ -272,3 +272,34 @@ def test_storage_layout_and_host_round_trip(ndim, dims, halo):
         f = c.decl_field("f%d" % cen[0], cen, init)
         assert np.array_equal(c.fetch_field(f, cen), init)
     c.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_field_summary_folds_into_the_step_chain(dim):
+    # A diagnostic sum queued after a step joins the step's chain (its SUM
+    # reduction is not read in the chain, so nothing splits it) and reads only
+    # fields the chain holds anyway: the transfer sets are the step's own.
+    if dim == 2:
+        from paper_1709_02125_amd import hydro2d as hm
+        n = (24, 300)
+        make = lambda: hm.Hydro2D(n[0], n[1], np.full(n[::-1], 0.2), np.full(n[::-1], 1.0),
+                                  budget=hm.device_footprint_bytes(*n) // 3, bind=False)
+    else:
+        from paper_1709_02125_amd import hydro3d as hm
+        n = (16, 12, 120)
+        make = lambda: hm.Hydro3D(n, np.full(n[::-1], 0.2), np.full(n[::-1], 1.0),
+                                  budget=hm.device_footprint_bytes(n) // 3, bind=False)
+    plans = []
+    for fold in (False, True):
+        app = make()
+        app.ctx.set_flags(ooc.FLAG_CYCLIC, 0)
+        app.queue_step()
+        if fold:
+            app.queue_mass()
+        plans.append(app.ctx.debug_plan())
+        app.close()
+    step, folded = plans
+    assert folded["nloops"] == step["nloops"] + 1
+    assert folded["ntiles"] == step["ntiles"]
+    for key in ("up", "down"):
+        assert np.array_equal(folded[key], step[key]), key
