@@ -299,7 +299,7 @@ def committed_traffic(kernel, workload):
 
 
 def link_probe(nbytes=1 << 30):
-    """Host-link peak as this box delivers it: one pinned 1 GiB buffer copied
+    """Host-link peak as this machine delivers it: one pinned 1 GiB buffer copied
     to the device, then back, by the runtime (GB/s each way)."""
     import torch
     h = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
