@@ -27,6 +27,22 @@ def test_hydro3d_tiled_matches_oracle_step_by_step():
     assert abs(mass - omass) <= 1e-13 * omass
 
 
+def test_hydro3d_two_block_columns_match_oracle():
+    # x spans two 64-wide block columns with a ragged tail (70 = 64 + 6): the
+    # carried z-walk kernels and the cell/node stencils cross block columns;
+    # tiled along z at a third of the footprint, against the oracle
+    n, steps = (70, 20, 120), 3
+    say("case: hydro3d 70x20x120 two block columns, tiled, vs oracle")
+    got, gdts, st, _ = gpu_hydro3d(n, steps, flags=ooc.FLAG_PREFETCH)
+    ref, odts, _ = oracle_hydro3d(n, steps)
+    assert st["ntiles_last"] > 2
+    for name in STATE3:
+        e = rel_err(got[name], ref[name])
+        say(name, e)
+        assert e <= TOL, name
+    assert abs(gdts[-1] - odts[-1]) <= TOL * odts[-1]
+
+
 def test_hydro3d_incore_matches_oracle():
     n, steps = (33, 29, 27), 5
     say("case: hydro3d in-core vs oracle")

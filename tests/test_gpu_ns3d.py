@@ -67,3 +67,25 @@ def test_ns3d_conserves_mass_and_energy_on_gpu():
     for q in ("q_r", "q_re"):
         m0, m1 = z[q].sum(), got[q].sum()
         assert abs(m1 - m0) <= 1e-13 * abs(m0), q
+
+
+def test_ns3d_two_block_columns_match_oracle_and_incore():
+    # x spans two 64-wide block columns with a ragged tail (72 = 64 + 8; the
+    # gradients' range starts at -2), so the marching kernels' x-halo loads
+    # cross blocks; tiled with 2-step chains against in-core (bit-exact) and
+    # in-core against the oracle
+    n, steps = 72, 2
+    say("case: ns3d 72^3 two block columns, tiled vs in-core vs oracle")
+    got, st = gpu_ns(n, steps, tile_rows=9, chain_steps=2)
+    ref, _ = gpu_ns(n, steps, incore=True)
+    assert st["ntiles_last"] >= 4
+    o = on.NS3D(n)
+    o.set_primitives(*tgv_initial_state(n))
+    for _ in range(steps):
+        o.step(on.stable_dt(n))
+    for q in N.Q:
+        assert np.array_equal(got[q], ref[q]), q
+        e = rel_err(ref[q], o.interior(q))
+        say(q, e)
+        assert e <= TOL, q
+
