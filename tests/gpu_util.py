@@ -97,6 +97,7 @@ def gpu_hydro3d(n, steps, budget=None, flags=0, tile_rows=0, slots=0, incore=Fal
         dts.append(app.ctx.reduce(app.dt))
     out = {name: app.fetch(name) for name in STATE3}
     st = app.ctx.stats()   # of the last step's chain
+    assert st["host_pageable_bytes"] == 0 and st["host_pinned_bytes"] > 0, st
     app.queue_mass()
     mass = app.ctx.reduce(app.mass)
     app.close()

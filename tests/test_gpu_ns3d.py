@@ -25,6 +25,7 @@ def gpu_ns(n, steps, tile_rows=0, chain_steps=0, slots=0, incore=False, flags=0,
     app.run(steps)
     out = {q: app.interior(q) for q in N.Q}
     st = app.ctx.stats()
+    assert st["host_pageable_bytes"] == 0 and st["host_pinned_bytes"] > 0, st
     app.close()
     return out, st
 
