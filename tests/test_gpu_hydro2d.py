@@ -178,6 +178,15 @@ def test_hydro2d_fp32_streaming_error_is_stated_and_tiling_independent():
     say("fp32 streaming max rel error after %d steps:" % steps, errs)
     for n, e in errs.items():
         assert e < 1e-4, (n, e)
+    # geometry streamed too: chains move 4 fields down for 7 up, so the
+    # download kernel runs on its narrow grid (converting in flight)
+    d, _, std = gpu_hydro(nx, ny, steps, flags=flags, budget=h2.device_footprint_bytes(nx, ny) // 3)
+    e, _, _ = gpu_hydro(nx, ny, steps, flags=flags, tile_rows=6, slots=3,
+                        budget=h2.device_footprint_bytes(nx, ny))
+    assert std["ntiles_last"] > 2
+    for n in STATE:
+        assert np.array_equal(d[n], e[n]), n
+        assert rel_err(d[n], ref[n]) < 1e-4, n
 
 
 def test_hydro2d_field_summary_folded_into_the_step_chain():
