@@ -261,6 +261,27 @@ def timed_run(app, steps, warmup, knames, dom=None, timing=True):
     return d
 
 
+def tile_stage_summary(app):
+    """One more, untimed step with per-tile stage events on the three
+    streams: the average duration per tile of the upload, compute, edge-copy
+    and download stages, and the span of the step from the first upload to
+    the last download (ms)."""
+    app.ctx.set_tile_timing(True)
+    app.run(1)
+    recs = app.ctx.tile_times()
+    app.ctx.set_tile_timing(False)
+    if not recs:
+        return None
+
+    def avg(a, b):
+        return round(sum(r[b] - r[a] for r in recs) / len(recs) / 1e3, 3)
+
+    span = (max(r["d2h_end_us"] for r in recs) - min(r["h2d_begin_us"] for r in recs)) / 1e3
+    return {"tiles": len(recs), "h2d_ms": avg("h2d_begin_us", "h2d_end_us"),
+            "compute_ms": avg("comp_begin_us", "comp_end_us"), "edge_ms": avg("comp_end_us", "edge_end_us"),
+            "d2h_ms": avg("d2h_begin_us", "d2h_end_us"), "step_span_ms": round(span, 2)}
+
+
 def roofline_of(r, knames, where):
     """Dominant kernel (most time) of a timed run: algorithmic bytes per
     launch / average launch time, against the HBM peak."""
@@ -388,6 +409,7 @@ def main():
     app.initialise()
     log("out-of-core setup %.1f s" % (time.perf_counter() - t))
     ooc_r = timed_run(app, args.steps, args.warmup, w.knames, w.dominant)
+    tile_stages = tile_stage_summary(app)
     app.close()
     del app
     torch.cuda.empty_cache()
@@ -480,6 +502,7 @@ def main():
         "link": link,
         "variants": variants,
         "cpu_baseline": cpu,
+        "ooc_tile_stages": tile_stages,
         "ooc_warmup_kernel_ms": {w.knames[k]: round(v, 2) for k, v in ooc_r.get("warmup_kernel_ms", {}).items()},
     }
     print(json.dumps(out), flush=True)

@@ -216,6 +216,27 @@ int ooc_get_layout(ooc_ctx *ctx, int64_t *pitch, int64_t *plane, int64_t *x_orig
  * Every call clears the accumulated per-kernel figures. */
 int ooc_set_timing(ooc_ctx *ctx, int on);
 
+/* Per-tile stage timing (hipEvents on the three streams), from the next
+ * flush on while on != 0: for every tile, the begin and end of its upload
+ * stage (upload stream, after the wait for its slot), of its loops and of its
+ * edge copy (compute stream, after the wait for its uploads) and of its
+ * download stage (download stream, after the wait for its compute).  Times
+ * are microseconds from the first tile's upload begin of the collected
+ * period: the tiles issued since the previous waiting flush. */
+typedef struct {
+  int64_t tile;                       /* global tile index */
+  float h2d_begin_us, h2d_end_us;     /* upload stage */
+  float comp_begin_us, comp_end_us;   /* loops of the tile */
+  float edge_end_us;                  /* edge copy to the next slot, from comp_end_us */
+  float d2h_begin_us, d2h_end_us;     /* download stage */
+} ooc_tile_time;
+int ooc_set_tile_timing(ooc_ctx *ctx, int on);
+
+/* The records of the last collected period (see ooc_set_tile_timing): *count
+ * receives their number; min(capacity, count) records are copied to out (out
+ * may be NULL to query the count).  Returns OOC_E_ARG if count is NULL. */
+int ooc_tile_times(ooc_ctx *ctx, ooc_tile_time *out, int capacity, int *count);
+
 /* Accumulated timing of one kernel id over the flushes since timing was
  * enabled: summed launch time (ms, hipEvents on the compute stream), launch
  * count and algorithmic bytes (Section 5.1 rule: 1x per read or written

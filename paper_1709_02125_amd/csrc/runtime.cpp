@@ -106,6 +106,16 @@ struct ooc_ctx {
   std::vector<hipEvent_t> tev_pool;
   size_t tev_next = 0;
   std::map<int, KStat> kstats;
+  // per-tile stage events (ooc_set_tile_timing): 7 per tile, pooled
+  bool tile_timing = false;
+  struct TileEv {
+    int64_t g;
+    hipEvent_t e[7];  // h2d begin/end, compute begin/end, edge end, d2h begin/end
+  };
+  std::vector<TileEv> tile_ev;
+  std::vector<hipEvent_t> tile_pool;
+  size_t tile_pool_next = 0;
+  std::vector<ooc_tile_time> tile_times;
   // per-chain launch-argument tables: device copy read by the kernels, pinned
   // host mirror it is uploaded from, cache keyed by chain and slot phase
   KArgs *argtab_dev = nullptr, *argtab_host = nullptr;
@@ -170,6 +180,46 @@ void wait_tile(ooc_ctx *c, hipStream_t s, std::vector<hipEvent_t> &v, int64_t g)
   if (c->capture_g0 >= 0 && g < c->capture_g0) return;  // ordered before the graph instead
   hipEvent_t e = evref(v, c, g);
   timed_call(c, [&] { HIPCHK(hipStreamWaitEvent(s, e, 0)); }, 3);
+}
+
+// record stage k of the tile being issued (tile timing on)
+void tile_mark(ooc_ctx *c, int k, hipStream_t s) {
+  if (c->tile_ev.empty()) return;
+  hipEvent_t &e = c->tile_ev.back().e[k];
+  timed_call(c, [&] { HIPCHK(hipEventRecord(e, s)); }, kCallRecord);
+}
+
+void tile_begin(ooc_ctx *c, int64_t g) {
+  ooc_ctx::TileEv t;
+  t.g = g;
+  for (hipEvent_t &e : t.e) {
+    if (c->tile_pool_next == c->tile_pool.size()) {
+      hipEvent_t x;
+      HIPCHK(hipEventCreate(&x));
+      c->tile_pool.push_back(x);
+    }
+    e = c->tile_pool[c->tile_pool_next++];
+  }
+  c->tile_ev.push_back(t);
+}
+
+// turn the stage events of the tiles issued since the last collection into
+// microseconds from the first tile's upload begin (after a device sync)
+void collect_tile_times(ooc_ctx *c) {
+  if (c->tile_ev.empty()) return;
+  c->tile_times.clear();
+  const hipEvent_t base = c->tile_ev[0].e[0];
+  for (const ooc_ctx::TileEv &t : c->tile_ev) {
+    float us[7];
+    for (int k = 0; k < 7; k++) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, base, t.e[k]));
+      us[k] = ms * 1e3f;
+    }
+    c->tile_times.push_back({t.g, us[0], us[1], us[2], us[3], us[4], us[5], us[6]});
+  }
+  c->tile_ev.clear();
+  c->tile_pool_next = 0;
 }
 
 hipEvent_t timing_event(ooc_ctx *c) {
@@ -652,6 +702,10 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       if (t == 0) launch_fill((double *)slot, P.slot_bytes / 8, NAN, c->s_up);
       else wait_tile(c, c->s_up, c->ev_comp, g - 1);
     }
+    if (c->tile_timing && c->capture_g0 < 0) {
+      tile_begin(c, g);
+      tile_mark(c, 0, c->s_up);
+    }
     int64_t waited = -1;
     uint64_t stage_up = 0, stage_down = 0;
     const bool kcopy = (c->flags & OOC_FLAG_KERNEL_COPY) != 0;
@@ -688,10 +742,12 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       timed_call(c, [&] { launch_xfer_segments(xup.data(), (int)xup.size(), false, false, c->s_up); }, kCallH2D);
       HIPCHK(hipGetLastError());
     }
+    if (c->tile_timing && c->capture_g0 < 0) tile_mark(c, 1, c->s_up);
     timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_up, c, g), c->s_up)); }, kCallRecord);
     if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_up));
     // ---- execute every loop of the chain over its rows of this tile
     timed_call(c, [&] { HIPCHK(hipStreamWaitEvent(c->s_comp, evref(c->ev_up, c, g), 0)); }, kCallWait);
+    if (c->tile_timing && c->capture_g0 < 0) tile_mark(c, 2, c->s_comp);
     const bool fuse = (c->flags & OOC_FLAG_FUSE) && !c->timing;
     std::vector<const KArgs *> bh, bd;  // pending batch of independent mirror loops
     std::vector<int> bl;
@@ -724,6 +780,7 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
         li++;
       }
     flush_batch();
+    if (c->tile_timing && c->capture_g0 < 0) tile_mark(c, 3, c->s_comp);
     // ---- hand the right edge to the next tile's slot (on the compute stream)
     const bool poison = (c->flags & OOC_FLAG_DEBUG_POISON) != 0;
     if (t + 1 < T && (poison || !edge[t + 1].empty())) {
@@ -750,10 +807,12 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
         else launch_red_commit(r.acc, r.committed, c->s_comp);
       }
     }
+    if (c->tile_timing && c->capture_g0 < 0) tile_mark(c, 4, c->s_comp);
     timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_comp, c, g), c->s_comp)); }, kCallRecord);
     if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_comp));
     // ---- download the left footprint of modified datasets
     timed_call(c, [&] { HIPCHK(hipStreamWaitEvent(c->s_down, evref(c->ev_comp, c, g), 0)); }, kCallWait);
+    if (c->tile_timing && c->capture_g0 < 0) tile_mark(c, 5, c->s_down);
     std::vector<XferSeg> xdown;
     for (const Run *r : down[t]) {
       Field &f = c->fields[r->f];
@@ -787,6 +846,7 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
                  kCallD2H);
       HIPCHK(hipGetLastError());
     }
+    if (c->tile_timing && c->capture_g0 < 0) tile_mark(c, 6, c->s_down);
     timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_down, c, g), c->s_down)); }, kCallRecord);
     if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_down));
   }
@@ -904,6 +964,7 @@ int flush(ooc_ctx *c, bool wait = true) {
     if (wait && c->ready && c->gtile - 1 > c->gsynced) {
       sync_all(c);
       if (c->timing) collect_timing(c);
+      collect_tile_times(c);
     }
     return OOC_OK;
   }
@@ -979,6 +1040,7 @@ int flush(ooc_ctx *c, bool wait = true) {
   if (!wait) return OOC_OK;
   sync_all(c);
   if (c->timing) collect_timing(c);
+  collect_tile_times(c);
   c->st.last_flush_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return OOC_OK;
 }
@@ -1315,6 +1377,20 @@ int ooc_set_timing(ooc_ctx *c, int on) {
   return OOC_OK;
 }
 
+int ooc_set_tile_timing(ooc_ctx *c, int on) {
+  GUARD(c);
+  c->tile_timing = on != 0;
+  return OOC_OK;
+}
+
+int ooc_tile_times(ooc_ctx *c, ooc_tile_time *out, int capacity, int *count) {
+  if (!c || !count || capacity < 0) return OOC_E_ARG;
+  *count = (int)c->tile_times.size();
+  if (out)
+    for (int i = 0; i < capacity && i < *count; i++) out[i] = c->tile_times[i];
+  return OOC_OK;
+}
+
 int ooc_kernel_stats(ooc_ctx *c, int kid, double *ms, uint64_t *launches, uint64_t *bytes) {
   if (!c) return OOC_E_ARG;
   auto it = c->kstats.find(kid);
@@ -1337,7 +1413,7 @@ int ooc_destroy(ooc_ctx *c) {
   for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second.exec);
   for (hipEvent_t e : {c->ev_fork, c->ev_join_c, c->ev_join_d, c->ev_pre, c->ev_post})
     if (e) (void)hipEventDestroy(e);
-  for (auto *v : {&c->ev_up, &c->ev_comp, &c->ev_down, &c->tev_pool})
+  for (auto *v : {&c->ev_up, &c->ev_comp, &c->ev_down, &c->tev_pool, &c->tile_pool})
     for (hipEvent_t e : *v) (void)hipEventDestroy(e);
   for (size_t k = 0; k < c->fields.size(); k++) free_host(c->fields[k].host, c->pinned[k]);
   if (c->argtab_host) free_host(c->argtab_host, true);

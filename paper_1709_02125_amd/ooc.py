@@ -51,6 +51,12 @@ class ooc_stats(ctypes.Structure):
                 ("host_pinned_bytes", ctypes.c_uint64), ("host_pageable_bytes", ctypes.c_uint64)]
 
 
+class ooc_tile_time(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int64), ("h2d_begin_us", ctypes.c_float), ("h2d_end_us", ctypes.c_float),
+                ("comp_begin_us", ctypes.c_float), ("comp_end_us", ctypes.c_float),
+                ("edge_end_us", ctypes.c_float), ("d2h_begin_us", ctypes.c_float), ("d2h_end_us", ctypes.c_float)]
+
+
 class ooc_plan_info(ctypes.Structure):
     _fields_ = [("ntiles", ctypes.c_int32), ("nloops", ctypes.c_int32), ("nfields", ctypes.c_int32),
                 ("slots", ctypes.c_int32), ("tile_rows", ctypes.c_int64), ("slot_bytes", ctypes.c_uint64),
@@ -62,7 +68,7 @@ class ooc_plan_info(ctypes.Structure):
 
 EXPORTS = ["ooc_create", "ooc_bind_device", "ooc_decl_field", "ooc_decl_reduction", "ooc_set_reduction",
            "ooc_par_loop", "ooc_mark_step", "ooc_discard_queue", "ooc_execute", "ooc_submit", "ooc_reduce", "ooc_fetch_field",
-           "ooc_set_field", "ooc_set_flags", "ooc_set_schedule", "ooc_get_stats", "ooc_set_timing",
+           "ooc_set_field", "ooc_set_flags", "ooc_set_schedule", "ooc_get_stats", "ooc_set_timing", "ooc_set_tile_timing", "ooc_tile_times",
            "ooc_kernel_stats", "ooc_last_error", "ooc_destroy", "ooc_debug_plan", "ooc_field_shape", "ooc_get_layout",
            "ooc_mlp_create", "ooc_mlp_num_params", "ooc_mlp_get_params", "ooc_mlp_set_params",
            "ooc_mlp_predict", "ooc_mlp_gradient", "ooc_mlp_train", "ooc_mlp_destroy"]
@@ -106,6 +112,8 @@ def load_library() -> ctypes.CDLL:
         "ooc_get_stats": [P, ctypes.POINTER(ooc_stats)],
         "ooc_get_layout": [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)],
         "ooc_set_timing": [P, I],
+        "ooc_set_tile_timing": [P, I],
+        "ooc_tile_times": [P, ctypes.POINTER(ooc_tile_time), I, ctypes.POINTER(I)],
         "ooc_kernel_stats": [P, I, DP, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
         "ooc_last_error": [P],
         "ooc_destroy": [P],
@@ -321,6 +329,19 @@ class Context:
         s = ooc_stats()
         self._check(self.lib.ooc_get_stats(self._h, ctypes.byref(s)))
         return {n: getattr(s, n) for n, _ in ooc_stats._fields_}
+
+    def set_tile_timing(self, on: bool = True):
+        """Per-tile stage events on the three streams from the next flush on."""
+        self._check(self.lib.ooc_set_tile_timing(self._h, 1 if on else 0))
+
+    def tile_times(self) -> list:
+        """Stage times (us) of the tiles of the last collected period, one dict
+        per tile: tile, h2d_begin/end, comp_begin/end, edge_end, d2h_begin/end."""
+        n = ctypes.c_int32()
+        self._check(self.lib.ooc_tile_times(self._h, None, 0, ctypes.byref(n)))
+        buf = (ooc_tile_time * max(1, n.value))()
+        self._check(self.lib.ooc_tile_times(self._h, buf, n.value, ctypes.byref(n)))
+        return [{f: getattr(buf[i], f) for f, _ in ooc_tile_time._fields_} for i in range(n.value)]
 
     def kernel_stats(self, kid: int):
         ms = ctypes.c_double()

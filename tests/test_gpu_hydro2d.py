@@ -223,3 +223,35 @@ def test_hydro2d_field_summary_folded_into_the_step_chain():
         assert np.array_equal(a.fetch(n), b.fetch(n)), n
     a.close()
     b.close()
+
+
+def test_hydro2d_tile_stage_timing_follows_the_pipeline():
+    # per-tile stage events on the three streams: each tile's compute begins
+    # after its upload ends, its download after its compute and edge copy;
+    # the upload into a slot begins after the download of the tile that held
+    # the slot before it (S tiles earlier)
+    nx, ny, slots = 64, 300, 3
+    say("case: tile stage timing", nx, ny, slots)
+    from paper_1709_02125_amd.inputs import hydro_initial_state
+    rho, ene = hydro_initial_state((nx, ny))
+    app = h2.Hydro2D(nx, ny, rho, ene, budget=h2.device_footprint_bytes(nx, ny))
+    app.ctx.set_schedule(tile_rows=20, slots=slots)
+    app.initialise()
+    app.ctx.set_tile_timing(True)
+    app.run(2)
+    recs = app.ctx.tile_times()
+    st = app.ctx.stats()
+    app.close()
+    assert st["ntiles_last"] >= 2 * slots
+    assert len(recs) == 2 * st["ntiles_last"]
+    by = {r["tile"]: r for r in recs}
+    eps = 1.0   # us
+    order = ["h2d_begin_us", "h2d_end_us", "comp_begin_us", "comp_end_us", "edge_end_us", "d2h_begin_us",
+             "d2h_end_us"]
+    for r in recs:
+        for a, b in zip(order, order[1:]):
+            assert r[a] <= r[b] + eps, (r["tile"], a, b, r)
+        prev = by.get(r["tile"] - slots)
+        if prev is not None:
+            assert prev["d2h_end_us"] <= r["h2d_begin_us"] + eps, (r["tile"], prev, r)
+    assert recs[0]["h2d_begin_us"] == 0.0 and recs[-1]["d2h_end_us"] > 0.0
