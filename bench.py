@@ -337,6 +337,66 @@ def link_probe(nbytes=1 << 30):
     return out
 
 
+def hbm_copy_probe(nbytes=4 << 30, reps=3):
+    """HBM bandwidth a plain device copy reaches here: 4 GiB copied by the
+    runtime's copy kernel, (read + written bytes) / best time, GB/s."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * nbytes / (best * 1e-3) / 1e9, 1)
+
+
+def link_both_probe(nbytes=1 << 30):
+    """Both link directions at once: 1 GiB up and 1 GiB down by the runtime on
+    two streams, each direction's rate from events on its own stream (GB/s)."""
+    import torch
+    hu = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    hd = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    du = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dd = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    su, sd = torch.cuda.Stream(), torch.cuda.Stream()
+    rates = None
+    for _ in range(2):   # the first pass warms both paths
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        torch.cuda.synchronize()
+        with torch.cuda.stream(su):
+            ev[0].record()
+            du.copy_(hu, non_blocking=True)
+            ev[1].record()
+        with torch.cuda.stream(sd):
+            ev[2].record()
+            hd.copy_(dd, non_blocking=True)
+            ev[3].record()
+        torch.cuda.synchronize()
+        rates = (round(nbytes / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9, 2),
+                 round(nbytes / (ev[2].elapsed_time(ev[3]) * 1e-3) / 1e9, 2))
+    del hu, hd, du, dd
+    torch.cuda.empty_cache()
+    return rates
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def copy_probe(nbytes=1 << 30, reps=3):
     """A plain device copy of known size (counter calibration for rocprofv3)."""
     import torch
@@ -459,22 +519,41 @@ def main():
         roofline["traffic"] = committed_traffic(roofline["kernel"], args.workload)
     incore_roofline = roofline_of(inc_r, w.knames, "in-core timed steps") if inc_r else None
     probe_h2d, probe_d2h = link_probe()
+    both_h2d, both_d2h = link_both_probe()
+    hbm_copy = hbm_copy_probe()
+    if roofline:
+        roofline["copy_probe_GBs"] = hbm_copy
     link = {"h2d_GBs": round(ooc_r["bytes_h2d"] / ooc_r["seconds"] / 1e9, 2),
             "d2h_GBs": round(ooc_r["bytes_d2h"] / ooc_r["seconds"] / 1e9, 2),
             "peak_per_direction_GBs": LINK_PEAK_GBS,
             "probe_h2d_GBs": probe_h2d, "probe_d2h_GBs": probe_d2h,
+            "probe_both_h2d_GBs": both_h2d, "probe_both_d2h_GBs": both_d2h,
             "h2d_frac_of_probe": round(ooc_r["bytes_h2d"] / ooc_r["seconds"] / 1e9 / probe_h2d, 3),
             "h2d_bytes_per_step": ooc_r["bytes_h2d"] // args.steps,
             "d2h_bytes_per_step": ooc_r["bytes_d2h"] // args.steps,
             "edge_bytes_per_step": ooc_r["bytes_edge"] // args.steps}
     avg_bw = ooc_r["bytes_hbm_alg"] / ooc_r["seconds"] / 1e9
+    # out-of-core ceiling (an upper bound): the slowest of HBM (copy probe) over
+    # the algorithmic bytes and each link direction (its own probe) over its
+    # bytes, per cell and step, assuming the three streams overlap perfectly.
+    # (Both directions at once the runtime's copies reach less; the concurrent
+    # probe is reported beside it.)
+    per_cell = lambda b: b / (w.cells * args.steps)
+    terms = {"hbm": hbm_copy * 1e9 / per_cell(ooc_r["bytes_hbm_alg"])}
+    if ooc_r["bytes_h2d"]:
+        terms["h2d"] = probe_h2d * 1e9 / per_cell(ooc_r["bytes_h2d"])
+    if ooc_r["bytes_d2h"]:
+        terms["d2h"] = probe_d2h * 1e9 / per_cell(ooc_r["bytes_d2h"])
+    bound = min(terms, key=terms.get)
+    ceiling = {"value": terms[bound], "bound": bound, "terms": {k: round(v) for k, v in terms.items()},
+               "frac": round(ooc_rate / terms[bound], 3)}
 
     cpu = None
     if not args.no_cpu:
         import oracle
         val, sample = w.cpu_baseline()
         cpu = {"value": val, "unit": "grid-point updates/s", "cores": int(oracle.load().oracle_threads()),
-               "kind": "oracle", "sample": sample}
+               "kind": "oracle", "sample": sample, "cpu_model": cpu_model()}
         log("cpu oracle: %.3g upd/s on %d threads" % (cpu["value"], cpu["cores"]))
 
     ms_step = ooc_r["seconds"] / args.steps * 1e3
@@ -500,6 +579,7 @@ def main():
         "roofline": roofline,
         "incore_roofline": incore_roofline,
         "link": link,
+        "ooc_ceiling": ceiling,
         "variants": variants,
         "cpu_baseline": cpu,
         "ooc_tile_stages": tile_stages,
