@@ -39,6 +39,15 @@ NS_NAMES = ["ns_init", "ns_prims", "ns_grads", "ns_rhs_first", "ns_rhs"]
 COMMON = {1: "mirror", 2: "fill", 3: "sum_prod"}
 
 
+def ablations(pf):
+    """The two other combinations of the transfer optimisations the paper
+    evaluates (Section 4.1, measured in Section 5.3) beside the headline's
+    Prefetch + Cyclic: speculative Prefetch off (a chain's first tile is
+    uploaded only once the previous chain's last tile has run), and both
+    Prefetch and Cyclic off (write-first data is downloaded too)."""
+    return [("no_prefetch_cyclic", 0, {}), ("no_prefetch_no_cyclic", 0, {"cyclic": False})]
+
+
 class Workload:
     """One benchmark problem: how to build the app at a budget, its sizes,
     kernel names, and its CPU-oracle sample."""
@@ -69,13 +78,14 @@ class Hydro2DWork(Workload):
                               flags=flags)
         return h2.Hydro2D(self.n, self.n, self.rho, self.ene, budget=budget, flags=flags,
                           resident_geometry=opts.get("resident_geometry", self.args.resident_geometry),
-                          cyclic_after_init=not self.args.no_cyclic,
+                          cyclic_after_init=opts.get("cyclic", not self.args.no_cyclic),
                           resident_state=opts.get("resident_state", self.args.resident_state))
 
     def variants(self):
         from paper_1709_02125_amd import ooc
         pf = ooc.FLAG_PREFETCH
-        return [("fp32_stream_resident_geometry", pf | ooc.FLAG_FP32_STREAM, {"resident_geometry": True}),
+        return [*ablations(pf),
+                ("fp32_stream_resident_geometry", pf | ooc.FLAG_FP32_STREAM, {"resident_geometry": True}),
                 ("resident_geometry", pf, {"resident_geometry": True}),
                 ("resident_state", pf, {"resident_state": True}),
                 ("resident_state_fused", pf | ooc.FLAG_FUSE, {"resident_state": True})]
@@ -128,13 +138,14 @@ class Hydro3DWork(Workload):
                               flags=flags)
         return h3.Hydro3D(self.dims, self.rho, self.ene, budget=budget, flags=flags,
                           resident_geometry=opts.get("resident_geometry", self.args.resident_geometry),
-                          cyclic_after_init=not self.args.no_cyclic,
+                          cyclic_after_init=opts.get("cyclic", not self.args.no_cyclic),
                           resident_state=opts.get("resident_state", self.args.resident_state))
 
     def variants(self):
         from paper_1709_02125_amd import ooc
         pf = ooc.FLAG_PREFETCH
-        return [("fp32_stream_resident_geometry", pf | ooc.FLAG_FP32_STREAM, {"resident_geometry": True}),
+        return [*ablations(pf),
+                ("fp32_stream_resident_geometry", pf | ooc.FLAG_FP32_STREAM, {"resident_geometry": True}),
                 ("resident_geometry", pf, {"resident_geometry": True})]
 
     def describe(self):
@@ -181,7 +192,7 @@ class NS3DWork(Workload):
         N = self.mod
         if incore:
             return N.NS3D(self.n, self.prims, budget=N.device_footprint_bytes(self.n), flags=flags)
-        app = N.NS3D(self.n, self.prims, budget=budget, flags=flags, cyclic_after_init=not self.args.no_cyclic)
+        app = N.NS3D(self.n, self.prims, budget=budget, flags=flags, cyclic_after_init=opts.get("cyclic", not self.args.no_cyclic))
         app.ctx.set_schedule(tile_rows=opts.get("tile_rows", self.args.tile_rows),
                              chain_steps=opts.get("chain_steps", self.args.chain_steps),
                              slots=opts.get("slots", self.args.slots))
@@ -190,7 +201,8 @@ class NS3DWork(Workload):
     def variants(self):
         from paper_1709_02125_amd import ooc
         pf = ooc.FLAG_PREFETCH
-        return [("default_schedule_1_step_chains", pf, {"chain_steps": 1, "tile_rows": 0, "slots": 3}),
+        return [*ablations(pf),
+                ("default_schedule_1_step_chains", pf, {"chain_steps": 1, "tile_rows": 0, "slots": 3}),
                 ("chains_of_2_steps_largest_tiles", pf, {"chain_steps": 2, "tile_rows": 0, "slots": 3}),
                 ("fp32_stream_swept_schedule", pf | ooc.FLAG_FP32_STREAM,
                  {"chain_steps": 2, "tile_rows": 32, "slots": 2})]
