@@ -273,13 +273,14 @@ def timed_run(app, steps, warmup, knames, dom=None, timing=True):
     return d
 
 
-def tile_stage_summary(app):
-    """One more, untimed step with per-tile stage events on the three
-    streams: the average duration per tile of the upload, compute, edge-copy
-    and download stages, and the span of the step from the first upload to
-    the last download (ms)."""
+def tile_stage_summary(app, steps=1):
+    """One more, untimed chain of `steps` steps (the workload's chain length)
+    with per-tile stage events on the three streams: the average duration per
+    tile of the upload, compute, edge-copy and download stages, and the span
+    of the chain from the first upload to the last download (ms), also per
+    step."""
     app.ctx.set_tile_timing(True)
-    app.run(1)
+    app.run(steps)
     recs = app.ctx.tile_times()
     app.ctx.set_tile_timing(False)
     if not recs:
@@ -289,9 +290,12 @@ def tile_stage_summary(app):
         return round(sum(r[b] - r[a] for r in recs) / len(recs) / 1e3, 3)
 
     span = (max(r["d2h_end_us"] for r in recs) - min(r["h2d_begin_us"] for r in recs)) / 1e3
-    return {"tiles": len(recs), "h2d_ms": avg("h2d_begin_us", "h2d_end_us"),
+    return {"steps": steps, "tiles": len(recs), "h2d_ms": avg("h2d_begin_us", "h2d_end_us"),
             "compute_ms": avg("comp_begin_us", "comp_end_us"), "edge_ms": avg("comp_end_us", "edge_end_us"),
-            "d2h_ms": avg("d2h_begin_us", "d2h_end_us"), "step_span_ms": round(span, 2)}
+            "d2h_ms": avg("d2h_begin_us", "d2h_end_us"), "chain_span_ms": round(span, 2),
+            "step_span_ms": round(span / steps, 2),
+            # share of the span the compute stream is busy (compute + edge copy)
+            "compute_busy_frac": round(sum(r["edge_end_us"] - r["comp_begin_us"] for r in recs) / 1e3 / span, 3)}
 
 
 def roofline_of(r, knames, where):
@@ -481,7 +485,7 @@ def main():
     app.initialise()
     log("out-of-core setup %.1f s" % (time.perf_counter() - t))
     ooc_r = timed_run(app, args.steps, args.warmup, w.knames, w.dominant)
-    tile_stages = tile_stage_summary(app)
+    tile_stages = tile_stage_summary(app, args.chain_steps if args.workload == "ns3d" else 1)
     app.close()
     del app
     torch.cuda.empty_cache()
