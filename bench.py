@@ -273,7 +273,7 @@ def timed_run(app, steps, warmup, knames, dom=None, timing=True):
     return d
 
 
-def tile_stage_summary(app, steps=1):
+def tile_stage_summary(app, steps=1, log_path=None):
     """One more, untimed chain of `steps` steps (the workload's chain length)
     with per-tile stage events on the three streams: the average duration per
     tile of the upload, compute, edge-copy and download stages, and the span
@@ -285,6 +285,10 @@ def tile_stage_summary(app, steps=1):
     app.ctx.set_tile_timing(False)
     if not recs:
         return None
+    if log_path:  # the raw per-tile records, one JSON object per line
+        with open(log_path, "w") as fh:
+            for r in recs:
+                fh.write(json.dumps(r) + "\n")
 
     def avg(a, b):
         return round(sum(r[b] - r[a] for r in recs) / len(recs) / 1e3, 3)
@@ -446,6 +450,8 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=None, help="tile height (default: largest that fits; ns3d: 24)")
     ap.add_argument("--chain-steps", type=int, default=3, help="ns3d: time steps per chain")
     ap.add_argument("--no-variants", action="store_true", help="skip the other schedules of the same grid")
+    ap.add_argument("--tile-log", default=None,
+                    help="write the per-tile stage records of the staged chain to this file (JSON lines, us)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -485,7 +491,7 @@ def main():
     app.initialise()
     log("out-of-core setup %.1f s" % (time.perf_counter() - t))
     ooc_r = timed_run(app, args.steps, args.warmup, w.knames, w.dominant)
-    tile_stages = tile_stage_summary(app, args.chain_steps if args.workload == "ns3d" else 1)
+    tile_stages = tile_stage_summary(app, args.chain_steps if args.workload == "ns3d" else 1, args.tile_log)
     app.close()
     del app
     torch.cuda.empty_cache()
