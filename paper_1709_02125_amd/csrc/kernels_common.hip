@@ -296,6 +296,11 @@ struct XferTable {
 };
 constexpr int64_t kXferChunk = 4096;  // elements per block
 
+// four float64 values read as two 16-byte loads
+struct Double4 {
+  double2 lo, hi;
+};
+
 // A small grid strides over the chunks.  The copy is bound by the host link.
 // Its stores to host memory hold up other kernels' memory requests while they
 // sit in the queues towards the link (measured: a strip loop beside a
@@ -333,9 +338,13 @@ __device__ void xfer_chunk(const XferTable &t, int64_t b) {
   } else if (t.mode[s] == 1) {  // float32 -> float64, 2 elements per lane step
     xfer_range((const float2 *)t.src[s], (double2 *)t.dst[s], base / 2, end / 2,
                [](float2 v) { return make_double2((double)v.x, (double)v.y); });
-  } else {  // float64 -> float32 (round to nearest even)
+  } else if (t.mode[s] == 2) {  // float64 -> float32 (round to nearest even), 8-byte stores
     xfer_range((const double2 *)t.src[s], (float2 *)t.dst[s], base / 2, end / 2,
                [](double2 v) { return make_float2((float)v.x, (float)v.y); });
+  } else {  // the same, 4 elements per lane step: 16-byte stores like the float64 copy's
+    xfer_range((const Double4 *)t.src[s], (float4 *)t.dst[s], base / 4, end / 4, [](Double4 v) {
+      return make_float4((float)v.lo.x, (float)v.lo.y, (float)v.hi.x, (float)v.hi.y);
+    });
   }
 }
 

@@ -70,7 +70,9 @@ void launch_mirror_batch(const KArgs *const *host_args, const KArgs *const *dev_
                          void *stream);
 void launch_fill(double *dst, int64_t n, double value, void *stream);
 // host-link transfer by kernel: mode 0 copies n 16-byte units, mode 1 widens
-// n float32 to float64, mode 2 rounds n float64 to float32 (n even)
+// n float32 to float64, mode 2 rounds n float64 to float32 with 8-byte stores
+// (n even), mode 3 the same with 16-byte stores (n a multiple of 4, source
+// 32-byte and destination 16-byte aligned)
 struct XferSeg {
   const void *src;
   void *dst;

@@ -678,6 +678,13 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
   // blocks 239 ms per step, 8 blocks 270 ms).  Otherwise the wider grid
   // finishes each download sooner (C4: 8 blocks 111 ms, 2 blocks 121 ms).
   const bool narrow_down = chain_down * 5 <= chain_up * 3;
+  // Float32 downloads round on the way out.  A chain whose kernels move more
+  // than 60 times its link bytes through HBM is bound by its kernels: its
+  // downloads keep 8-byte host stores, which slow the stencils beside them
+  // less (ns3d 512^3 FP32: 82-85 against 90-91 ms per step with 16-byte
+  // stores); otherwise 16-byte stores move the rows faster (hydro2d 15360^2
+  // FP32 with resident geometry: 102 against 122 ms).
+  const int f32_down_mode = P.alg_bytes > 60 * (chain_up + chain_down) ? 2 : 3;
   for (const Run &r : P.edge) c->st.bytes_edge += (uint64_t)(r.hi - r.lo) * c->fields[r.f].row_elems * 8;
   const uint64_t launches0 = c->st.launches;
 
@@ -829,7 +836,10 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
         if (!f.host_dev) throw DeviceError("kernel copy needs device-mapped pinned host arrays");
         char *hdst = (char *)f.host_dev + r->lo * f.row_bytes_host();
         const int64_t elems = (r->hi - r->lo) * f.row_elems;
-        xdown.push_back(f.fp32 ? XferSeg{src, hdst, elems, 2} : XferSeg{src, hdst, (int64_t)nb / 16, 0});
+        if (f.fp32 && f32_down_mode == 3 && (elems % 4 || (uintptr_t)src % 32 || (uintptr_t)hdst % 16))
+          throw DeviceError("float32 download run not aligned for 4-element steps");
+        xdown.push_back(f.fp32 ? XferSeg{src, hdst, elems, f32_down_mode}
+                               : XferSeg{src, hdst, (int64_t)nb / 16, 0});
         continue;
       }
       if (f.fp32) {  // rounded to float32 (nearest even) in staging, then sent

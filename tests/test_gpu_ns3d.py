@@ -90,3 +90,46 @@ def test_ns3d_two_block_columns_match_oracle_and_incore():
         say(q, e)
         assert e <= TOL, q
 
+
+
+@pytest.mark.parametrize("k", [6, 2])
+def test_ns3d_fp32_streaming_matches_oracle_with_the_same_roundings(k):
+    # Extension: the streamed fields are stored on the host and moved as
+    # float32; compute stays float64 on the device.  The initial primitives
+    # are rounded once on the way in, and every chain of k steps rounds the
+    # conserved variables once on the way out, whatever the tiles -- so the
+    # float64 oracle doing the same roundings gives the same values.  With
+    # k = 6 the chain's kernels move more than 60x its link bytes and the
+    # download kernel keeps 8-byte host stores; with k = 2 it uses 16-byte
+    # stores.
+    n, steps = 24, 6
+    say("case: ns3d fp32 streaming, chains of", k)
+    prims = tgv_initial_state(n)
+    flags = ooc.FLAG_FP32_STREAM | ooc.FLAG_PREFETCH
+    got, st = gpu_ns(n, steps, tile_rows=6, chain_steps=k, slots=2, flags=flags, prims=prims)
+    assert st["ntiles_last"] >= 3
+    if k == 6:
+        other, _ = gpu_ns(n, steps, tile_rows=4, chain_steps=k, slots=3, flags=flags, prims=prims)
+        for q in N.Q:
+            assert np.array_equal(got[q], other[q]), q
+
+    def r32(x):
+        return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+    o = on.NS3D(n)
+    o.set_primitives(*[r32(p) for p in prims])
+
+    def round_conserved():
+        for q in N.Q:
+            fld = o.field(q)
+            fld[...] = r32(fld)
+
+    round_conserved()
+    for s in range(steps):
+        o.step(on.stable_dt(n))
+        if (s + 1) % k == 0:
+            round_conserved()
+    for q in N.Q:
+        e = rel_err(got[q], o.interior(q))
+        say(q, e)
+        assert e <= TOL, q
