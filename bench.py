@@ -579,7 +579,7 @@ def main():
         log("cpu oracle: %.3g upd/s on %d threads" % (cpu["value"], cpu["cores"]))
 
     ms_step = ooc_r["seconds"] / args.steps * 1e3
-    config = {"workload": w.describe(), "global_batch": w.cells, "seq_len": 1, "parallelism": "single-gpu",
+    config = {"workload": w.describe(), "cells": w.cells,
               "prefetch": not args.no_prefetch, "cyclic": not args.no_cyclic,
               "resident_geometry": args.resident_geometry, "resident_state": args.resident_state,
               "fp32_stream": args.fp32,
