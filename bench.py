@@ -302,6 +302,24 @@ def tile_stage_summary(app, steps=1, log_path=None):
             "compute_busy_frac": round(sum(r["edge_end_us"] - r["comp_begin_us"] for r in recs) / 1e3 / span, 3)}
 
 
+def ooc_ceiling(rate, cell_steps, bytes_hbm, bytes_h2d, bytes_d2h, hbm_GBs, h2d_GBs, d2h_GBs):
+    """Out-of-core ceiling (an upper bound, grid-point updates/s): the slowest
+    of HBM at the copy probe's rate over the algorithmic bytes, and of each
+    link direction at its own probe's rate over the bytes it moves, per cell
+    and step, as if the three streams overlapped perfectly.  (Both directions
+    at once the runtime's copies reach less; the concurrent probe is reported
+    beside it, not used here.)  `rate` is the measured updates/s; the result
+    carries its fraction of the ceiling."""
+    terms = {"hbm": hbm_GBs * 1e9 * cell_steps / bytes_hbm}
+    if bytes_h2d:
+        terms["h2d"] = h2d_GBs * 1e9 * cell_steps / bytes_h2d
+    if bytes_d2h:
+        terms["d2h"] = d2h_GBs * 1e9 * cell_steps / bytes_d2h
+    bound = min(terms, key=terms.get)
+    return {"value": terms[bound], "bound": bound, "terms": {k: round(v) for k, v in terms.items()},
+            "frac": round(rate / terms[bound], 3)}
+
+
 def roofline_of(r, knames, where):
     """Dominant kernel (most time) of a timed run: algorithmic bytes per
     launch / average launch time, against the HBM peak."""
@@ -555,20 +573,8 @@ def main():
             "d2h_bytes_per_step": ooc_r["bytes_d2h"] // args.steps,
             "edge_bytes_per_step": ooc_r["bytes_edge"] // args.steps}
     avg_bw = ooc_r["bytes_hbm_alg"] / ooc_r["seconds"] / 1e9
-    # out-of-core ceiling (an upper bound): the slowest of HBM (copy probe) over
-    # the algorithmic bytes and each link direction (its own probe) over its
-    # bytes, per cell and step, assuming the three streams overlap perfectly.
-    # (Both directions at once the runtime's copies reach less; the concurrent
-    # probe is reported beside it.)
-    per_cell = lambda b: b / (w.cells * args.steps)
-    terms = {"hbm": hbm_copy * 1e9 / per_cell(ooc_r["bytes_hbm_alg"])}
-    if ooc_r["bytes_h2d"]:
-        terms["h2d"] = probe_h2d * 1e9 / per_cell(ooc_r["bytes_h2d"])
-    if ooc_r["bytes_d2h"]:
-        terms["d2h"] = probe_d2h * 1e9 / per_cell(ooc_r["bytes_d2h"])
-    bound = min(terms, key=terms.get)
-    ceiling = {"value": terms[bound], "bound": bound, "terms": {k: round(v) for k, v in terms.items()},
-               "frac": round(ooc_rate / terms[bound], 3)}
+    ceiling = ooc_ceiling(ooc_rate, w.cells * args.steps, ooc_r["bytes_hbm_alg"], ooc_r["bytes_h2d"],
+                          ooc_r["bytes_d2h"], hbm_copy, probe_h2d, probe_d2h)
 
     cpu = None
     if not args.no_cpu:

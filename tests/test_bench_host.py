@@ -26,3 +26,24 @@ def test_workloads_build_on_host(name, n):
     assert all(isinstance(k, int) and isinstance(v, str) for k, v in w.knames.items())
     val, sample = w.cpu_baseline(target_s=0.5)
     assert val > 0 and sample
+
+
+def test_ooc_ceiling_is_the_slowest_stream():
+    # hydro2d 15360^2 per cell and step: 1168 algorithmic HBM bytes, 56 B up
+    # and 32 B down (FP64, every field streamed); probes 5000 / 57.5 / 57.1 GB/s
+    cells = 15360 * 15360 * 20
+    c = bench.ooc_ceiling(1.0e9, cells, 1168 * cells, 56 * cells, 32 * cells, 5000.0, 57.5, 57.1)
+    assert c["bound"] == "h2d"
+    assert c["value"] == pytest.approx(57.5e9 / 56)
+    assert c["terms"]["hbm"] == round(5000e9 / 1168) and c["terms"]["d2h"] == round(57.1e9 / 32)
+    assert c["frac"] == round(1.0e9 / (57.5e9 / 56), 3)
+    # in core nothing crosses the link: HBM alone bounds it
+    c = bench.ooc_ceiling(4.0e9, cells, 1168 * cells, 0, 0, 5000.0, 57.5, 57.1)
+    assert c["bound"] == "hbm" and set(c["terms"]) == {"hbm"}
+
+
+def test_ablation_variants_are_the_papers_combinations():
+    names = [v[0] for v in bench.ablations(2)]
+    assert names == ["no_prefetch_cyclic", "no_prefetch_no_cyclic"]
+    assert all(flags == 0 for _, flags, _ in bench.ablations(2))   # Prefetch off in both
+    assert bench.ablations(2)[1][2] == {"cyclic": False}
