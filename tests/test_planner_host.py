@@ -303,3 +303,105 @@ def test_field_summary_folds_into_the_step_chain(dim):
     assert folded["ntiles"] == step["ntiles"]
     for key in ("up", "down"):
         assert np.array_equal(folded[key], step[key]), key
+
+
+CENTRINGS3 = [(0, 0, 0), (1, 1, 1), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+
+
+def random_chain3(n, shapes, rng, nloops):
+    """Random valid toy loops in 3D (AVG / INC_ADD / MIRROR / FILL), tiled along z."""
+    fields = list(shapes)
+
+    def ext(cen):
+        return [(-H, n[a] + H + cen[a]) for a in range(3)]
+
+    loops, tries = [], 0
+    while len(loops) < nloops and tries < 4000:
+        tries += 1
+        kind = rng.choice(["avg", "avg", "avg", "inc", "mirror", "fill"])
+        fo = int(rng.choice(fields))
+        eo = ext(shapes[fo])
+        if kind == "fill":
+            r = []
+            for a in range(3):
+                lo = int(rng.integers(eo[a][0], eo[a][1]))
+                r.append((lo, int(rng.integers(lo + 1, eo[a][1] + 1))))
+            loops.append(tile_sim.ToyLoop(tile_sim.K_FILL, tuple(r), [(fo, WRITE, ((0, 0, 0),))],
+                                          [float(rng.standard_normal())]))
+            continue
+        if kind == "mirror":   # a boundary layer along one axis, read mirrored across it
+            ax, low = int(rng.integers(3)), bool(rng.integers(2))
+            dep = int(rng.integers(1, H + 1))
+            r = list(eo)
+            a0 = eo[ax][0] if low else eo[ax][1] - dep
+            r[ax] = (a0, a0 + dep)
+            off = [0, 0, 0]
+            off[ax] = 2 * dep if low else -2 * dep
+            loops.append(tile_sim.ToyLoop(tile_sim.K_MIRROR, tuple(r), [(fo, WRITE, ((0, 0, 0),)),
+                                                                        (fo, READ, (tuple(off),))],
+                                          [float(rng.choice([-1.0, 1.0]))]))
+            continue
+        fi = int(rng.choice([f for f in fields if f != fo] or fields))
+        ei = ext(shapes[fi])
+        if kind == "inc":
+            offs = ((0, 0, 0),)
+        else:
+            offs = tuple(tuple(int(v) for v in rng.integers(-2, 3, size=3)) for _ in range(int(rng.integers(1, 5))))
+        r = []
+        for a in range(3):
+            lo = max(eo[a][0], ei[a][0] - min(o[a] for o in offs))
+            hi = min(eo[a][1], ei[a][1] - max(o[a] for o in offs))
+            if hi <= lo:
+                break
+            if rng.random() < 0.6:
+                r.append((lo, hi))
+            else:
+                a0 = int(rng.integers(lo, hi))
+                r.append((a0, int(rng.integers(a0 + 1, hi + 1))))
+        if len(r) < 3:
+            continue
+        if kind == "inc":
+            loops.append(tile_sim.ToyLoop(tile_sim.K_INC_ADD, tuple(r), [(fo, INC, ((0, 0, 0),)), (fi, READ, offs)],
+                                          [0.5]))
+        else:
+            loops.append(tile_sim.ToyLoop(tile_sim.K_AVG, tuple(r), [(fo, WRITE, ((0, 0, 0),)), (fi, READ, offs)],
+                                          [float(rng.uniform(0.5, 1.5)), float(rng.standard_normal())]))
+    return loops
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_3d_chains_tiled_along_z_equal_untiled(seed):
+    # the planner's 3D form: tiles cut along z, plans replayed plane by plane
+    # on NaN-poisoned host slots against the untiled program
+    rng = np.random.default_rng(100 + seed)
+    n = (int(rng.integers(3, 6)), int(rng.integers(3, 6)), int(rng.integers(5, 12)))
+    nf = int(rng.integers(2, 5))
+    cens = [CENTRINGS3[int(rng.integers(len(CENTRINGS3)))] for _ in range(nf)]
+    loops = None
+    cyclic = bool(seed % 2)
+    planes = n[2] + 2 * H + 1
+    for slots in (2, 3):
+        for h in range(1, planes + 1, 2):
+            c = ooc.Context(3, n, H, 1 << 30, ooc.FLAG_CYCLIC if cyclic else 0, bind=False)
+            frng = np.random.default_rng(seed)
+            host, shapes = {}, {}
+            for f in range(nf):
+                init = frng.standard_normal(c.field_shape_for(cens[f]))
+                hnd = c.decl_field("f%d" % f, cens[f], init)
+                host[hnd], shapes[hnd] = init, cens[f]
+            if loops is None:
+                loops = random_chain3(n, shapes, rng, int(rng.integers(3, 10)))
+            c.set_schedule(tile_rows=h, slots=slots)
+            queue(c, loops)
+            p = c.debug_plan()
+            ref = tile_sim.run_untiled3(loops, host, H)
+            got = tile_sim.run_tiled3(loops, host, p, H, slots)
+            for f in host:
+                if cyclic and p["temporary"][f] and any(d[0] == f for lp in loops for d in lp.dats):
+                    continue  # host copy intentionally stale
+                assert np.array_equal(got[f], ref[f]), (seed, h, slots, f)
+            for i, lp in enumerate(loops):
+                lr = p["loop_rows"][i]
+                assert lr[0, 0] == lp.rng[2][0] and lr[-1, 1] == lp.rng[2][1]
+                assert all(lr[t, 1] == lr[t + 1, 0] for t in range(p["ntiles"] - 1))
+            c.close()

@@ -111,3 +111,94 @@ def run_tiled(loops, host, plan, H, slots):
             A = res[f, t, 0]
             arr[f][r0:r1] = slot[(s, f)][r0 - A:r1 - A]
     return arr
+
+
+# ---- the same in 3D: loops tiled along z, arrays indexed [k, j, i]
+
+def apply_loop3(loop, get, put, rows):
+    """Run one toy loop over its x and y ranges x its planes (a (lo, hi) along z)."""
+    (x0, x1), (y0, y1), _ = loop.rng
+    k0, k1 = rows
+    if k1 <= k0 or x1 <= x0 or y1 <= y0:
+        return
+    K, J, I = np.meshgrid(np.arange(k0, k1), np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
+    if loop.kid == K_AVG:
+        (fo, _, _), (fi, _, offs) = loop.dats
+        s = np.zeros(K.shape)
+        for (ox, oy, oz) in offs:
+            s = s + get(fi, I + ox, J + oy, K + oz)
+        put(fo, I, J, K, loop.consts[0] * (s / float(len(offs))) + loop.consts[1])
+    elif loop.kid == K_INC_ADD:
+        (fo, _, _), (fi, _, _) = loop.dats
+        put(fo, I, J, K, get(fo, I, J, K) + loop.consts[0] * get(fi, I, J, K))
+    elif loop.kid == K_MIRROR:
+        vals = []
+        for q in range(len(loop.dats) // 2):
+            fs, _, offs = loop.dats[2 * q + 1]
+            ox, oy, oz = offs[0]
+            vals.append(loop.consts[q] * get(fs, I + ox, J + oy, K + oz))
+        for q in range(len(loop.dats) // 2):
+            put(loop.dats[2 * q][0], I, J, K, vals[q])
+    elif loop.kid == K_FILL:
+        put(loop.dats[0][0], I, J, K, np.full(K.shape, loop.consts[0]))
+    else:
+        raise ValueError(loop.kid)
+
+
+def run_untiled3(loops, host, H):
+    arr = {f: a.copy() for f, a in host.items()}
+
+    def get(f, I, J, K):
+        return arr[f][K + H, J + H, I + H]
+
+    def put(f, I, J, K, v):
+        arr[f][K + H, J + H, I + H] = v
+
+    for lp in loops:
+        apply_loop3(lp, get, put, lp.rng[2])
+    return arr
+
+
+def run_tiled3(loops, host, plan, H, slots):
+    """Follow the plan along z; returns the host arrays after all downloads."""
+    T = plan["ntiles"]
+    res = plan["resident"]
+    arr = {f: a.copy() for f, a in host.items()}
+    used = sorted(set(f for lp in loops for (f, _, _) in lp.dats))
+    cap = {f: int(max(res[f, t, 1] - res[f, t, 0] for t in range(T))) for f in used}
+    slot = {}
+    up = {t: [r for r in plan["up"] if r[1] == t] for t in range(T)}
+    down = {t: [r for r in plan["down"] if r[1] == t] for t in range(T)}
+    edge = {t: [r for r in plan["edge"] if r[1] == t] for t in range(T)}
+    for t in range(T):
+        s = t % slots
+        for f in used:
+            slot[(s, f)] = np.full((max(cap[f], 1),) + host[f].shape[1:], np.nan)
+        if t > 0:
+            ps = (t - 1) % slots
+            for f, _, r0, r1 in edge[t]:
+                A0, A1 = res[f, t - 1, 0], res[f, t, 0]
+                slot[(s, f)][r0 - A1:r1 - A1] = slot[(ps, f)][r0 - A0:r1 - A0]
+        for f, _, r0, r1 in up[t]:
+            A = res[f, t, 0]
+            slot[(s, f)][r0 - A:r1 - A] = arr[f][r0:r1]
+
+        def get(f, I, J, K, t=t, s=s):
+            A, B = res[f, t, 0], res[f, t, 1]
+            r = K + H
+            assert (r >= A).all() and (r < B).all(), "read outside the planes held for tile %d" % t
+            return slot[(s, f)][r - A, J + H, I + H]
+
+        def put(f, I, J, K, v, t=t, s=s):
+            A, B = res[f, t, 0], res[f, t, 1]
+            r = K + H
+            assert (r >= A).all() and (r < B).all(), "write outside the planes held for tile %d" % t
+            slot[(s, f)][r - A, J + H, I + H] = v
+
+        for i, lp in enumerate(loops):
+            a, b = plan["loop_rows"][i, t]
+            apply_loop3(lp, get, put, (a, b))
+        for f, _, r0, r1 in down[t]:
+            A = res[f, t, 0]
+            arr[f][r0:r1] = slot[(s, f)][r0 - A:r1 - A]
+    return arr
