@@ -47,3 +47,31 @@ def test_ablation_variants_are_the_papers_combinations():
     assert names == ["no_prefetch_cyclic", "no_prefetch_no_cyclic"]
     assert all(flags == 0 for _, flags, _ in bench.ablations(2))   # Prefetch off in both
     assert bench.ablations(2)[1][2] == {"cyclic": False}
+
+
+def test_benchmark_configurations_plan_as_measured():
+    # The planner alone (no storage) at the benchmark sizes and budgets gives
+    # the tile shapes the measured runs used, within the budget.
+    from paper_1709_02125_amd import hydro2d as h2, hydro3d as h3, ns3d as N, ooc
+    pf = ooc.FLAG_PREFETCH
+
+    cases = []
+    a = h2.Hydro2D(15360, 15360, None, None, budget=16_000_000_000, flags=pf, plan_only=True)
+    cases.append((a, 1, 16_000_000_000, 9, 1729))
+    a = h2.Hydro2D(15360, 15360, None, None, budget=16_000_000_000, flags=pf | ooc.FLAG_FP32_STREAM,
+                   plan_only=True, resident_geometry=True)
+    cases.append((a, 1, 16_000_000_000, 15, 1072))
+    n3 = (640, 640, 640)
+    a = h3.Hydro3D(n3, None, None, budget=h3.footprint_bytes(n3) // 3, flags=pf, plan_only=True)
+    cases.append((a, 1, h3.footprint_bytes(n3) // 3, 11, 63))
+    a = N.NS3D(512, None, budget=N.footprint_bytes(512) // 3, flags=pf, plan_only=True)
+    a.ctx.set_schedule(tile_rows=24, chain_steps=3, slots=2)
+    cases.append((a, 3, N.footprint_bytes(512) // 3, 22, 24))
+    for app, steps, budget, tiles, rows in cases:
+        app.ctx.set_flags(ooc.FLAG_CYCLIC, 0)
+        for _ in range(steps):
+            app.queue_step()
+        p = app.ctx.debug_plan()
+        assert (p["ntiles"], p["tile_rows"]) == (tiles, rows)
+        assert p["slots"] * p["slot_bytes"] <= budget
+        app.close()
