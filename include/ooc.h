@@ -243,8 +243,13 @@ int ooc_tile_times(ooc_ctx *ctx, ooc_tile_time *out, int capacity, int *count);
  * dataset point, 2x for read-write). */
 int ooc_kernel_stats(ooc_ctx *ctx, int kernel_id, double *ms, uint64_t *launches, uint64_t *bytes);
 
+/* Message of the last failing call on ctx (owned by the context, valid until
+ * its next call; empty if nothing failed yet); "null context" for NULL. */
 const char *ooc_last_error(ooc_ctx *ctx);
 
+/* Waits for the context's device work (unless it failed), then frees its
+ * events, pinned host arrays, argument tables, streams and arena where the
+ * library created them, and the context itself.  OOC_E_ARG for NULL. */
 int ooc_destroy(ooc_ctx *ctx);
 
 /* ------------------------------------------------------------ inspection */
@@ -277,7 +282,9 @@ int ooc_field_shape(ooc_ctx *ctx, ooc_field f, int64_t lo[3], int64_t n[3]);
  * (tile height, chain length, buffer depth) from features of the plan, and
  * proposes schedules; the exhaustive sweep is its fallback and yardstick.  This is
  * an extension, not part of the paper.  X is row-major N x n_inputs (host);
- * all buffers are the caller's and copied. */
+ * all buffers are the caller's and copied.  Every call returns 0, OOC_E_ARG
+ * for a NULL or out-of-range argument (n_inputs 1..256, n_hidden 1..1024,
+ * n >= 1), or OOC_E_DEVICE when a device call fails. */
 typedef struct ooc_mlp ooc_mlp;
 int ooc_mlp_create(ooc_mlp **out, int n_inputs, int n_hidden, uint64_t seed);
 int ooc_mlp_num_params(ooc_mlp *m);
