@@ -111,10 +111,14 @@ typedef struct {
   double last_flush_ms;                        /* device time of the last flush */
   double last_kernel_ms;                       /* summed kernel time of the last flush (if timed) */
   double last_issue_ms;                        /* host time spent issuing the last flush's chains */
-  double max_call_ms;                          /* longest single runtime call while issuing */
+  double max_call_ms;                          /* longest single runtime call while issuing chains,
+                                                  since creation or the last ooc_set_timing call */
   uint64_t host_pinned_bytes, host_pageable_bytes; /* host field storage pinned / left pageable
                                                      (pinning failed): transfers of pageable rows
                                                      are synchronous with the host */
+  int32_t max_call_kind;                       /* that call: 0 upload copy, 1 download, 2 kernel
+                                                  launch, 3 stream wait, 4 event record, 5 other */
+  int32_t max_call_chain;                      /* chains issued before it (0 = in the first chain) */
 } ooc_stats;
 
 /* Create a context for a grid of ndim (2 or 3) axes with dims[a] interior cells
@@ -213,7 +217,8 @@ int ooc_get_layout(ooc_ctx *ctx, int64_t *pitch, int64_t *plane, int64_t *x_orig
  * summed kernel time of the last flush from ooc_stats.last_kernel_ms.
  * on = 1 times every loop launch; on = 2 + k times only launches of kernel
  * id k (one kernel's figures with few events in flight); 0 turns it off.
- * Every call clears the accumulated per-kernel figures. */
+ * Every call clears the accumulated per-kernel figures and the longest-call
+ * record of ooc_stats (max_call_ms, max_call_kind, max_call_chain). */
 int ooc_set_timing(ooc_ctx *ctx, int on);
 
 /* Per-tile stage timing (hipEvents on the three streams), from the next
@@ -247,9 +252,19 @@ int ooc_kernel_stats(ooc_ctx *ctx, int kernel_id, double *ms, uint64_t *launches
  * its next call; empty if nothing failed yet); "null context" for NULL. */
 const char *ooc_last_error(ooc_ctx *ctx);
 
-/* Waits for the context's device work (unless it failed), then frees its
- * events, pinned host arrays, argument tables, streams and arena where the
- * library created them, and the context itself.  OOC_E_ARG for NULL. */
+/* Failure injection for tests of the error path: from now on, the n-th
+ * runtime call the context checks (copies, launches, event and stream calls
+ * while it issues chains) is reported as failed right after it was issued
+ * successfully; n = 0 turns injection off.  The device sees no fault; the
+ * context becomes failed exactly as after a real OOC_E_DEVICE (the failing
+ * call returns OOC_E_DEVICE, later calls OOC_E_FAILED, ooc_destroy still
+ * waits for the issued work and frees everything).  OOC_E_ARG for n < 0. */
+int ooc_debug_fail_after(ooc_ctx *ctx, int64_t n);
+
+/* Waits for the context's device work on its three streams (also after a
+ * failure: errors of that wait are ignored), then frees its events, pinned
+ * host arrays, argument tables, streams and arena where the library created
+ * them, and the context itself.  OOC_E_ARG for NULL. */
 int ooc_destroy(ooc_ctx *ctx);
 
 /* ------------------------------------------------------------ inspection */

@@ -27,11 +27,15 @@ struct ArgError : std::runtime_error {
   ArgError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
 };
 
+// failure injection (ooc_debug_fail_after): called after every checked call
+void after_hip_call();
+
 #define HIPCHK(x)                                                                  \
   do {                                                                             \
     hipError_t e_ = (x);                                                           \
     if (e_ != hipSuccess)                                                          \
       throw DeviceError(std::string(#x) + ": " + hipGetErrorString(e_));           \
+    after_hip_call();                                                              \
   } while (0)
 
 uint64_t align256(uint64_t x) { return (x + 255) / 256 * 256; }
@@ -129,10 +133,20 @@ struct ooc_ctx {
   std::map<std::string, ChainGraph> graphs;
   int64_t capture_g0 = -1;  // first tile of the chain being captured, -1 if none
   hipEvent_t ev_fork = nullptr, ev_join_c = nullptr, ev_join_d = nullptr, ev_pre = nullptr, ev_post = nullptr;
+  int64_t fail_after = 0;  // ooc_debug_fail_after: checked calls left until the injected failure
   std::string err;
 };
 
 namespace {
+
+// context whose ABI call is running on this thread (set by guarded())
+thread_local ooc_ctx *t_ctx = nullptr;
+
+void after_hip_call() {
+  ooc_ctx *c = t_ctx;
+  if (c && c->fail_after > 0 && --c->fail_after == 0)
+    throw DeviceError("injected failure of a runtime call (ooc_debug_fail_after)");
+}
 
 KernelInfo *g_table = nullptr;
 
@@ -159,7 +173,7 @@ hipEvent_t &evref(std::vector<hipEvent_t> &v, ooc_ctx *c, int64_t g) {
 
 // Host-side issue profile (OOC_PROFILE_HOST=1 prints it per flush): time spent
 // in each kind of runtime call while issuing.
-enum { kCallH2D, kCallD2H, kCallLaunch, kCallWait, kCallRecord, kCallN };
+enum { kCallH2D, kCallD2H, kCallLaunch, kCallWait, kCallRecord, kCallOther, kCallN };
 double g_call_ms[kCallN];
 int g_call_n[kCallN];
 double g_call_max[kCallN];
@@ -169,7 +183,11 @@ void timed_call(ooc_ctx *c, Fn fn, int kind = kCallH2D) {
   auto a = std::chrono::steady_clock::now();
   fn();
   double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - a).count();
-  c->st.max_call_ms = std::max(c->st.max_call_ms, ms);
+  if (ms > c->st.max_call_ms) {
+    c->st.max_call_ms = ms;
+    c->st.max_call_kind = kind;
+    c->st.max_call_chain = (int32_t)c->st.chains;
+  }
   g_call_ms[kind] += ms;
   g_call_n[kind]++;
   g_call_max[kind] = std::max(g_call_max[kind], ms);
@@ -179,7 +197,7 @@ void wait_tile(ooc_ctx *c, hipStream_t s, std::vector<hipEvent_t> &v, int64_t g)
   if (g <= c->gsynced || g < c->gbase) return;
   if (c->capture_g0 >= 0 && g < c->capture_g0) return;  // ordered before the graph instead
   hipEvent_t e = evref(v, c, g);
-  timed_call(c, [&] { HIPCHK(hipStreamWaitEvent(s, e, 0)); }, 3);
+  timed_call(c, [&] { HIPCHK(hipStreamWaitEvent(s, e, 0)); }, kCallWait);
 }
 
 // record stage k of the tile being issued (tile timing on)
@@ -308,6 +326,11 @@ int fail(ooc_ctx *c, int code, const std::string &m) {
 
 template <class Fn>
 int guarded(ooc_ctx *c, Fn fn) {
+  struct Cur {
+    ooc_ctx *prev;
+    explicit Cur(ooc_ctx *x) : prev(t_ctx) { t_ctx = x; }
+    ~Cur() { t_ctx = prev; }
+  } cur(c);
   try {
     return fn();
   } catch (const DeviceError &e) {
@@ -653,8 +676,10 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
     }
     abase = c->argtab_used;
     std::memcpy(c->argtab_host + abase, hostargs.data(), hostargs.size() * sizeof(KArgs));
-    HIPCHK(hipMemcpyAsync(c->argtab_dev + abase, c->argtab_host + abase, hostargs.size() * sizeof(KArgs),
-                          hipMemcpyHostToDevice, c->s_comp));
+    timed_call(c, [&] {
+      HIPCHK(hipMemcpyAsync(c->argtab_dev + abase, c->argtab_host + abase, hostargs.size() * sizeof(KArgs),
+                            hipMemcpyHostToDevice, c->s_comp));
+    }, kCallOther);
     c->argtab_used += hostargs.size();
     c->argtab_cache.emplace(akey, abase);
   }
@@ -698,8 +723,8 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
   for (int t = 0; t < T; t++) {
     const int64_t g = c->gtile++;
     char *slot = c->slot_base + (uint64_t)(g % S) * c->slot_stride;
-    // ---- upload: the part of the tile's footprint not handed over by the
-    // previous tile (Algorithm 1, "upload right footprint to next slot")
+    // ---- upload: the rows of the tile's footprint that the previous tile
+    // does not hand over (Algorithm 1's upload stage)
     wait_tile(c, c->s_up, c->ev_down, g - S);  // slot free again
     if (t == 0 && prev_last_tile >= 0 && !(c->flags & OOC_FLAG_PREFETCH))
       wait_tile(c, c->s_up, c->ev_comp, prev_last_tile);  // no early start of the next chain
@@ -755,7 +780,10 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
     // ---- execute every loop of the chain over its rows of this tile
     timed_call(c, [&] { HIPCHK(hipStreamWaitEvent(c->s_comp, evref(c->ev_up, c, g), 0)); }, kCallWait);
     if (c->tile_timing && c->capture_g0 < 0) tile_mark(c, 2, c->s_comp);
-    const bool fuse = (c->flags & OOC_FLAG_FUSE) && !c->timing;
+    // fused strip loops cannot be timed one by one: fusion stays on unless
+    // the mirror loops themselves are being timed
+    const bool fuse = (c->flags & OOC_FLAG_FUSE) &&
+                      !(c->timing && (c->timing_kid < 0 || c->timing_kid == OOC_K_MIRROR));
     std::vector<const KArgs *> bh, bd;  // pending batch of independent mirror loops
     std::vector<int> bl;
     auto flush_batch = [&] {
@@ -1038,7 +1066,7 @@ int flush(ooc_ctx *c, bool wait = true) {
   }
   c->queue.erase(c->queue.begin(), c->queue.begin() + chains.back().second);
   if (std::getenv("OOC_PROFILE_HOST")) {
-    const char *nm[kCallN] = {"h2d", "d2h", "launch", "wait", "record"};
+    const char *nm[kCallN] = {"h2d", "d2h", "launch", "wait", "record", "other"};
     std::fprintf(stderr, "[ooc host] issue %.1f ms:", c->st.last_issue_ms);
     for (int k = 0; k < kCallN; k++) {
       std::fprintf(stderr, " %s %d calls %.1f ms (max %.2f)", nm[k], g_call_n[k], g_call_ms[k], g_call_max[k]);
@@ -1384,6 +1412,9 @@ int ooc_set_timing(ooc_ctx *c, int on) {
   c->timing = on != 0;  // read when loops are issued
   c->timing_kid = on >= 2 ? on - 2 : -1;
   c->kstats.clear();
+  c->st.max_call_ms = 0;
+  c->st.max_call_kind = 0;
+  c->st.max_call_chain = 0;
   return OOC_OK;
 }
 
@@ -1413,12 +1444,22 @@ int ooc_kernel_stats(ooc_ctx *c, int kid, double *ms, uint64_t *launches, uint64
 
 const char *ooc_last_error(ooc_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
+int ooc_debug_fail_after(ooc_ctx *c, int64_t n) {
+  GUARD(c);
+  if (n < 0) return fail(c, OOC_E_ARG, "negative call count");
+  c->fail_after = n;
+  return OOC_OK;
+}
+
 int ooc_destroy(ooc_ctx *c) {
   if (!c) return OOC_E_ARG;
-  if (c->ready && !c->failed) {
-    (void)hipStreamSynchronize(c->s_up);
-    (void)hipStreamSynchronize(c->s_comp);
-    (void)hipStreamSynchronize(c->s_down);
+  // Work issued before a failure may still read the pinned host arrays and
+  // the argument table: wait for all three streams in every case (a failed
+  // stream returns an error, which is ignored) before anything is freed.
+  if (c->bound) {
+    for (hipStream_t s : {c->s_up, c->s_comp, c->s_down})
+      if (s) (void)hipStreamSynchronize(s);
+    (void)hipGetLastError();
   }
   for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second.exec);
   for (hipEvent_t e : {c->ev_fork, c->ev_join_c, c->ev_join_d, c->ev_pre, c->ev_post})

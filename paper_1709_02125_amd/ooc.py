@@ -48,7 +48,8 @@ class ooc_stats(ctypes.Structure):
                 ("slots", ctypes.c_int32), ("slot_bytes", ctypes.c_uint64),
                 ("last_flush_ms", ctypes.c_double), ("last_kernel_ms", ctypes.c_double),
                 ("last_issue_ms", ctypes.c_double), ("max_call_ms", ctypes.c_double),
-                ("host_pinned_bytes", ctypes.c_uint64), ("host_pageable_bytes", ctypes.c_uint64)]
+                ("host_pinned_bytes", ctypes.c_uint64), ("host_pageable_bytes", ctypes.c_uint64),
+                ("max_call_kind", ctypes.c_int32), ("max_call_chain", ctypes.c_int32)]
 
 
 class ooc_tile_time(ctypes.Structure):
@@ -69,7 +70,7 @@ class ooc_plan_info(ctypes.Structure):
 EXPORTS = ["ooc_create", "ooc_bind_device", "ooc_decl_field", "ooc_decl_reduction", "ooc_set_reduction",
            "ooc_par_loop", "ooc_mark_step", "ooc_discard_queue", "ooc_execute", "ooc_submit", "ooc_reduce", "ooc_fetch_field",
            "ooc_set_field", "ooc_set_flags", "ooc_set_schedule", "ooc_get_stats", "ooc_set_timing", "ooc_set_tile_timing", "ooc_tile_times",
-           "ooc_kernel_stats", "ooc_last_error", "ooc_destroy", "ooc_debug_plan", "ooc_field_shape", "ooc_get_layout",
+           "ooc_kernel_stats", "ooc_last_error", "ooc_debug_fail_after", "ooc_destroy", "ooc_debug_plan", "ooc_field_shape", "ooc_get_layout",
            "ooc_mlp_create", "ooc_mlp_num_params", "ooc_mlp_get_params", "ooc_mlp_set_params",
            "ooc_mlp_predict", "ooc_mlp_gradient", "ooc_mlp_train", "ooc_mlp_destroy"]
 
@@ -116,6 +117,7 @@ def load_library() -> ctypes.CDLL:
         "ooc_tile_times": [P, ctypes.POINTER(ooc_tile_time), I, ctypes.POINTER(I)],
         "ooc_kernel_stats": [P, I, DP, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
         "ooc_last_error": [P],
+        "ooc_debug_fail_after": [P, I64],
         "ooc_destroy": [P],
         "ooc_debug_plan": [P, ctypes.POINTER(ooc_plan_info)],
         "ooc_field_shape": [P, ctypes.c_int32, I64P, I64P],
@@ -213,9 +215,16 @@ class Context:
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
-            self.lib.ooc_destroy(self._h)
+            rc = self.lib.ooc_destroy(self._h)
             self._h = ctypes.c_void_p()
+            self.arena = None
+            self._check(rc, None)
         self.arena = None
+
+    def debug_fail_after(self, n: int):
+        """ooc_debug_fail_after: report the n-th checked runtime call from now
+        on as failed (host-side injection; 0 turns it off)."""
+        self._check(self.lib.ooc_debug_fail_after(self._h, int(n)))
 
     def __del__(self):
         try:

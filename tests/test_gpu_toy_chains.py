@@ -54,3 +54,37 @@ def test_random_chain_gpu_matches_untiled(seed):
             got = c.fetch_field(f, shapes2[f])
             assert np.array_equal(got, ref[f]), (seed, tile_rows, slots, flags, f)
         c.close()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_prefetch_across_different_consecutive_chains(seed):
+    # Speculative prefetch (Section 4.1, opt 3): a chain's first upload may
+    # start while the previous chain still runs, ordered only after the
+    # downloads of the host rows it reads.  Here three different random
+    # chains (other fields, shifted ranges) follow each other in one flush,
+    # split by step marks with one step per chain, so every chain's first
+    # tile reads rows the previous chain's last tiles write and download.
+    # Each schedule must equal the untiled run of all loops in order.
+    rng = np.random.default_rng(100 + seed)
+    nx, ny = int(rng.integers(3, 40)), int(rng.integers(12, 60))
+    nf = int(rng.integers(3, 6))
+    c0, _, shapes = make_ctx_bound(nx, ny, nf, 100 + seed, 0)
+    c0.close()
+    chains = [random_chain(nx, ny, shapes, rng, int(rng.integers(3, 10))) for _ in range(3)]
+    rows = ny + 2 * H + 1
+    for tile_rows, slots, flags in [(2, 2, ooc.FLAG_PREFETCH), (5, 3, ooc.FLAG_PREFETCH),
+                                    (rows // 3 + 1, 4, ooc.FLAG_PREFETCH | ooc.FLAG_DEBUG_POISON),
+                                    (3, 3, 0)]:
+        say("case: toy prefetch seed", seed, "tile_rows", tile_rows, "slots", slots, "flags", flags)
+        c, host, shapes2 = make_ctx_bound(nx, ny, nf, 100 + seed, flags)
+        assert shapes2 == shapes
+        c.set_schedule(tile_rows=tile_rows, chain_steps=1, slots=slots)
+        for ch in chains:
+            queue(c, ch)
+            c.mark_step()
+        c.execute()
+        assert c.stats()["chains"] == 3
+        ref = tile_sim.run_untiled([lp for ch in chains for lp in ch], host, H)
+        for f in host:
+            assert np.array_equal(c.fetch_field(f, shapes2[f]), ref[f]), (seed, tile_rows, slots, flags, f)
+        c.close()

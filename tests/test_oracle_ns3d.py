@@ -90,3 +90,65 @@ def test_taylor_green_early_decay_matches_closed_form():
     assert abs(rate - 6 * nu) <= 0.02 * 6 * nu
     slope = (ke[1] - ke[0]) / dt
     assert abs(slope - (-0.75 * nu)) <= 0.02 * 0.75 * nu
+
+
+def _rk3_scalar(z, A, B):
+    # 2N-storage Runge-Kutta on dq/dt = lambda q with z = lambda dt
+    q, d = 1.0 + 0j, 0j
+    for a, b in zip(A, B):
+        d = a * d + z * q
+        q = q + b * d
+    return q
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_entropy_wave_amplification_is_the_rk3_polynomial(axis):
+    # A density wave carried by a uniform velocity U at uniform pressure is an
+    # exact solution of the inviscid semi-discrete equations: momentum and
+    # energy follow the mass (rho u = U rho, p unchanged), so the density obeys
+    # d rho / dt = -U D rho, a linear system.  The fourth-order difference
+    # turns e^{i m x} into i k_h e^{i m x} with k_h = (8 sin mh - sin 2mh)/(6h),
+    # and any three-stage third-order Runge-Kutta step multiplies a mode with
+    # z = -i U k_h dt by P(z) = 1 + z + z^2/2 + z^3/6.  The amplitude can be
+    # large (0.1) because nothing here is linearised; that keeps rounding far
+    # below the tolerance.  The z axis runs periodic for this case.
+    n, m, eps, U, steps = 16, 3, 0.1, 1.0, 6
+    h = 2.0 * np.pi / n
+    c = (np.arange(n) + 0.5) * h
+    grids = np.meshgrid(c, c, c, indexing="ij")  # z, y, x
+    x = grids[2 - axis]
+    p0 = 1.0 / (1.4 * 0.01)
+    rho = 1.0 + eps * np.cos(m * x)
+    vel = [np.zeros_like(rho) for _ in range(3)]
+    vel[axis] = np.full_like(rho, U)
+    o = ns.NS3D(n, re=float("inf"), periodic_z=True)
+    o.set_primitives(rho, vel[0], vel[1], vel[2], np.full_like(rho, p0))
+    dt = ns.stable_dt(n)
+    for _ in range(steps):
+        o.step(dt)
+    kh = (8.0 * np.sin(m * h) - np.sin(2.0 * m * h)) / (6.0 * h)
+    z = -1j * U * kh * dt
+    P = 1.0 + z + z * z / 2.0 + z ** 3 / 6.0
+    want = 1.0 + eps * np.real(P ** steps * np.exp(1j * m * x))
+    got = o.interior("q_r")
+    assert np.abs(got - want).max() <= 1e-12 * eps
+    mom = ["q_ru", "q_rv", "q_rw"][axis]
+    assert np.abs(o.interior(mom) - U * got).max() <= 1e-13
+    # the test is sensitive: the wave moved by a visible amount, and a 1 %
+    # change of any Runge-Kutta coefficient (or the second-order difference
+    # (f[+1] - f[-1]) / 2h in place of the fourth-order one) moves the answer
+    # by far more than the tolerance
+    assert np.abs(want - (1.0 + eps * np.cos(m * x))).max() > 1e-3 * eps
+    A, B = [0.0, -5.0 / 9.0, -153.0 / 128.0], [1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0]
+    assert abs(_rk3_scalar(z, A, B) - P) <= 1e-15
+    for k in range(1, 3):
+        Ap = list(A)
+        Ap[k] *= 1.01
+        assert abs(_rk3_scalar(z, Ap, B) ** steps - P ** steps) * eps > 1e3 * 1e-12 * eps
+    for k in range(3):
+        Bp = list(B)
+        Bp[k] *= 1.01
+        assert abs(_rk3_scalar(z, A, Bp) ** steps - P ** steps) * eps > 1e3 * 1e-12 * eps
+    z2 = -1j * U * (np.sin(m * h) / h) * dt
+    P2 = 1.0 + z2 + z2 * z2 / 2.0 + z2 ** 3 / 6.0
+    assert abs(P2 ** steps - P ** steps) * eps > 1e3 * 1e-12 * eps
