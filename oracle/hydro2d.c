@@ -444,6 +444,42 @@ double h2d_step(h2d_state *s, double dt) {
   return h2d_dt(s);
 }
 
+/* Field summary of the current state: the periodic diagnostic that reads
+ * many fields, whose separate chain the paper names as a cause of its
+ * CloverLeaf 2D gap (Section 5.3).  First the pressure of the state from the
+ * equation of state over the interior, then five plain sums over the
+ * interior cells, rows in order, each row in x order:
+ *   out[0] volume           sum of vol
+ *   out[1] mass             sum of rho0 vol
+ *   out[2] internal energy  sum of (rho0 vol) e0
+ *   out[3] kinetic energy   sum of (rho0 vol) (0.5 w), w = the mean over the
+ *                           cell's four nodes of u0^2 + v0^2
+ *   out[4] pressure         sum of p vol */
+void h2d_field_summary(h2d_state *s, double out[5]) {
+  eos(s, RHO0, E0, 0, 0, s->nx, 0, s->ny);
+  double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < s->ny; j++) {
+    double row[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < s->nx; i++) {
+      const double vol = A(s, VOL, i, j);
+      const double m = A(s, RHO0, i, j) * vol;
+      double w[4];
+      for (int c = 0; c < 4; c++) {
+        const int ii = i + (c & 1), jj = j + (c >> 1);
+        w[c] = A(s, U0, ii, jj) * A(s, U0, ii, jj) + A(s, V0, ii, jj) * A(s, V0, ii, jj);
+      }
+      const double wm = 0.25 * ((w[0] + w[1]) + (w[2] + w[3]));
+      row[0] += vol;
+      row[1] += m;
+      row[2] += m * A(s, E0, i, j);
+      row[3] += m * (0.5 * wm);
+      row[4] += A(s, PRE, i, j) * vol;
+    }
+    for (int q = 0; q < 5; q++) tot[q] += row[q];
+  }
+  for (int q = 0; q < 5; q++) out[q] = tot[q];
+}
+
 /* Plain sum of f * vol over the interior cells, rows in order, each row in x
  * order (a conservation diagnostic). */
 double h2d_sum_cells(h2d_state *s, int k, int times_rho0) {

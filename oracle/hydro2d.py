@@ -32,6 +32,7 @@ def _setup(lib):
     lib.h2d_lagrangian.argtypes = [ctypes.c_void_p, ctypes.c_double]
     lib.h2d_sum_cells.restype = ctypes.c_double
     lib.h2d_sum_cells.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    lib.h2d_field_summary.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
     lib._h2d_ready = True
 
 
@@ -80,6 +81,13 @@ class Hydro2D:
 
     def sum_cells(self, name: str, times_rho0: bool = False) -> float:
         return self.lib.h2d_sum_cells(self.s, FID[name], int(times_rho0))
+
+    def field_summary(self) -> np.ndarray:
+        """(volume, mass, internal energy, kinetic energy, pressure) of the
+        current state; recomputes the pressure field from rho0 and e0."""
+        out = np.zeros(5)
+        self.lib.h2d_field_summary(self.s, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return out
 
     def run(self, steps: int, dt0=None):
         """Advance `steps` steps starting from dt0 (default: the state's own

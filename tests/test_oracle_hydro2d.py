@@ -173,3 +173,63 @@ def test_shock_tube_converges_to_exact_riemann_solution():
     e2, _ = _sod(200)
     assert e1 < 0.02
     assert e2 < 0.8 * e1      # first-order scheme: the error falls with dx
+
+
+# ---- field summary (the periodic diagnostic of Section 5.3)
+
+def test_field_summary_of_a_uniform_gas_at_rest_has_its_closed_form():
+    # unit square: volume 1, mass rho, internal energy rho e, no kinetic
+    # energy, pressure (gamma - 1) rho e; a stale pressure field is ignored
+    nx, ny, rho, e = 30, 22, 0.7, 2.3
+    o = h.Hydro2D(nx, ny)
+    o.set_state(np.full((ny, nx), rho), np.full((ny, nx), e))
+    o.field("p")[...] = 123.0
+    vol, mass, ie, ke, press = o.field_summary()
+    assert abs(vol - 1.0) <= 1e-13
+    assert abs(mass - rho) <= 1e-13 * rho
+    assert abs(ie - rho * e) <= 1e-13 * rho * e
+    assert ke == 0.0
+    assert abs(press - 0.4 * rho * e) <= 1e-13 * rho * e
+
+
+def test_field_summary_kinetic_energy_of_uniform_and_linear_velocities():
+    nx, ny, rho = 24, 20, 1.3
+    dx, dy = 1.0 / nx, 1.0 / ny
+    # uniform velocity: 0.5 rho |u|^2 over the unit square
+    o = h.Hydro2D(nx, ny)
+    o.set_state(np.full((ny, nx), rho), np.ones((ny, nx)), np.full((ny + 1, nx + 1), 0.3),
+                np.full((ny + 1, nx + 1), -0.4))
+    ke = o.field_summary()[3]
+    assert abs(ke - 0.5 * rho * (0.09 + 0.16)) <= 1e-13
+    # u = x at the nodes: each cell averages x^2 over its two node columns,
+    # sum_i (i^2 + (i+1)^2) dx^3 / 4 = (S(n-1) + S(n)) dx^3 / 4, S(m) = sum of squares to m
+    S = lambda m: m * (m + 1) * (2 * m + 1) / 6.0
+    xs = np.arange(nx + 1) * dx
+    o = h.Hydro2D(nx, ny)
+    o.set_state(np.full((ny, nx), rho), np.ones((ny, nx)), np.tile(xs, (ny + 1, 1)), np.zeros((ny + 1, nx + 1)))
+    assert abs(o.field_summary()[3] - rho * (S(nx - 1) + S(nx)) * dx ** 3 / 4) <= 1e-13
+    # v = y at the nodes: the same along y
+    ys = np.arange(ny + 1) * dy
+    o = h.Hydro2D(nx, ny)
+    o.set_state(np.full((ny, nx), rho), np.ones((ny, nx)), np.zeros((ny + 1, nx + 1)),
+                np.tile(ys[:, None], (1, nx + 1)))
+    assert abs(o.field_summary()[3] - rho * (S(ny - 1) + S(ny)) * dy ** 3 / 4) <= 1e-13
+    # u = x y: the mean over a cell's four corners of x^2 y^2 factorises,
+    # (x_i^2 + x_i+1^2)(y_j^2 + y_j+1^2) / 4, which only the four true corners give
+    o = h.Hydro2D(nx, ny)
+    o.set_state(np.full((ny, nx), rho), np.ones((ny, nx)), np.outer(ys, xs), np.zeros((ny + 1, nx + 1)))
+    want = rho / 8 * (S(nx - 1) + S(nx)) * dx ** 3 * (S(ny - 1) + S(ny)) * dy ** 3
+    assert abs(o.field_summary()[3] - want) <= 1e-13
+
+
+def test_field_summary_pressure_is_the_equation_of_state_and_mass_is_conserved():
+    # for any state the pressure sum is (gamma - 1) times the internal-energy
+    # sum; in the closed box the volume and the mass stay as they were
+    o = _blobs(48, 40)
+    s0 = o.field_summary()
+    o.run(6)
+    s1 = o.field_summary()
+    for s in (s0, s1):
+        assert abs(s[4] - 0.4 * s[2]) <= 1e-13 * s[2]
+    assert abs(s1[0] - s0[0]) <= 1e-15 and abs(s1[1] - s0[1]) <= 1e-13 * s0[1]
+    assert s0[3] == 0.0 and s1[3] > 0.0
