@@ -845,7 +845,8 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
     if (c->tile_timing && c->capture_g0 < 0) tile_mark(c, 4, c->s_comp);
     timed_call(c, [&] { HIPCHK(hipEventRecord(evref(c->ev_comp, c, g), c->s_comp)); }, kCallRecord);
     if (dbg_sync) HIPCHK(hipStreamSynchronize(c->s_comp));
-    // ---- download the left footprint of modified datasets
+    // ---- download: the written rows this tile holds that the next tile
+    // does not take over (Algorithm 1's download stage)
     timed_call(c, [&] { HIPCHK(hipStreamWaitEvent(c->s_down, evref(c->ev_comp, c, g), 0)); }, kCallWait);
     if (c->tile_timing && c->capture_g0 < 0) tile_mark(c, 5, c->s_down);
     std::vector<XferSeg> xdown;
