@@ -307,6 +307,22 @@ int ooc_mlp_num_params(ooc_mlp *m);
 int ooc_mlp_get_params(ooc_mlp *m, double *out);
 int ooc_mlp_set_params(ooc_mlp *m, const double *in);  /* also resets Adam state */
 int ooc_mlp_predict(ooc_mlp *m, const double *X, int n, double *out);
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same prediction
+ * as ooc_mlp_predict, bit for bit (same kernels), but it allocates nothing.
+ * Its inputs, hidden activations and outputs live in one static device array
+ * of OOC_MLP_SCRATCH_DOUBLES doubles (4 MiB), held by every device the
+ * library runs on until the process ends.  A batch needs
+ * pad(n*n_inputs) + 2*pad(n*n_hidden) + pad(n) doubles, pad() rounding up to
+ * a multiple of 32; a larger batch is refused with OOC_E_ARG before any
+ * device work.  X (n x n_inputs, row-major) and out (n) are host memory owned
+ * by the caller.  The call runs on the network's device and stream and waits
+ * for its result.  All calls on one device share the array: calls that
+ * overlap in time on one device (from several threads) race.  OOC_E_ARG for a
+ * NULL pointer or n < 1, OOC_E_DEVICE when a device call fails. */
+#define OOC_MLP_SCRATCH_DOUBLES 524288
+int ooc_mlp_predict_noalloc(ooc_mlp *m, const double *X, int n, double *out);
 /* gradient of the loss with respect to every parameter (same layout) */
 int ooc_mlp_gradient(ooc_mlp *m, const double *X, const double *y, int n, double *grad, double *loss);
 /* full-batch Adam (beta 0.9 / 0.999, eps 1e-8); loss after the last epoch */

@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -99,6 +100,37 @@ unsigned blocks(int n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
+// Device scratch of the allocation-free prediction (ooc_mlp_predict_noalloc):
+// one call's inputs, both hidden activations and its outputs.  Every device
+// the library runs on holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns for that
+// device (the array's name is a host-side stand-in, not a device address).
+static __device__ __align__(256) double scratch[OOC_MLP_SCRATCH_DOUBLES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch`, per device, once looked up
+
+// Address of `scratch` on device `dev`, which must be the current device.
+int scratch_on(int dev, double **out) {
+  if (dev < 0 || dev >= kMaxDevices) return OOC_E_ARG;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return OOC_E_DEVICE;
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return OOC_OK;
+}
+
+// element counts rounded up to 32 doubles, so every scratch part starts 256-byte aligned
+size_t pad32(size_t n) { return (n + 31) & ~size_t(31); }
+
+}  // namespace
+
 struct ooc_mlp {
   int D = 0, Hd = 0, P = 0, cap = 0;  // inputs, hidden width, parameter count, batch capacity
   // parameter layout: W0[H*D] b0[H] W1[H*H] b1[H] W2[H] b2[1]
@@ -106,6 +138,7 @@ struct ooc_mlp {
   double *X = nullptr, *y = nullptr, *A1 = nullptr, *A2 = nullptr, *out = nullptr;
   double *dO = nullptr, *dZ2 = nullptr, *dZ1 = nullptr, *loss = nullptr;
   int step = 0;
+  int dev = 0;  // device the network lives on
   hipStream_t s = nullptr;
   int off_W0() const { return 0; }
   int off_b0() const { return Hd * D; }
@@ -133,15 +166,18 @@ int ensure_batch(ooc_mlp *m, int N) {
   return OOC_OK;
 }
 
-void forward(ooc_mlp *m, int N) {
+// forward pass of N rows: X (N x D) -> A1, A2 (N x H) -> out (N)
+void forward_into(ooc_mlp *m, int N, const double *X, double *A1, double *A2, double *out) {
   const int H = m->Hd, D = m->D;
-  hipLaunchKernelGGL(k_dense_fwd, dim3(blocks(N * H)), dim3(256), 0, m->s, m->X, m->p + m->off_W0(),
-                     m->p + m->off_b0(), m->A1, N, D, H, 1);
-  hipLaunchKernelGGL(k_dense_fwd, dim3(blocks(N * H)), dim3(256), 0, m->s, m->A1, m->p + m->off_W1(),
-                     m->p + m->off_b1(), m->A2, N, H, H, 1);
-  hipLaunchKernelGGL(k_dense_fwd, dim3(blocks(N)), dim3(256), 0, m->s, m->A2, m->p + m->off_W2(),
-                     m->p + m->off_b2(), m->out, N, H, 1, 0);
+  hipLaunchKernelGGL(k_dense_fwd, dim3(blocks(N * H)), dim3(256), 0, m->s, X, m->p + m->off_W0(),
+                     m->p + m->off_b0(), A1, N, D, H, 1);
+  hipLaunchKernelGGL(k_dense_fwd, dim3(blocks(N * H)), dim3(256), 0, m->s, A1, m->p + m->off_W1(),
+                     m->p + m->off_b1(), A2, N, H, H, 1);
+  hipLaunchKernelGGL(k_dense_fwd, dim3(blocks(N)), dim3(256), 0, m->s, A2, m->p + m->off_W2(),
+                     m->p + m->off_b2(), out, N, H, 1, 0);
 }
+
+void forward(ooc_mlp *m, int N) { forward_into(m, N, m->X, m->A1, m->A2, m->out); }
 
 void backward(ooc_mlp *m, int N) {
   const int H = m->Hd, D = m->D;
@@ -176,7 +212,7 @@ int ooc_mlp_create(ooc_mlp **out, int n_inputs, int n_hidden, uint64_t seed) {
   m->D = n_inputs;
   m->Hd = n_hidden;
   m->P = m->off_b2() + 1;
-  if (hipStreamCreateWithFlags(&m->s, hipStreamNonBlocking) != hipSuccess ||
+  if (hipGetDevice(&m->dev) != hipSuccess || hipStreamCreateWithFlags(&m->s, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc((void **)&m->p, sizeof(double) * m->P) != hipSuccess ||
       hipMalloc((void **)&m->g, sizeof(double) * m->P) != hipSuccess ||
       hipMalloc((void **)&m->m, sizeof(double) * m->P) != hipSuccess ||
@@ -239,6 +275,31 @@ int ooc_mlp_predict(ooc_mlp *m, const double *X, int N, double *out) {
   MCHK(hipMemcpyAsync(out, m->out, sizeof(double) * N, hipMemcpyDeviceToHost, m->s));
   MCHK(hipStreamSynchronize(m->s));
   return OOC_OK;
+}
+
+int ooc_mlp_predict_noalloc(ooc_mlp *m, const double *X, int N, double *out) {
+  if (!m || !X || !out || N < 1) return OOC_E_ARG;
+  const size_t nX = pad32((size_t)N * m->D), nA = pad32((size_t)N * m->Hd), nO = pad32((size_t)N);
+  if (nX + 2 * nA + nO > (size_t)OOC_MLP_SCRATCH_DOUBLES) return OOC_E_ARG;
+  int prev = 0;
+  MCHK(hipGetDevice(&prev));
+  if (prev != m->dev) MCHK(hipSetDevice(m->dev));
+  double *base = nullptr;
+  int rc = scratch_on(m->dev, &base);
+  if (rc == OOC_OK) {
+    double *sX = base, *sA1 = sX + nX, *sA2 = sA1 + nA, *sO = sA2 + nA;
+    if (hipMemcpyAsync(sX, X, sizeof(double) * N * m->D, hipMemcpyHostToDevice, m->s) != hipSuccess) {
+      rc = OOC_E_DEVICE;
+    } else {
+      forward_into(m, N, sX, sA1, sA2, sO);
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(out, sO, sizeof(double) * N, hipMemcpyDeviceToHost, m->s) != hipSuccess ||
+          hipStreamSynchronize(m->s) != hipSuccess)
+        rc = OOC_E_DEVICE;
+    }
+  }
+  if (prev != m->dev) (void)hipSetDevice(prev);
+  return rc;
 }
 
 int ooc_mlp_gradient(ooc_mlp *m, const double *X, const double *y, int N, double *grad, double *loss) {

@@ -21,6 +21,7 @@ FLAG_CYCLIC, FLAG_PREFETCH, FLAG_FP32_STREAM, FLAG_INCORE = 1, 2, 4, 8
 FLAG_GRAPH, FLAG_FUSE, FLAG_DEBUG_POISON, FLAG_DEBUG_SYNC, FLAG_PLAN_ONLY = 16, 32, 64, 128, 256
 FLAG_KERNEL_COPY = 512
 FIELD_RESIDENT = 1
+SCRATCH_DOUBLES = 524288  # OOC_MLP_SCRATCH_DOUBLES: static device scratch of ooc_mlp_predict_noalloc
 
 _ERRNAMES = {E_ARG: "OOC_E_ARG", E_BUDGET: "OOC_E_BUDGET", E_DEVICE: "OOC_E_DEVICE",
              E_STATE: "OOC_E_STATE", E_FAILED: "OOC_E_FAILED", E_STALE: "OOC_E_STALE",
@@ -72,7 +73,7 @@ EXPORTS = ["ooc_create", "ooc_bind_device", "ooc_decl_field", "ooc_decl_reductio
            "ooc_set_field", "ooc_set_flags", "ooc_set_schedule", "ooc_get_stats", "ooc_set_timing", "ooc_set_tile_timing", "ooc_tile_times",
            "ooc_kernel_stats", "ooc_last_error", "ooc_debug_fail_after", "ooc_destroy", "ooc_debug_plan", "ooc_field_shape", "ooc_get_layout",
            "ooc_mlp_create", "ooc_mlp_num_params", "ooc_mlp_get_params", "ooc_mlp_set_params",
-           "ooc_mlp_predict", "ooc_mlp_gradient", "ooc_mlp_train", "ooc_mlp_destroy"]
+           "ooc_mlp_predict", "ooc_mlp_predict_noalloc", "ooc_mlp_gradient", "ooc_mlp_train", "ooc_mlp_destroy"]
 
 _lib = None
 
@@ -126,6 +127,7 @@ def load_library() -> ctypes.CDLL:
         "ooc_mlp_get_params": [P, DP],
         "ooc_mlp_set_params": [P, DP],
         "ooc_mlp_predict": [P, DP, I, DP],
+        "ooc_mlp_predict_noalloc": [P, DP, I, DP],
         "ooc_mlp_gradient": [P, DP, DP, I, DP, DP],
         "ooc_mlp_train": [P, DP, DP, I, I, D, DP],
         "ooc_mlp_destroy": [P],
@@ -422,6 +424,24 @@ class Mlp:
         X = np.ascontiguousarray(X, dtype=np.float64)
         out = np.empty(X.shape[0])
         self._chk(self.lib.ooc_mlp_predict(self._h, _dp(X), X.shape[0], _dp(out)), "predict")
+        return out
+
+    def scratch_doubles(self, n: int) -> int:
+        """Doubles of the static device scratch a batch of n rows needs in
+        predict_noalloc (each part rounded up to 32 doubles)."""
+        pad = lambda k: (k + 31) // 32 * 32
+        return pad(n * self.n_inputs) + 2 * pad(n * self.n_hidden) + pad(n)
+
+    def predict_noalloc(self, X) -> np.ndarray:
+        """predict() without any device allocation (static device scratch)."""
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        out = np.empty(X.shape[0])
+        rc = self.lib.ooc_mlp_predict_noalloc(self._h, _dp(X), X.shape[0], _dp(out))
+        if rc == E_ARG and X.shape[0] >= 1 and self.scratch_doubles(X.shape[0]) > SCRATCH_DOUBLES:
+            raise OocError(rc, "predict_noalloc: a batch of %d rows needs %d doubles of scratch, the static "
+                               "device scratch holds %d" % (X.shape[0], self.scratch_doubles(X.shape[0]),
+                                                            SCRATCH_DOUBLES))
+        self._chk(rc, "predict_noalloc")
         return out
 
     def gradient(self, X, y):
