@@ -70,6 +70,11 @@ enum {
   OOC_K_H2D_VEL_Y = 121,
   /* R e0, R u0 4n, R v0 4n; CONST dx, CONST dy; RED(MIN) dt */
   OOC_K_H2D_DT = 122,
+  /* Field summary (interior range): R vol, R rho0, R e0, R u0 4n, R v0 4n;
+   * RED(SUM) x5: volume = sum vol, mass = sum m (m = rho0 vol), internal
+   * energy = sum m e0, kinetic energy = sum m w / 2 (w = mean of u0^2 + v0^2
+   * over the 4 nodes), pressure = sum p vol (p = (gamma - 1) rho0 e0) */
+  OOC_K_H2D_SUMMARY = 123,
 
   /* ---- 3D Navier-Stokes proxy (tiled along z).  q = conserved (rho, rho u,
    * rho v, rho w, rho E); prims = (rho, u, v, w, p); grads = du/dx, du/dy,

@@ -249,6 +249,44 @@ OOC_KERNEL(k_dt) {
   block_min_to(t, a.red[0]);
 }
 
+// Field summary of the state (the periodic diagnostic that reads many fields,
+// Section 5.3): one block per row, each of the five sums in a fixed order
+// (x stride 256 per thread, then a fixed tree), written to the row's partial
+// slot of its SUM reduction -- volume (vol), mass (m = rho0 vol), internal
+// energy (m e0), kinetic energy (m w / 2 with w the mean of u0^2 + v0^2 over
+// the cell's four nodes) and pressure (p vol, p from the equation of state).
+OOC_KERNEL(k_summary) {
+  ARGS
+  __shared__ double sm[5][256];
+  const int j = a.lo[1] + blockIdx.y;
+  const int k = 0;  // 2D: no plane term
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = a.lo[0] + threadIdx.x; i < a.hi[0]; i += 256) {
+    const double vol = AT(0, 0, 0, 0);
+    const double r = AT(1, 0, 0, 0), e = AT(2, 0, 0, 0);
+    const double m = r * vol;
+    const double u00 = AT(3, 0, 0, 0), u10 = AT(3, 1, 0, 0), u01 = AT(3, 0, 1, 0), u11 = AT(3, 1, 1, 0);
+    const double v00 = AT(4, 0, 0, 0), v10 = AT(4, 1, 0, 0), v01 = AT(4, 0, 1, 0), v11 = AT(4, 1, 1, 0);
+    const double w00 = u00 * u00 + v00 * v00, w10 = u10 * u10 + v10 * v10;
+    const double w01 = u01 * u01 + v01 * v01, w11 = u11 * u11 + v11 * v11;
+    const double wm = 0.25 * ((w00 + w10) + (w01 + w11));
+    const double p = (kGm1 * r) * e;
+    acc[0] += vol;
+    acc[1] += m;
+    acc[2] += m * e;
+    acc[3] += m * (0.5 * wm);
+    acc[4] += p * vol;
+  }
+  for (int q = 0; q < 5; q++) sm[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int q = 0; q < 5; q++) sm[q][threadIdx.x] += sm[q][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) a.red[threadIdx.x][j + a.halo] = sm[threadIdx.x][0];
+}
+
 #define L(name, kern) \
   void name(const KArgs &a, const KArgs *d, int nd, void *s) { launch_point(kern, a, d, nd, s); }
 L(l_eos, k_eos)
@@ -275,6 +313,7 @@ L(l_vel_x, k_vel<0>)
 L(l_vel_y, k_vel<1>)
 L(l_dt, k_dt)
 #undef L
+void l_summary(const KArgs &a, const KArgs *d, int nd, void *s) { launch_rows(k_summary, a, d, nd, s); }
 
 }  // namespace
 
@@ -303,6 +342,7 @@ void register_hydro2d_kernels(KernelInfo *t) {
   t[OOC_K_H2D_VEL_X] = {"h2d_vel_x", 4, 4, 0, 0, 0, kPointGrid, l_vel_x};
   t[OOC_K_H2D_VEL_Y] = {"h2d_vel_y", 4, 4, 0, 0, 0, kPointGrid, l_vel_y};
   t[OOC_K_H2D_DT] = {"h2d_dt", 3, 3, 2, 0, 1, kPointGrid, l_dt};
+  t[OOC_K_H2D_SUMMARY] = {"h2d_summary", 5, 5, 0, 0, 5, kRowReduce, l_summary};
 }
 
 }  // namespace ooc

@@ -14,7 +14,7 @@ namespace ooc {
 constexpr int kMaxDat = 32;
 constexpr int kMaxConst = 12;
 constexpr int kMaxDev = 2;
-constexpr int kMaxRed = 2;
+constexpr int kMaxRed = 5;
 constexpr int kMaxStencil = 32;
 // storage element of x = 0 within every field row (a multiple of 16 elements)
 constexpr int64_t kXOrigin = 16;

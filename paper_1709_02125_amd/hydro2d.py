@@ -19,7 +19,7 @@ H = 2
 K_MIRROR, K_FILL, K_SUM_PROD = 1, 2, 3
 (K_EOS, K_EOS_P, K_VISC, K_PDV_PRED, K_PDV_CORR, K_ACCEL, K_FLUX_X, K_FLUX_Y, K_ADV_VOL_X, K_ADV_VOL_Y,
  K_ADV_FLUX_X, K_ADV_FLUX_Y, K_ADV_CELL_X, K_ADV_CELL_Y, K_NFLUX_X, K_NFLUX_Y, K_NMASS_X, K_NMASS_Y,
- K_MFLUX_X, K_MFLUX_Y, K_VEL_X, K_VEL_Y, K_DT) = range(100, 123)
+ K_MFLUX_X, K_MFLUX_Y, K_VEL_X, K_VEL_Y, K_DT, K_SUMMARY) = range(100, 124)
 
 CELL, NODE, XFACE, YFACE = (0, 0), (1, 1), (1, 0), (0, 1)
 FIELDS = [  # name, centring, streamed state?
@@ -30,6 +30,7 @@ FIELDS = [  # name, centring, streamed state?
     ("w_nmpre", NODE), ("w_mf", NODE)]
 GEOMETRY = ("vol", "xarea", "yarea")
 STATE = ("rho0", "e0", "u0", "v0")           # what persists from step to step
+SUMMARY = ("volume", "mass", "internal_energy", "kinetic_energy", "pressure")  # field summary sums
 N4 = ((0, 0), (1, 0), (0, 1), (1, 1))        # the four nodes of a cell
 C4 = ((-1, -1), (0, -1), (-1, 0), (0, 0))    # the four cells of a node
 
@@ -42,14 +43,16 @@ def footprint_bytes(nx: int, ny: int) -> int:
     return tot
 
 
-def device_footprint_bytes(nx: int, ny: int) -> int:
+def device_footprint_bytes(nx: int, ny: int, summary: bool = False) -> int:
     """Device bytes to hold every field resident in the library's padded
-    layout (ooc.row_pitch elements per row), plus reduction buffers."""
+    layout (ooc.row_pitch elements per row), plus reduction buffers (with
+    `summary`, the field summary's five sums too)."""
     pitch = ooc.row_pitch(nx, H)
     tot = 0
     for _, (dx, dy) in FIELDS:
         tot += ((ny + 2 * H + dy) * pitch * 8 + 255) // 256 * 256
-    return tot + 64 * 1024 + ((ny + 2 * H + 1) * 8 + 255) // 256 * 256
+    nsum = 1 + (len(SUMMARY) if summary else 0)
+    return tot + 64 * 1024 + nsum * (((ny + 2 * H + 1) * 8 + 255) // 256 * 256)
 
 
 def full_extent(nx, ny, centring, interior=None):
@@ -70,7 +73,8 @@ class Hydro2D:
 
     def __init__(self, nx: int, ny: int, rho: np.ndarray, ene: np.ndarray, budget: int, flags: int = 0,
                  resident_geometry: bool = False, cyclic_after_init: bool = True, bind: bool = True,
-                 arena_bytes: int | None = None, plan_only: bool = False, resident_state: bool = False):
+                 arena_bytes: int | None = None, plan_only: bool = False, resident_state: bool = False,
+                 summary: bool = False):
         self.nx, self.ny = nx, ny
         if plan_only:
             flags |= ooc.FLAG_PLAN_ONLY
@@ -91,6 +95,8 @@ class Hydro2D:
         self.centring = dict(FIELDS)
         self.dt = self.ctx.decl_reduction(ooc.RED_MIN)
         self.mass = self.ctx.decl_reduction(ooc.RED_SUM)
+        # the field summary's five order-fixed sums (declared on request)
+        self.summary_reds = [self.ctx.decl_reduction(ooc.RED_SUM) for _ in SUMMARY] if summary else []
         self.cyclic_after_init = cyclic_after_init
         self.steps_queued = 0
 
@@ -226,6 +232,22 @@ class Hydro2D:
         (its reduction is not read in the chain) and moves no extra bytes;
         queued alone it is a chain of its own that uploads rho0 and vol."""
         self._loop(K_SUM_PROD, ((0, self.nx), (0, self.ny)), self.d("rho0"), self.d("vol"), Red(self.mass))
+
+    def queue_summary(self):
+        """Field summary of the state: volume, mass, internal energy, kinetic
+        energy and pressure summed over the interior in one loop (the periodic
+        diagnostic whose separate chain the paper names as a cause of its
+        CloverLeaf 2D gap, Section 5.3).  Queued after a step and before the
+        flush, it joins that step's chain like queue_mass; read the sums with
+        summary().  Needs summary=True at construction."""
+        if not self.summary_reds:
+            raise ValueError("construct with summary=True to queue the field summary")
+        self._loop(K_SUMMARY, ((0, self.nx), (0, self.ny)), self.d("vol"), self.d("rho0"), self.d("e0"),
+                   self.d("u0", READ, *N4), self.d("v0", READ, *N4), *[Red(r) for r in self.summary_reds])
+
+    def summary(self) -> np.ndarray:
+        """The committed field-summary sums, in SUMMARY order (flushes)."""
+        return np.array([self.ctx.reduce(r) for r in self.summary_reds])
 
     # ---------------------------------------------------------------- driver
     def run(self, steps: int, overlap: bool = True):

@@ -225,6 +225,90 @@ def test_hydro2d_field_summary_folded_into_the_step_chain():
     b.close()
 
 
+def _summary_run(nx, ny, steps, every, budget, flags, folded=True):
+    """Run `steps` steps with the field summary every `every` steps; folded:
+    queued after the step, before the flush (it joins the step's chain);
+    otherwise the step is issued first and the summary is a chain of its own.
+    Returns the sums at each summary step, the state and the bytes uploaded
+    for each step (its chain and, on summary steps, the summary's)."""
+    from paper_1709_02125_amd.inputs import hydro_initial_state
+    rho, ene = hydro_initial_state((nx, ny))
+    app = h2.Hydro2D(nx, ny, rho, ene, budget=budget, flags=flags, summary=True)
+    app.initialise()
+    sums, up = [], []
+    for s in range(1, steps + 1):
+        b0 = app.ctx.stats()["bytes_h2d"]
+        app.queue_step()
+        if s % every == 0:
+            if not folded:
+                app.ctx.submit()
+            app.queue_summary()
+            sums.append(app.summary())
+        else:
+            app.ctx.submit()
+        up.append(app.ctx.stats()["bytes_h2d"] - b0)
+    app.ctx.execute()
+    st = app.ctx.stats()
+    out = {n: app.fetch(n) for n in STATE}
+    app.close()
+    return sums, out, up, st
+
+
+def test_hydro2d_field_summary_every_10_steps_matches_oracle():
+    # The paper's periodic field summary (volume, mass, internal and kinetic
+    # energy, pressure; Section 5.3) every 10 steps, folded into the step's
+    # chain: each sum equals the oracle's plain sum of the same state to
+    # 1e-12, the sums are bit-identical across tilings (order-fixed per row)
+    # and to a summary run as a chain of its own, and folding leaves the state
+    # unchanged.  Mass and volume are conserved in the closed box.
+    import oracle.hydro2d as oh
+    from paper_1709_02125_amd.inputs import hydro_initial_state
+    nx, ny, steps, every = 96, 130, 20, 10
+    say("case: hydro2d field summary every 10 steps, 96x130, 1/3 budget, folded")
+    fs = h2.device_footprint_bytes(nx, ny, summary=True)
+    a, sa, upa, sta = _summary_run(nx, ny, steps, every, fs // 3, ooc.FLAG_PREFETCH)
+    assert sta["ntiles_last"] >= 3
+    rho, ene = hydro_initial_state((nx, ny))
+    o = oh.Hydro2D(nx, ny)
+    o.set_state(rho, ene)
+    dt = o.dt()
+    ref = []
+    for s in range(1, steps + 1):
+        dt = o.step(dt)
+        if s % every == 0:
+            ref.append(o.field_summary())
+    assert len(a) == len(ref) == steps // every
+    for g, r in zip(a, ref):
+        for q, name in enumerate(h2.SUMMARY):
+            e = abs(g[q] - r[q]) / abs(r[q])
+            say("summary", name, g[q], r[q], e)
+            assert e <= TOL, name
+    assert a[0][0] == a[1][0]                          # volume: the mesh does not move
+    assert abs(a[1][1] - a[0][1]) <= 1e-13 * a[0][1]   # mass: closed box
+    say("case: the same in core and with 7-row tiles, and unfolded")
+    b, sb, _, _ = _summary_run(nx, ny, steps, every, fs, ooc.FLAG_INCORE)
+    c, sc, _, _ = _summary_run(nx, ny, steps, every, fs // 3, ooc.FLAG_PREFETCH, folded=False)
+    for g1, g2, g3 in zip(a, b, c):
+        assert np.array_equal(g1, g2) and np.array_equal(g1, g3)
+    for n in STATE:
+        assert np.array_equal(sa[n], sb[n]) and np.array_equal(sa[n], sc[n]), n
+
+
+def test_hydro2d_folded_summary_moves_no_extra_bytes():
+    # folded into the step's chain the summary reads rows the chain holds
+    # anyway: a summary step uploads what any other step does; as a chain of
+    # its own the summary uploads vol, rho0, e0, u0 and v0 again
+    nx, ny = 64, 150
+    say("case: folded field summary bytes", nx, ny)
+    fs = h2.device_footprint_bytes(nx, ny, summary=True)
+    _, _, up_f, _ = _summary_run(nx, ny, 4, 2, fs // 3, ooc.FLAG_PREFETCH)
+    _, _, up_s, _ = _summary_run(nx, ny, 4, 2, fs // 3, ooc.FLAG_PREFETCH, folded=False)
+    say("bytes per step, folded", up_f, "separate", up_s)
+    assert up_f[0] > 0 and all(u == up_f[0] for u in up_f), up_f
+    assert up_s[0] == up_s[2] == up_f[0], up_s
+    assert up_s[1] > up_f[0] and up_s[3] > up_f[0], up_s
+
+
 def test_hydro2d_tile_stage_timing_follows_the_pipeline():
     # per-tile stage events on the three streams: each tile's compute begins
     # after its upload ends, its download after its compute and edge copy;

@@ -274,16 +274,19 @@ def test_storage_layout_and_host_round_trip(ndim, dims, halo):
     c.close()
 
 
-@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("dim", [2, 3, "2-summary"])
 def test_field_summary_folds_into_the_step_chain(dim):
     # A diagnostic sum queued after a step joins the step's chain (its SUM
     # reduction is not read in the chain, so nothing splits it) and reads only
     # fields the chain holds anyway: the transfer sets are the step's own.
-    if dim == 2:
+    # "2-summary": the five-sum field summary of the 2D proxy.
+    if dim in (2, "2-summary"):
         from paper_1709_02125_amd import hydro2d as hm
         n = (24, 300)
+        summ = dim == "2-summary"
         make = lambda: hm.Hydro2D(n[0], n[1], np.full(n[::-1], 0.2), np.full(n[::-1], 1.0),
-                                  budget=hm.device_footprint_bytes(*n) // 3, bind=False)
+                                  budget=hm.device_footprint_bytes(*n, summary=summ) // 3, bind=False,
+                                  summary=summ)
     else:
         from paper_1709_02125_amd import hydro3d as hm
         n = (16, 12, 120)
@@ -295,7 +298,10 @@ def test_field_summary_folds_into_the_step_chain(dim):
         app.ctx.set_flags(ooc.FLAG_CYCLIC, 0)
         app.queue_step()
         if fold:
-            app.queue_mass()
+            if dim == "2-summary":
+                app.queue_summary()
+            else:
+                app.queue_mass()
         plans.append(app.ctx.debug_plan())
         app.close()
     step, folded = plans
