@@ -94,7 +94,7 @@ typedef struct {
   int32_t kind;            /* OOC_ARG_* */
   int32_t handle;          /* field (DAT) or reduction (RED, DEVSCALAR) handle */
   int32_t access;          /* DAT only: OOC_READ / OOC_WRITE / OOC_RW / OOC_INC */
-  int32_t npts;            /* DAT only: number of stencil points (>= 1) */
+  int32_t npts;            /* DAT only: number of stencil points (1 .. 256) */
   const int32_t *offsets;  /* DAT only: npts * ndim offsets, point-major */
   double value;            /* CONST only */
 } ooc_arg;

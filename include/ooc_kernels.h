@@ -90,6 +90,14 @@ enum {
    * CONST 1/(12h), mu, kappa, dt, A_s, B_s: dq = A_s dq + dt R(q); q += B_s dq */
   OOC_K_NS_RHS_FIRST = 203,
   OOC_K_NS_RHS = 204,
+  /* The same residual + update with the gradients evaluated from the
+   * primitives inside the kernel (no stored gradient fields):
+   * R prims x5 G, RW q x5, W dq x5 (first stage) or RW dq x5;
+   * CONST 1/(12h), mu, kappa, dt, A_s, B_s, gamma M^2.  "G" = the 73 points
+   * {a e_A + b e_B : a, b in {0, +-1, +-2}; axes A, B} (fluxes at the points of
+   * the 5-point stencils, each from the 5-point stencils of the primitives). */
+  OOC_K_NS_RHS_FUSED_FIRST = 205,
+  OOC_K_NS_RHS_FUSED = 206,
 
   /* ---- 3D hydro proxy (tiled along z).  "8n" = the 8 nodes of a cell
    * {0,1}^3; "8c" = the 8 cells of a node {-1,0}^3; "F4x" = the 4 nodes of a

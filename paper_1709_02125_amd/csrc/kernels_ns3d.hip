@@ -286,6 +286,279 @@ __global__ void __launch_bounds__(64 * PH) k_ns_rhs(const KArgs *__restrict__ ap
   }
 }
 
+// Residual and RK update with the first derivatives evaluated on the fly from
+// the primitives instead of read from stored gradient fields (so the chain
+// keeps 15 fields instead of 27).  Same z-march as k_ns_rhs, with the fluxes
+// of plane c evaluated when plane m = c + 2 of the primitives arrives and the
+// update of plane k = c - 2 applied at the same step:
+//  - each thread keeps u, v, w, T = gamma M^2 p / rho of its own column and of
+//    one y-halo column (rows j0-2, j0-1, j0+4, j0+5) for planes c-2 .. c+2 in
+//    registers (their z-derivatives), and rho, p for planes c .. c+2;
+//  - u, v, w, T of plane c over the patch plus four columns / rows (a cross:
+//    the x/y stencils of the patch and of its flux halo) are staged in LDS for
+//    the x- and y-derivatives; the four x-halo flux columns load their
+//    z-neighbours directly;
+//  - fluxes, differences and the update then proceed as in k_ns_rhs.
+// T, every derivative and every flux are the same expressions of the same
+// values as in k_ns_grads and k_ns_rhs, so the results are bit-identical to
+// the stored-gradient chain.
+constexpr int kFusedRows = 4;
+constexpr bool kFusedYRing = true;
+// planes of a fused z-segment at least (each re-reads 8 planes of primitives)
+constexpr int kFusedMinSegPlanes = 16;
+
+// fused-residual argument slots
+enum { FPR = 0, FQR = 5, FDR = 10 };
+
+// u, v, w, T of the primitives at storage offset o
+__device__ __forceinline__ void ns_uvwt(const KArgs &a, int64_t o, double gm2, double out[4]) {
+  out[0] = gp(a.p[FPR + 1])[o];
+  out[1] = gp(a.p[FPR + 2])[o];
+  out[2] = gp(a.p[FPR + 3])[o];
+  out[3] = (gm2 * gp(a.p[FPR + 4])[o]) / gp(a.p[FPR])[o];
+}
+
+// the 17 flux inputs at one point from its rho, p, the staged plane (row
+// sy, column sx of sv) and its z-column values zc[0..4] (planes c-2 .. c+2)
+template <int R, int C>
+__device__ __forceinline__ void ns_inputs(const double (&sv)[4][R][C], int sy, int sx, const double (&zc)[5][4],
+                                          double rho, double p, double inv, double v[17]) {
+  v[PR] = rho;
+  v[PU] = zc[2][0];
+  v[PV] = zc[2][1];
+  v[PW] = zc[2][2];
+  v[PP] = p;
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    v[GUX + 3 * c] = deriv(sv[c][sy][sx - 2], sv[c][sy][sx - 1], sv[c][sy][sx + 1], sv[c][sy][sx + 2], inv);
+    v[GUX + 3 * c + 1] = deriv(sv[c][sy - 2][sx], sv[c][sy - 1][sx], sv[c][sy + 1][sx], sv[c][sy + 2][sx], inv);
+    v[GUX + 3 * c + 2] = deriv(zc[0][c], zc[1][c], zc[3][c], zc[4][c], inv);
+  }
+  v[GTX] = deriv(sv[3][sy][sx - 2], sv[3][sy][sx - 1], sv[3][sy][sx + 1], sv[3][sy][sx + 2], inv);
+  v[GTX + 1] = deriv(sv[3][sy - 2][sx], sv[3][sy - 1][sx], sv[3][sy + 1][sx], sv[3][sy + 2][sx], inv);
+  v[GTX + 2] = deriv(zc[0][3], zc[1][3], zc[3][3], zc[4][3], inv);
+}
+
+template <bool kFirst, int PH, bool kYRing>
+__global__ void __launch_bounds__(64 * PH) k_ns_rhs_fused(const KArgs *__restrict__ ap) {
+  ARGS
+  // u, v, w, T at plane c: rows y = j0-4 .. j0+PH+3, columns x = i0-4 .. i0+67
+  __shared__ double sv[4][PH + 8][72];
+  __shared__ double sfx[5][PH][68];      // x-flux at plane c, x = i0-2 .. i0+65, the patch's rows
+  __shared__ double sfy[5][PH + 4][64];  // y-flux at plane c, y = j0-2 .. j0+PH+1, the patch's columns
+  ZMARCH_BEGIN(PH)
+  const double inv = a.c[0], mu = a.c[1], kappa = a.c[2], dt = a.c[3], A = a.c[4], B = a.c[5], gm2 = a.c[6];
+  // columns and rows whose primitives exist: the range plus 4 on each side
+  const int xl = a.lo[0] - 4, xh = a.hi[0] + 4, yl = a.lo[1] - 4, yh = a.hi[1] + 4;
+  const bool inx = i >= a.lo[0] && i < a.hi[0];
+  // own column (i, j): flux point if `own`; loaded wherever it exists
+  const bool own_ld = i >= xl && i < xh && j < yh;
+  // y-halo column (i, hy): a flux point for the patch's y differences
+  const bool yh_flux = yhalo && inx && hy < ye;
+  const bool yh_ld = yhalo && i >= xl && i < xh && hy >= yl && hy < yh;
+  // staged-only points of plane c: outer rows (i, oy); the y-halo rows' x
+  // extension (hx, hy) for tx < 4; the patch rows' x extension (ox, j) for tx < 8
+  const int orow = ty < 2 ? ty : PH + 4 + ty, oy = j0 - 4 + orow;
+  const bool oy_ld = yhalo && inx && oy >= yl && oy < yh;
+  const bool hxy_ld = yhalo && tx < 4 && hx >= xl && hx < xh && hy >= yl && hy < yh;
+  const int om = tx < 4 ? tx : 64 + tx, ox = i0 - 4 + om;
+  const bool ox_ld = tx < 8 && ox >= xl && ox < xh && j < yh;
+  // x-halo flux columns i0-2, i0-1, i0+64, i0+65 (tx = 2 .. 5) in the patch's rows
+  const bool xh_flux = tx >= 2 && tx < 6 && ox >= xs && ox < xe && j < a.hi[1];
+  const int64_t ycol = (int64_t)hy * a.pitch + i;
+  const int64_t ocol = (int64_t)oy * a.pitch + i, hcol = (int64_t)hy * a.pitch + hx;
+  const int64_t xcol = (int64_t)j * a.pitch + ox;
+  double za[5][4], zb[5][4];  // own / y-halo column: u, v, w, T at planes c-2 .. c+2
+  double ra[3][2], rb[3][2];  // own / y-halo column: rho, p at planes c .. c+2
+  double fz[5][5];            // own column's z-flux, planes k-2 .. k+2
+  double rxy[3][5];           // own column's x/y residual part, planes k .. k+2
+  auto load_ring = [&](bool ok, int64_t o, double (&z)[5][4], double (&r)[3][2], int zq, int rq) {
+    if (ok) {
+      ns_uvwt(a, o, gm2, z[zq]);
+      if (rq >= 0) {
+        r[rq][0] = gp(a.p[FPR])[o];
+        r[rq][1] = gp(a.p[FPR + 4])[o];
+      }
+    }
+  };
+#pragma unroll
+  for (int q = 0; q < 4; q++) {  // planes kb-4 .. kb-1
+    const int64_t pq = (int64_t)(kb - 4 + q) * a.plane;
+    load_ring(own_ld, pq + col, za, ra, q, q >= 2 ? q - 2 : -1);
+    if (kYRing) load_ring(yh_ld, pq + ycol, zb, rb, q, q >= 2 ? q - 2 : -1);
+  }
+#pragma unroll 1
+  for (int c = kb - 2; c < ke + 2; c++) {
+    const int64_t pc = (int64_t)c * a.plane, pm = pc + 2 * a.plane;
+    load_ring(own_ld, pm + col, za, ra, 4, 2);
+    double yv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // without the ring: the y-halo column's rho, u, v, w, p at plane c
+    if (kYRing) {
+      load_ring(yh_ld, pm + ycol, zb, rb, 4, 2);
+    } else if (yh_ld) {
+      const int64_t o = pc + ycol;
+      yv[0] = gp(a.p[FPR])[o];
+      yv[1] = gp(a.p[FPR + 1])[o];
+      yv[2] = gp(a.p[FPR + 2])[o];
+      yv[3] = gp(a.p[FPR + 3])[o];
+      yv[4] = gp(a.p[FPR + 4])[o];
+    }
+    const bool xy = c >= kb && c < ke;  // the same for the whole block
+    // ---- stage plane c
+    double hv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // the x-halo flux column's rho, u, v, w, p at plane c
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+      if (own_ld) sv[f][ty + 4][tx + 4] = za[2][f];
+      if (kYRing && yh_ld) sv[f][hn + 2][tx + 4] = zb[2][f];
+    }
+    if (!kYRing && yh_ld) {
+      sv[0][hn + 2][tx + 4] = yv[1];
+      sv[1][hn + 2][tx + 4] = yv[2];
+      sv[2][hn + 2][tx + 4] = yv[3];
+      sv[3][hn + 2][tx + 4] = (gm2 * yv[4]) / yv[0];
+    }
+    if (oy_ld) {
+      double v[4];
+      ns_uvwt(a, pc + ocol, gm2, v);
+#pragma unroll
+      for (int f = 0; f < 4; f++) sv[f][orow][tx + 4] = v[f];
+    }
+    if (hxy_ld) {
+      double v[4];
+      ns_uvwt(a, pc + hcol, gm2, v);
+#pragma unroll
+      for (int f = 0; f < 4; f++) sv[f][hn + 2][hm + 2] = v[f];
+    }
+    if (ox_ld) {
+      const int64_t o = pc + xcol;
+      hv[0] = gp(a.p[FPR])[o];
+      hv[1] = gp(a.p[FPR + 1])[o];
+      hv[2] = gp(a.p[FPR + 2])[o];
+      hv[3] = gp(a.p[FPR + 3])[o];
+      hv[4] = gp(a.p[FPR + 4])[o];
+      sv[0][ty + 4][om] = hv[1];
+      sv[1][ty + 4][om] = hv[2];
+      sv[2][ty + 4][om] = hv[3];
+      sv[3][ty + 4][om] = (gm2 * hv[4]) / hv[0];
+    }
+    __syncthreads();
+    // ---- fluxes of plane c
+    if (own) {
+      double v[17];
+      ns_inputs(sv, ty + 4, tx + 4, za, ra[0][0], ra[0][1], inv, v);
+      ns_flux<2>(v, mu, kappa, fz[4]);
+      if (xy) {
+        double f[5];
+        ns_flux<0>(v, mu, kappa, f);
+#pragma unroll
+        for (int q = 0; q < 5; q++) sfx[q][ty][tx + 2] = f[q];
+        ns_flux<1>(v, mu, kappa, f);
+#pragma unroll
+        for (int q = 0; q < 5; q++) sfy[q][ty + 2][tx] = f[q];
+      }
+    }
+    if (xy) {
+      if (yh_flux) {
+        double v[17], f[5];
+        if (kYRing) {
+          ns_inputs(sv, hn + 2, tx + 4, zb, rb[0][0], rb[0][1], inv, v);
+        } else {
+          double zc[5][4];
+#pragma unroll
+          for (int q = 0; q < 5; q++) {
+            if (q == 2) {
+              zc[2][0] = yv[1];
+              zc[2][1] = yv[2];
+              zc[2][2] = yv[3];
+              zc[2][3] = 0.0;  // T at the point itself is not used by its derivatives
+            } else {
+              ns_uvwt(a, pc + (int64_t)(q - 2) * a.plane + ycol, gm2, zc[q]);
+            }
+          }
+          ns_inputs(sv, hn + 2, tx + 4, zc, yv[0], yv[4], inv, v);
+        }
+        ns_flux<1>(v, mu, kappa, f);
+#pragma unroll
+        for (int q = 0; q < 5; q++) sfy[q][hn][tx] = f[q];
+      }
+      if (xh_flux) {
+        double zc[5][4];
+#pragma unroll
+        for (int q = 0; q < 5; q++) {
+          if (q == 2) {
+            zc[2][0] = hv[1];
+            zc[2][1] = hv[2];
+            zc[2][2] = hv[3];
+            zc[2][3] = 0.0;  // T at the point itself is not used by its derivatives
+          } else {
+            ns_uvwt(a, pc + (int64_t)(q - 2) * a.plane + xcol, gm2, zc[q]);
+          }
+        }
+        double v[17], f[5];
+        ns_inputs(sv, ty + 4, om, zc, hv[0], hv[4], inv, v);
+        ns_flux<0>(v, mu, kappa, f);
+#pragma unroll
+        for (int q = 0; q < 5; q++) sfx[q][ty][om - 2] = f[q];
+      }
+      __syncthreads();
+      if (out) {
+#pragma unroll
+        for (int q = 0; q < 5; q++) {
+          double r = 0.0;
+          r -= deriv(sfx[q][ty][tx], sfx[q][ty][tx + 1], sfx[q][ty][tx + 3], sfx[q][ty][tx + 4], inv);
+          r -= deriv(sfy[q][ty][tx], sfy[q][ty + 1][tx], sfy[q][ty + 3][tx], sfy[q][ty + 4][tx], inv);
+          rxy[2][q] = r;
+        }
+      }
+    }
+    __syncthreads();  // the next plane overwrites the staged values and fluxes
+    if (c >= kb + 2 && out) {
+      const int64_t o = pc - 2 * a.plane + col;  // plane k = c - 2
+#pragma unroll
+      for (int q = 0; q < 5; q++) {
+        const double res = rxy[0][q] - deriv(fz[0][q], fz[1][q], fz[3][q], fz[4][q], inv);
+        const double d = kFirst ? dt * res : A * gp(a.p[FDR + q])[o] + dt * res;
+        gp(a.p[FDR + q])[o] = d;
+        gp(a.p[FQR + q])[o] = gp(a.p[FQR + q])[o] + B * d;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+      for (int f = 0; f < 4; f++) {
+        za[q][f] = za[q + 1][f];
+        if (kYRing) zb[q][f] = zb[q + 1][f];
+      }
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      ra[q][0] = ra[q + 1][0];
+      ra[q][1] = ra[q + 1][1];
+      if (kYRing) {
+        rb[q][0] = rb[q + 1][0];
+        rb[q][1] = rb[q + 1][1];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 5; q++) {
+#pragma unroll
+      for (int r = 0; r < 4; r++) fz[r][q] = fz[r + 1][q];
+      rxy[0][q] = rxy[1][q];
+      rxy[1][q] = rxy[2][q];
+    }
+  }
+}
+
+template <int PH, int MINSEG>
+void launch_zmarch_seg(void (*kern)(const KArgs *), const KArgs &a, const KArgs *dev, int ndim, void *s) {
+  const int nx = a.hi[0] - x_origin(a.lo[0]), ny = a.hi[1] - a.lo[1], nz = ndim == 3 ? a.hi[2] - a.lo[2] : 1;
+  if (a.hi[0] <= a.lo[0] || ny <= 0 || nz <= 0) return;
+  const int gx = (nx + 63) / 64, gy = (ny + PH - 1) / PH;
+  const int per = gx * gy * 64 * PH;
+  const int want = (kTargetThreads + per - 1) / per;
+  const int most = (nz + MINSEG - 1) / MINSEG;
+  const int nseg = want < most ? want : most;
+  hipLaunchKernelGGL(kern, dim3(gx, gy, nseg > 1 ? nseg : 1), dim3(64, PH, 1), 0, (hipStream_t)s, dev);
+}
+
 #define L(name, kern) \
   void name(const KArgs &a, const KArgs *d, int nd, void *s) { launch_point(kern, a, d, nd, s); }
 L(l_init, k_ns_init)
@@ -299,6 +572,12 @@ void l_rhs_first(const KArgs &a, const KArgs *d, int nd, void *s) {
 void l_rhs(const KArgs &a, const KArgs *d, int nd, void *s) {
   launch_zmarch<kRhsRows>(k_ns_rhs<false, kRhsRows>, a, d, nd, s);
 }
+void l_rhs_fused_first(const KArgs &a, const KArgs *d, int nd, void *s) {
+  launch_zmarch_seg<kFusedRows, kFusedMinSegPlanes>(k_ns_rhs_fused<true, kFusedRows, kFusedYRing>, a, d, nd, s);
+}
+void l_rhs_fused(const KArgs &a, const KArgs *d, int nd, void *s) {
+  launch_zmarch_seg<kFusedRows, kFusedMinSegPlanes>(k_ns_rhs_fused<false, kFusedRows, kFusedYRing>, a, d, nd, s);
+}
 #undef L
 
 }  // namespace
@@ -309,6 +588,8 @@ void register_ns3d_kernels(KernelInfo *t) {
   t[OOC_K_NS_GRADS] = {"ns_grads", 17, 17, 2, 0, 0, kPointGrid, l_grads};
   t[OOC_K_NS_RHS_FIRST] = {"ns_rhs_first", 27, 27, 6, 0, 0, kPointGrid, l_rhs_first};
   t[OOC_K_NS_RHS] = {"ns_rhs", 27, 27, 6, 0, 0, kPointGrid, l_rhs};
+  t[OOC_K_NS_RHS_FUSED_FIRST] = {"ns_rhs_fused_first", 15, 15, 7, 0, 0, kPointGrid, l_rhs_fused_first};
+  t[OOC_K_NS_RHS_FUSED] = {"ns_rhs_fused", 15, 15, 7, 0, 0, kPointGrid, l_rhs_fused};
 }
 
 }  // namespace ooc

@@ -1107,7 +1107,7 @@ void check_loop(ooc_ctx *c, int kid, const int64_t range[6], int nargs, const oo
       case OOC_ARG_DAT: {
         if (a.handle < 0 || a.handle >= (int)c->fields.size()) throw ArgError(OOC_E_ARG, "bad field handle");
         if (a.access < OOC_READ || a.access > OOC_INC) throw ArgError(OOC_E_ARG, "bad access mode");
-        if (a.npts < 1 || a.npts > 64 || !a.offsets) throw ArgError(OOC_E_ARG, "bad stencil");
+        if (a.npts < 1 || a.npts > 256 || !a.offsets) throw ArgError(OOC_E_ARG, "bad stencil");
         r.offs.assign((size_t)a.npts * 3, 0);
         for (int p = 0; p < a.npts; p++)
           for (int d = 0; d < c->ndim; d++) r.offs[3 * p + d] = a.offsets[p * c->ndim + d];

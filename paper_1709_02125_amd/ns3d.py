@@ -19,15 +19,35 @@ TWO_PI = 2.0 * math.pi
 RK_A = (0.0, -5.0 / 9.0, -153.0 / 128.0)
 RK_B = (1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0)
 K_MIRROR = 1
-K_INIT, K_PRIMS, K_GRADS, K_RHS_FIRST, K_RHS = 200, 201, 202, 203, 204
+K_INIT, K_PRIMS, K_GRADS, K_RHS_FIRST, K_RHS, K_RHS_FUSED_FIRST, K_RHS_FUSED = 200, 201, 202, 203, 204, 205, 206
 
 Q = ["q_r", "q_ru", "q_rv", "q_rw", "q_re"]
 D = ["d_r", "d_ru", "d_rv", "d_rw", "d_re"]
 P = ["p_r", "p_u", "p_v", "p_w", "p_p"]
 G = ["g_ux", "g_uy", "g_uz", "g_vx", "g_vy", "g_vz", "g_wx", "g_wy", "g_wz", "g_tx", "g_ty", "g_tz"]
 FIELDS = Q + D + P + G
+FIELDS_FUSED = Q + D + P   # gradients evaluated inside the residual kernel
 STAR = ((1, 0, 0), (-1, 0, 0), (2, 0, 0), (-2, 0, 0), (0, 1, 0), (0, -1, 0), (0, 2, 0), (0, -2, 0),
         (0, 0, 1), (0, 0, -1), (0, 0, 2), (0, 0, -2))
+
+
+def _fused_stencil():
+    """Points of the primitives the fused residual reads: the fluxes at the
+    points a e_A (a in 0, +-1, +-2) of the 5-point difference along axis A,
+    each from the 5-point differences b e_B of the primitives (73 points)."""
+    pts = set()
+    for A in range(3):
+        for B in range(3):
+            for a in (0, 1, -1, 2, -2):
+                for b in (0, 1, -1, 2, -2):
+                    o = [0, 0, 0]
+                    o[A] += a
+                    o[B] += b
+                    pts.add(tuple(o))
+    return tuple(sorted(pts))
+
+
+FUSED_STENCIL = _fused_stencil()
 
 
 def stable_dt(n: int, cfl: float = 0.5) -> float:
@@ -35,24 +55,27 @@ def stable_dt(n: int, cfl: float = 0.5) -> float:
     return cfl * (TWO_PI / n) / (1.0 + 1.0 / MACH)
 
 
-def footprint_bytes(n: int) -> int:
-    return len(FIELDS) * (n + 2 * NH) ** 3 * 8
+def footprint_bytes(n: int, fused: bool = False) -> int:
+    return len(FIELDS_FUSED if fused else FIELDS) * (n + 2 * NH) ** 3 * 8
 
 
-def device_footprint_bytes(n: int) -> int:
+def device_footprint_bytes(n: int, fused: bool = False) -> int:
     pitch = ooc.row_pitch(n, NH)
     plane = pitch * (n + 2 * NH + 1)
     per = ((n + 2 * NH) * plane * 8 + 255) // 256 * 256
-    return len(FIELDS) * per + (1 << 20)
+    return len(FIELDS_FUSED if fused else FIELDS) * per + (1 << 20)
 
 
 class NS3D:
     """prims: interior arrays (rho, u, v, w, p), indexed [z, y, x]."""
 
     def __init__(self, n: int, prims, budget: int, flags: int = 0, re: float = 1600.0, bind: bool = True,
-                 cyclic_after_init: bool = True, plan_only: bool = False):
-        """plan_only: a context without storage, for planning schedules only."""
+                 cyclic_after_init: bool = True, plan_only: bool = False, fused: bool = False):
+        """plan_only: a context without storage, for planning schedules only;
+        fused: the residual evaluates the gradients itself (15 fields, no
+        gradient loop) instead of reading the 12 stored gradient fields."""
         self.n = n
+        self.fused = fused
         if plan_only:
             flags |= ooc.FLAG_PLAN_ONLY
             bind = False
@@ -65,7 +88,7 @@ class NS3D:
         self.dt = stable_dt(n)
         self.f = {}
         m = n + 2 * NH
-        for name in FIELDS:
+        for name in (FIELDS_FUSED if fused else FIELDS):
             init = None
             if name in P and not plan_only:
                 init = np.zeros((m, m, m))
@@ -103,10 +126,17 @@ class NS3D:
             self._mirror_q((full, full, (-1 - m, -m)), (0, 0, 2 * m + 1), odd)
             self._mirror_q((full, full, (n + m, n + m + 1)), (0, 0, -2 * m - 1), odd)
         self.ctx.par_loop(K_PRIMS, (full, full, full), [self.d(x) for x in Q] + [self.d(x, WRITE) for x in P])
+        first = s == 0
+        if self.fused:
+            self.ctx.par_loop(K_RHS_FUSED_FIRST if first else K_RHS_FUSED, ((0, n), (0, n), (0, n)),
+                              [self.d(x, READ, *FUSED_STENCIL) for x in P] + [self.d(x, RW) for x in Q] +
+                              [self.d(x, WRITE if first else RW) for x in D] +
+                              [Const(self.inv), Const(self.mu), Const(self.kappa), Const(self.dt), Const(RK_A[s]),
+                               Const(RK_B[s]), Const(self.gm2)])
+            return
         g2 = (-2, n + 2)
         self.ctx.par_loop(K_GRADS, (g2, g2, g2), [self.d(x, READ, *STAR) for x in P] +
                           [self.d(x, WRITE) for x in G] + [Const(self.inv), Const(self.gm2)])
-        first = s == 0
         self.ctx.par_loop(K_RHS_FIRST if first else K_RHS, ((0, n), (0, n), (0, n)),
                           [self.d(x, READ, *STAR) for x in P] + [self.d(x, READ, *STAR) for x in G] +
                           [self.d(x, RW) for x in Q] + [self.d(x, WRITE if first else RW) for x in D] +

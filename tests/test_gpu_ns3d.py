@@ -12,14 +12,15 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 
 
-def gpu_ns(n, steps, tile_rows=0, chain_steps=0, slots=0, incore=False, flags=0, budget=None, prims=None):
+def gpu_ns(n, steps, tile_rows=0, chain_steps=0, slots=0, incore=False, flags=0, budget=None, prims=None,
+           fused=False):
     prims = prims if prims is not None else tgv_initial_state(n)
     if incore:
         flags |= ooc.FLAG_INCORE
-        budget = N.device_footprint_bytes(n)
+        budget = N.device_footprint_bytes(n, fused)
     elif budget is None:
-        budget = 8 * N.device_footprint_bytes(n)
-    app = N.NS3D(n, prims, budget=budget, flags=flags)
+        budget = 8 * N.device_footprint_bytes(n, fused)
+    app = N.NS3D(n, prims, budget=budget, flags=flags, fused=fused)
     app.ctx.set_schedule(tile_rows=tile_rows, chain_steps=chain_steps, slots=slots)
     app.initialise()
     app.run(steps)
@@ -90,6 +91,43 @@ def test_ns3d_two_block_columns_match_oracle_and_incore():
         say(q, e)
         assert e <= TOL, q
 
+
+
+@pytest.mark.parametrize("tile_rows,chain_steps,slots,flags", [
+    (0, 1, 3, 0), (3, 2, 2, ooc.FLAG_PREFETCH), (5, 3, 2, ooc.FLAG_PREFETCH), (7, 1, 4, ooc.FLAG_FUSE)])
+def test_ns3d_fused_residual_equals_stored_gradients(tile_rows, chain_steps, slots, flags):
+    # The residual that evaluates the gradients itself (15 fields) against
+    # the chain with the 12 stored gradient fields: bit for bit, in core and
+    # tiled over several schedules
+    n, steps = 20, 3
+    say("case: ns3d fused residual vs stored gradients", tile_rows, chain_steps, slots, flags)
+    ref, _ = gpu_ns(n, steps, incore=True)
+    inc, _ = gpu_ns(n, steps, incore=True, fused=True)
+    got, st = gpu_ns(n, steps, tile_rows=tile_rows, chain_steps=chain_steps, slots=slots, flags=flags,
+                     budget=16 * N.device_footprint_bytes(n, True), fused=True)
+    for q in N.Q:
+        assert np.array_equal(inc[q], ref[q]), q
+        assert np.array_equal(got[q], ref[q]), q
+
+
+def test_ns3d_fused_two_block_columns_match_oracle():
+    # x over two 64-wide block columns with a ragged tail, tiled with 2-step
+    # chains: the fused residual against the oracle and, bit for bit, against
+    # the stored-gradient chain in core
+    n, steps = 72, 2
+    say("case: ns3d 72^3 fused residual, tiled vs oracle vs stored gradients")
+    got, st = gpu_ns(n, steps, tile_rows=9, chain_steps=2, fused=True)
+    ref, _ = gpu_ns(n, steps, incore=True)
+    assert st["ntiles_last"] >= 4
+    o = on.NS3D(n)
+    o.set_primitives(*tgv_initial_state(n))
+    for _ in range(steps):
+        o.step(on.stable_dt(n))
+    for q in N.Q:
+        e = rel_err(got[q], o.interior(q))
+        say(q, e)
+        assert e <= TOL, q
+        assert np.array_equal(got[q], ref[q]), q
 
 
 @pytest.mark.parametrize("k", [6, 2])
