@@ -6,8 +6,8 @@ roofline, the host-link throughput, and the CPU oracle timed on a sample.
 Workloads (one step = one time step over the whole grid):
   hydro2d (default)  15360 x 15360 FP64, 25 fields, 55-loop chain, budget 16e9 B
   hydro3d            640^3 FP64, 30 fields, 82-loop chain, budget 1/3 of the fields
-  ns3d               512^3 FP64, 27 fields, 45 loops per step, budget 1/3 of the fields,
-                     chains of --chain-steps steps
+  ns3d               512^3 FP64, 15 fields (residual evaluates the gradients; --stored-gradients:
+                     27 fields), budget 1/3 of the fields, chains of --chain-steps steps
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload hydro2d|hydro3d|ns3d]
 """
 import argparse
@@ -35,7 +35,7 @@ H2D_NAMES = ["h2d_eos", "h2d_eos_p", "h2d_visc", "h2d_pdv_pred", "h2d_pdv_corr",
 H3D_NAMES = ["h3d_visc", "h3d_pdv_pred", "h3d_pdv_corr", "h3d_accel"] + \
             ["h3d_%s_%s" % (k, a) for k in ("flux", "adv_vol", "adv_flux", "adv_cell", "nflux", "nmass",
                                             "mflux", "vel") for a in "xyz"] + ["h3d_dt"]
-NS_NAMES = ["ns_init", "ns_prims", "ns_grads", "ns_rhs_first", "ns_rhs"]
+NS_NAMES = ["ns_init", "ns_prims", "ns_grads", "ns_rhs_first", "ns_rhs", "ns_rhs_fused_first", "ns_rhs_fused"]
 COMMON = {1: "mirror", 2: "fill", 3: "sum_prod"}
 
 
@@ -46,6 +46,32 @@ def ablations(pf):
     uploaded only once the previous chain's last tile has run), and both
     Prefetch and Cyclic off (write-first data is downloaded too)."""
     return [("no_prefetch_cyclic", 0, {}), ("no_prefetch_no_cyclic", 0, {"cyclic": False})]
+
+
+def summary_variants(pf, every=10):
+    """The headline run with the field summary (volume, mass, internal and
+    kinetic energy, pressure) read every `every` steps, the periodic
+    diagnostic the paper names as a cause of its CloverLeaf 2D gap (Section
+    5.3): folded into that step's chain, and as a chain of its own."""
+    return [("field_summary_every_%d_folded" % every, pf, {"summary": ("folded", every)}),
+            ("field_summary_every_%d_separate" % every, pf, {"summary": ("separate", every)})]
+
+
+def summary_runner(app, mode, every):
+    """A step loop for timed_run that queues the field summary after every
+    `every`-th step and reads it (each read waits for the device)."""
+    def run(steps):
+        for s in range(1, steps + 1):
+            app.queue_step()
+            if s % every:
+                app.ctx.submit()
+                continue
+            if mode == "separate":
+                app.ctx.submit()
+            app.queue_summary()
+            app.summary()
+        app.ctx.execute()
+    return run
 
 
 class Workload:
@@ -79,7 +105,8 @@ class Hydro2DWork(Workload):
         return h2.Hydro2D(self.n, self.n, self.rho, self.ene, budget=budget, flags=flags,
                           resident_geometry=opts.get("resident_geometry", self.args.resident_geometry),
                           cyclic_after_init=opts.get("cyclic", not self.args.no_cyclic),
-                          resident_state=opts.get("resident_state", self.args.resident_state))
+                          resident_state=opts.get("resident_state", self.args.resident_state),
+                          summary="summary" in opts)
 
     def variants(self):
         from paper_1709_02125_amd import ooc
@@ -88,30 +115,16 @@ class Hydro2DWork(Workload):
                 ("fp32_stream_resident_geometry", pf | ooc.FLAG_FP32_STREAM, {"resident_geometry": True}),
                 ("resident_geometry", pf, {"resident_geometry": True}),
                 ("resident_state", pf, {"resident_state": True}),
-                ("resident_state_fused", pf | ooc.FLAG_FUSE, {"resident_state": True})]
+                ("resident_state_fused", pf | ooc.FLAG_FUSE, {"resident_state": True}),
+                *summary_variants(pf)]
 
     def describe(self):
         return ("hydro2d proxy %dx%d FP64, 25 fields, 55-loop chain per step, device budget %.3g B "
                 "(footprint %.3g B, %.2fx oversubscribed), tiles along y" %
                 (self.n, self.n, self.budget, self.footprint, self.footprint / self.budget))
 
-    def cpu_baseline(self, target_s=15.0):
-        import oracle
-        import oracle.hydro2d as oh
-        from paper_1709_02125_amd.inputs import hydro_initial_state
-        oracle.build(force=False)
-        nx, ny = self.n, max(64, self.n // 2)
-        rho, ene = hydro_initial_state((nx, ny))
-        o = oh.Hydro2D(nx, ny)
-        o.set_state(rho, ene)
-        dt = o.dt()
-        steps, t0 = 0, time.perf_counter()
-        while steps < 20 and (time.perf_counter() - t0) < target_s:
-            dt = o.step(dt)
-            steps += 1
-        sec = time.perf_counter() - t0
-        return nx * ny * steps / sec, "%d x %d cells (same width as the benchmark grid), %d steps, %.1f s" % (
-            nx, ny, steps, sec)
+    def cpu_baseline(self, target_s=15.0, one_thread=False):
+        return cpu_hydro2d(self.n, target_s, one_thread)
 
 
 class Hydro3DWork(Workload):
@@ -153,24 +166,8 @@ class Hydro3DWork(Workload):
                 "(footprint %.3g B, %.2fx oversubscribed), tiles along z" %
                 (self.n, self.budget, self.footprint, self.footprint / self.budget))
 
-    def cpu_baseline(self, target_s=15.0):
-        import oracle
-        import oracle.hydro3d as oh
-        from paper_1709_02125_amd.inputs import hydro_initial_state
-        oracle.build(force=False)
-        dims = (self.n, self.n, max(8, self.n // 12))
-        rho, ene = hydro_initial_state(dims)
-        o = oh.Hydro3D(*dims)
-        o.set_state(rho, ene)
-        dt = o.dt()
-        steps, t0 = 0, time.perf_counter()
-        while steps < 40 and (time.perf_counter() - t0) < target_s:
-            dt = o.step(dt)
-            steps += 1
-        sec = time.perf_counter() - t0
-        cells = dims[0] * dims[1] * dims[2]
-        return cells * steps / sec, "%d x %d x %d cells (a z-slab of the benchmark grid), %d steps, %.1f s" % (
-            dims + (steps, sec))
+    def cpu_baseline(self, target_s=15.0, one_thread=False):
+        return cpu_hydro3d(self.n, target_s, one_thread)
 
 
 class NS3DWork(Workload):
@@ -179,20 +176,23 @@ class NS3DWork(Workload):
         from paper_1709_02125_amd import ns3d as N
         from paper_1709_02125_amd.inputs import tgv_initial_state
         self.mod = N
+        self.fused = not args.stored_gradients
         self.n = args.n or 512
         self.cells = self.n ** 3
-        self.footprint = N.footprint_bytes(self.n)
+        self.footprint = N.footprint_bytes(self.n, self.fused)
         self.budget = int(args.budget) if args.budget else self.footprint // 3
         log("generating input %d^3" % self.n)
         self.prims = tgv_initial_state(self.n)
         self.knames = {**COMMON, **{200 + i: s for i, s in enumerate(NS_NAMES)}}
-        self.dominant = 200 + NS_NAMES.index("ns_rhs")
+        self.dominant = 200 + NS_NAMES.index("ns_rhs_fused" if self.fused else "ns_rhs")
 
     def make(self, budget, flags, incore=False, **opts):
         N = self.mod
         if incore:
-            return N.NS3D(self.n, self.prims, budget=N.device_footprint_bytes(self.n), flags=flags)
-        app = N.NS3D(self.n, self.prims, budget=budget, flags=flags, cyclic_after_init=opts.get("cyclic", not self.args.no_cyclic))
+            return N.NS3D(self.n, self.prims, budget=N.device_footprint_bytes(self.n, self.fused), flags=flags,
+                          fused=self.fused)
+        app = N.NS3D(self.n, self.prims, budget=budget, flags=flags, fused=self.fused,
+                     cyclic_after_init=opts.get("cyclic", not self.args.no_cyclic))
         app.ctx.set_schedule(tile_rows=opts.get("tile_rows", self.args.tile_rows),
                              chain_steps=opts.get("chain_steps", self.args.chain_steps),
                              slots=opts.get("slots", self.args.slots))
@@ -208,58 +208,142 @@ class NS3DWork(Workload):
                  {"chain_steps": 2, "tile_rows": 32, "slots": 2})]
 
     def describe(self):
-        return ("ns3d proxy %d^3 FP64 (Taylor-Green, Mach 0.1), 27 fields, 45 loops per step, chains of %d "
+        form = ("15 fields (gradients evaluated in the residual kernel), 42 loops per step" if self.fused else
+                "27 fields (12 stored gradients), 45 loops per step")
+        return ("ns3d proxy %d^3 FP64 (Taylor-Green, Mach 0.1), %s, chains of %d "
                 "steps, device budget %.3g B (footprint %.3g B, %.2fx oversubscribed), tiles along z" %
-                (self.n, self.args.chain_steps, self.budget, self.footprint, self.footprint / self.budget))
+                (self.n, form, self.args.chain_steps, self.budget, self.footprint, self.footprint / self.budget))
 
-    def cpu_baseline(self, target_s=15.0):
-        import oracle
-        import oracle.ns3d as on
-        from paper_1709_02125_amd.inputs import tgv_initial_state
-        oracle.build(force=False)
-        n = max(16, self.n // 2)
-        o = on.NS3D(n)
-        o.set_primitives(*tgv_initial_state(n))
-        dt = on.stable_dt(n)
-        steps, t0 = 0, time.perf_counter()
-        while steps < 40 and (time.perf_counter() - t0) < target_s:
-            o.step(dt)
-            steps += 1
-        sec = time.perf_counter() - t0
-        return n ** 3 * steps / sec, "%d^3 points, %d steps, %.1f s" % (n, steps, sec)
+    def cpu_baseline(self, target_s=15.0, one_thread=False):
+        return cpu_ns3d(self.n, target_s, one_thread)
+
+
+def cpu_hydro2d(n, target_s, one_thread):
+    """The oracle on a bounded sample of the hydro2d grid: the benchmark's
+    width, half its height (a 256-row strip for the one-thread figure)."""
+    import oracle
+    import oracle.hydro2d as oh
+    from paper_1709_02125_amd.inputs import hydro_initial_state
+    oracle.build(force=False)
+    nx, ny = n, (min(256, n) if one_thread else max(64, n // 2))
+    rho, ene = hydro_initial_state((nx, ny))
+    o = oh.Hydro2D(nx, ny)
+    o.set_state(rho, ene)
+    dt = o.dt()
+    steps, t0 = 0, time.perf_counter()
+    while steps < 20 and (time.perf_counter() - t0) < target_s:
+        dt = o.step(dt)
+        steps += 1
+    sec = time.perf_counter() - t0
+    return nx * ny * steps / sec, "%d x %d cells (same width as the benchmark grid), %d steps, %.1f s" % (
+        nx, ny, steps, sec)
+
+
+def cpu_hydro3d(n, target_s, one_thread):
+    """The oracle on a z-slab of the hydro3d grid (8 planes for the
+    one-thread figure)."""
+    import oracle
+    import oracle.hydro3d as oh
+    from paper_1709_02125_amd.inputs import hydro_initial_state
+    oracle.build(force=False)
+    dims = (n, n, 8 if one_thread else max(8, n // 12))
+    rho, ene = hydro_initial_state(dims)
+    o = oh.Hydro3D(*dims)
+    o.set_state(rho, ene)
+    dt = o.dt()
+    steps, t0 = 0, time.perf_counter()
+    while steps < 40 and (time.perf_counter() - t0) < target_s:
+        dt = o.step(dt)
+        steps += 1
+    sec = time.perf_counter() - t0
+    cells = dims[0] * dims[1] * dims[2]
+    return cells * steps / sec, "%d x %d x %d cells (a z-slab of the benchmark grid), %d steps, %.1f s" % (
+        dims + (steps, sec))
+
+
+def cpu_ns3d(n, target_s, one_thread):
+    """The oracle on a smaller cube of the ns3d problem (n/2; 96 points per
+    axis for the one-thread figure)."""
+    import oracle
+    import oracle.ns3d as on
+    from paper_1709_02125_amd.inputs import tgv_initial_state
+    oracle.build(force=False)
+    m = min(96, n) if one_thread else max(16, n // 2)
+    o = on.NS3D(m)
+    o.set_primitives(*tgv_initial_state(m))
+    dt = on.stable_dt(m)
+    steps, t0 = 0, time.perf_counter()
+    while steps < 40 and (time.perf_counter() - t0) < target_s:
+        o.step(dt)
+        steps += 1
+    sec = time.perf_counter() - t0
+    return m ** 3 * steps / sec, "%d^3 points, %d steps, %.1f s" % (m, steps, sec)
+
+
+CPU_SAMPLES = {"hydro2d": (cpu_hydro2d, 15360), "hydro3d": (cpu_hydro3d, 640), "ns3d": (cpu_ns3d, 512)}
+
+
+def cpu_one_thread(workload, n, target_s=8.0):
+    """The oracle's one-thread rate on a small sample, in a child process
+    started with OMP_NUM_THREADS=1 (OpenMP reads it once per process)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; f, n0 = bench.CPU_SAMPLES[%r]; "
+            "v, s = f(%d or n0, %r, True); print(json.dumps([v, s]))" % (ROOT, workload, n, target_s))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        log("one-thread oracle sample failed: %s" % r.stderr[-500:])
+        return None
+    v, sample = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": v, "sample": sample}
 
 
 WORKLOADS = {"hydro2d": Hydro2DWork, "hydro3d": Hydro3DWork, "ns3d": NS3DWork}
 
 
-def timed_run(app, steps, warmup, knames, dom=None, timing=True):
-    """Warm up, then time `steps` steps with wall clock between device syncs.
-    With timing, every launch of the roofline kernel `dom` in the timed steps
-    is bracketed by hipEvents on the compute stream (the stream the loops run
-    on), so its average comes from the same region as the throughput.  `dom`
-    is the workload's dominant kernel: the one with the most time in an
-    in-core profile.  (Out of core, strip loops that overlap a download stall
-    and can add up to more; the warm-up times every kernel and reports them.)"""
+CALL_KINDS = ("upload copy", "download", "kernel launch", "stream wait", "event record", "other")
+
+
+def timed_run(app, steps, warmup, knames, dom=None, timing=True, repeats=1, run=None):
+    """Warm up, then time `steps` steps with wall clock between device syncs,
+    `repeats` times; the run with the median time is reported (its bytes,
+    tiles and time) and every run's ms per step is listed.  With timing,
+    every launch of the roofline kernel `dom` in the timed steps is bracketed
+    by hipEvents on the compute stream (the stream the loops run on), so its
+    average comes from the same region as the throughput.  `dom` is the
+    workload's dominant kernel: the one with the most time in an in-core
+    profile.  (Out of core, strip loops that overlap a download stall and can
+    add up to more; the warm-up times every kernel and reports them.)  `run`
+    replaces app.run (a step loop with extra work, e.g. a field summary)."""
     import torch
+    run = run or app.run
     if timing:
         app.ctx.set_timing(True)
-        app.run(warmup)
+        run(warmup)
         per = {kid: app.ctx.kernel_stats(kid)[0] for kid in knames}
         app.ctx.set_timing(True, kernel_id=dom)
     else:
-        app.run(warmup)
-    s0 = app.ctx.stats()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    app.run(steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    s1 = app.ctx.stats()
-    d = {k: s1[k] - s0[k] for k in ("bytes_h2d", "bytes_d2h", "bytes_edge", "bytes_hbm_alg", "tiles", "chains",
-                                     "launches")}
-    d["seconds"] = t1 - t0
+        run(warmup)
+    runs = []
+    for _ in range(repeats):
+        s0 = app.ctx.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s1 = app.ctx.stats()
+        d = {k: s1[k] - s0[k] for k in ("bytes_h2d", "bytes_d2h", "bytes_edge", "bytes_hbm_alg", "tiles",
+                                         "chains", "launches")}
+        d["seconds"] = t1 - t0
+        runs.append(d)
+    order = sorted(range(repeats), key=lambda q: runs[q]["seconds"])
+    d = runs[order[repeats // 2]]
+    d["runs_ms_per_step"] = [round(r["seconds"] / steps * 1e3, 3) for r in runs]
     d["issue_ms"] = s1["last_issue_ms"]
     d["max_call_ms"] = s1["max_call_ms"]
+    d["max_call"] = {"ms": round(s1["max_call_ms"], 2), "kind": CALL_KINDS[min(s1["max_call_kind"], 5)],
+                     "chains_before": s1["max_call_chain"]}
     d["ntiles"] = s1["ntiles_last"]
     d["tile_rows"] = s1["tile_rows"]
     d["slot_bytes"] = s1["slot_bytes"]
@@ -446,11 +530,172 @@ def copy_probe(nbytes=1 << 30, reps=3):
     del a, b
 
 
+def c5_main(args):
+    """Configuration 5: the hydro2d (15360^2, 16e9 B) or ns3d (512^3, 1/3
+    budget) grid with its streamed fields stored and moved as float32 (the
+    hydro2d form keeps the read-only geometry resident), on the schedule the
+    device-trained cost model proposes.  The model is trained on the timings
+    of an exhaustive sweep of the FP64 form of the same grid (the schedule
+    sweep configuration 4 records) and picks among the float32 form's
+    schedules from their planned features alone; the exhaustive float32 sweep
+    that follows is its yardstick (regret) and fallback.  The picked schedule
+    then runs `--steps` steps from the initial state (the error of every state
+    field against the FP64 oracle after those steps is stated) and, warmed,
+    `--steps` more timed ones (the throughput)."""
+    import torch
+    import numpy as np
+    from paper_1709_02125_amd import ooc, tune
+    torch.cuda.set_device(0)
+    f32 = ooc.FLAG_FP32_STREAM
+    steps = args.steps or 20
+    if args.workload == "ns3d":
+        from paper_1709_02125_amd import ns3d as N
+        from paper_1709_02125_amd.inputs import tgv_initial_state
+        n = args.n or 512
+        budget = int(args.budget) if args.budget else N.footprint_bytes(n) // 3
+        cands = tune.grid([8, 16, 24, 32, 48, 0], [1, 2, 3], [2, 3, 4])
+        workload = lambda fl: tune.ns3d_workload(n, budget, fl)
+        cells = n ** 3
+        names = N.Q
+
+        def fresh(h, k, S):
+            app = N.NS3D(n, tgv_initial_state(n), budget=budget, flags=ooc.FLAG_PREFETCH | f32)
+            app.ctx.set_schedule(tile_rows=h, chain_steps=k, slots=S)
+            return app
+
+        def incore():
+            return N.NS3D(n, tgv_initial_state(n), budget=N.device_footprint_bytes(n), flags=ooc.FLAG_INCORE)
+
+        def oracle_state():
+            import oracle.ns3d as on
+            o = on.NS3D(n)
+            o.set_primitives(*tgv_initial_state(n))
+            for q in range(steps):
+                o.step(on.stable_dt(n))
+                log("oracle ns3d step", q + 1)
+            out = {x: o.interior(x).copy() for x in names}
+            del o
+            return out
+
+        got_state = lambda app: {x: app.interior(x) for x in names}
+        form = ("ns3d proxy %d^3 (Taylor-Green, Mach 0.1), conserved fields stored and streamed as float32, "
+                "compute in FP64, device budget %.3g B (1/3 of the FP64 fields)" % (n, budget))
+    else:
+        from paper_1709_02125_amd import hydro2d as h2
+        from paper_1709_02125_amd.inputs import hydro_initial_state
+        n = args.n or 15360
+        budget = int(args.budget) if args.budget else 16_000_000_000
+        cands = tune.grid([384, 768, 1152, 1536, 0], [1], [2, 3, 4])
+        workload = lambda fl: tune.hydro2d_workload(n, budget, fl, resident_geometry=bool(fl & f32))
+        cells = n * n
+        names = ("rho0", "e0", "u0", "v0")
+
+        def fresh(h, k, S):
+            rho, ene = hydro_initial_state((n, n))
+            app = h2.Hydro2D(n, n, rho, ene, budget=budget, flags=ooc.FLAG_PREFETCH | f32, resident_geometry=True)
+            app.ctx.set_schedule(tile_rows=h, slots=S)
+            return app
+
+        def incore():
+            rho, ene = hydro_initial_state((n, n))
+            return h2.Hydro2D(n, n, rho, ene, budget=h2.device_footprint_bytes(n, n), flags=ooc.FLAG_INCORE)
+
+        def oracle_state():
+            import oracle.hydro2d as oh
+            rho, ene = hydro_initial_state((n, n))
+            o = oh.Hydro2D(n, n)
+            o.set_state(rho, ene)
+            del rho, ene
+            dt = o.dt()
+            for q in range(steps):
+                dt = o.step(dt)
+                log("oracle hydro2d step", q + 1)
+            out = {x: o.interior(x, x in ("u0", "v0")).copy() for x in names}
+            del o
+            return out
+
+        got_state = lambda app: {x: app.interior(x) for x in names}
+        form = ("hydro2d proxy %dx%d, state fields stored and streamed as float32, geometry resident, compute "
+                "in FP64, device budget %.3g B" % (n, n, budget))
+
+    def run_sweep(fl, what):
+        t = time.perf_counter()
+        app, plan_ctx, q, cl, rb = workload(fl)
+        recs = tune.sweep(app, plan_ctx, q, cl, rb, budget, cands, chains=2,
+                          log=lambda m: log("%s sweep: %s" % (what, m)))
+        app.close()
+        del app
+        torch.cuda.empty_cache()
+        log("%s sweep: %d schedules, %.0f s" % (what, len(recs), time.perf_counter() - t))
+        return recs
+
+    train = run_sweep(0, "FP64 (training)")
+    target = run_sweep(f32, "FP32 (yardstick)")
+    picks = [tune.transfer_regret(train, target, seed=seed) for seed in (1709, 1, 2)]
+    for r in picks:
+        log("cost model pick %s: regret %.3f, gain over default %s" % (r["pick"], r["regret"],
+                                                                       r["gain_over_default"]))
+    h, k, S = picks[0]["pick"]
+
+    # the picked schedule from the initial state: error after `steps` steps,
+    # then warmed, `steps` timed steps
+    app = fresh(h, k, S)
+    app.initialise()
+    app.run(steps)
+    got = got_state(app)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    app.run(steps)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    st = app.ctx.stats()
+    app.close()
+    del app
+    torch.cuda.empty_cache()
+    rate = cells * steps / sec
+    log("C5 picked schedule h=%d k=%d S=%d: %.3f s/step, %.3g upd/s" % (h, k, S, sec / steps, rate))
+    app = incore()
+    app.initialise()
+    app.run(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    app.run(steps)
+    torch.cuda.synchronize()
+    inc_sec = time.perf_counter() - t0
+    app.close()
+    del app
+    torch.cuda.empty_cache()
+    ref = oracle_state()
+    errs = {}
+    for x in names:
+        m = float(np.abs(ref[x]).max())
+        errs[x] = float(np.abs(got[x] - ref[x]).max() / m) if m else float(np.abs(got[x]).max())
+        log("FP32 stream error after %d steps, %s: %.3e" % (steps, x, errs[x]))
+    inc_rate = cells * steps / inc_sec
+    out = {"metric": METRIC, "value": rate, "unit": "grid-point updates/s", "n_gpus": 1, "steps": steps,
+           "warmup": steps, "ms_per_step": round(sec / steps * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": form, "cells": cells, "schedule": {"tile_rows": h, "chain_steps": k, "slots": S},
+                      "tiles": st["ntiles_last"], "picked_by": "cost model trained on the FP64 sweep"},
+           "incore_value": inc_rate, "pct_of_incore": round(100.0 * rate / inc_rate, 2),
+           "incore_ms_per_step": round(inc_sec / steps * 1e3, 3),
+           "cost_model": {"picks": picks, "train_schedules": len(train), "target_schedules": len(target)},
+           "sweep_fp64": [{k_: r[k_] for k_ in ("h", "k", "S", "sec_per_cell_step")} for r in train],
+           "sweep_fp32": [{k_: r[k_] for k_ in ("h", "k", "S", "sec_per_cell_step")} for r in target],
+           "fp32_error_vs_fp64_oracle": {"steps": steps, "max_rel_err": errs}}
+    if args.c5_records:
+        with open(args.c5_records, "w") as fh:
+            json.dump({"train": train, "target": target, "features": tune.FEATURE_NAMES}, fh)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; 10 for the 3D workloads)")
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--repeats", type=int, default=3,
+                    help="timed runs of --steps steps each for the headline and in-core rates (median reported)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="hydro2d")
     ap.add_argument("--n", type=int, default=0, help="cells per axis (default: the workload's size)")
     ap.add_argument("--budget", type=float, default=0, help="device bytes (default: the workload's budget)")
@@ -467,27 +712,41 @@ def main():
     ap.add_argument("--slots", type=int, default=None, help="slot count (default 3; ns3d: 2)")
     ap.add_argument("--tile-rows", type=int, default=None, help="tile height (default: largest that fits; ns3d: 24)")
     ap.add_argument("--chain-steps", type=int, default=3, help="ns3d: time steps per chain")
+    ap.add_argument("--stored-gradients", action="store_true",
+                    help="ns3d: the 27-field chain with a gradient loop and stored gradients (default: the "
+                         "15-field chain whose residual evaluates the gradients itself)")
     ap.add_argument("--no-variants", action="store_true", help="skip the other schedules of the same grid")
     ap.add_argument("--tile-log", default=None,
                     help="write the per-tile stage records of the staged chain to this file (JSON lines, us)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a plain 1 GiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--c5", action="store_true",
+                    help="configuration 5 for --workload hydro2d or ns3d: float32 streaming on the schedule the "
+                         "cost model proposes (trained on the FP64 sweep), regret against the float32 sweep, "
+                         "error against the FP64 oracle")
+    ap.add_argument("--c5-records", default=None, help="write the two sweeps' records (with features) here")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the pipeline runs on a single MI355X "
               "(the multi-GPU sharding is a design note only); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.c5:
+        if args.workload == "hydro3d":
+            print("configuration 5 covers hydro2d and ns3d", file=sys.stderr)
+            sys.exit(2)
+        return c5_main(args)
     if args.steps is None:
         args.steps = 20 if args.workload == "hydro2d" else 10
-    # ns3d runs the schedule the exhaustive sweep of this grid and budget found
-    # fastest (24-plane tiles, chains of 3 steps, 2 slots; the largest tile
-    # measured within 2.5 % of it in the sweep but 6 % slower over 10 steps);
-    # the hydro proxies default to the largest tile and 3 slots
+    # ns3d runs chains of 3 steps on 2 slots: with stored gradients the sweep
+    # of this grid and budget found 24-plane tiles fastest (the largest tile
+    # within 2.5 % in the sweep, 6 % slower over 10 steps); the 15-field chain
+    # takes the largest tile that fits (14 planes at 3-step chains).  The
+    # hydro proxies default to the largest tile and 3 slots.
     ns = args.workload == "ns3d"
     if args.slots is None:
         args.slots = 2 if ns else 0
     if args.tile_rows is None:
-        args.tile_rows = 24 if ns else 0
+        args.tile_rows = 24 if ns and args.stored_gradients else 0
 
     import torch
     from paper_1709_02125_amd import ooc
@@ -508,15 +767,16 @@ def main():
         app.ctx.set_schedule(tile_rows=args.tile_rows, slots=args.slots)
     app.initialise()
     log("out-of-core setup %.1f s" % (time.perf_counter() - t))
-    ooc_r = timed_run(app, args.steps, args.warmup, w.knames, w.dominant)
+    ooc_r = timed_run(app, args.steps, args.warmup, w.knames, w.dominant, repeats=args.repeats)
     tile_stages = tile_stage_summary(app, args.chain_steps if args.workload == "ns3d" else 1, args.tile_log)
     app.close()
     del app
     torch.cuda.empty_cache()
     ooc_rate = w.cells * args.steps / ooc_r["seconds"]
-    log("out-of-core: %.3f s/step, %.3g upd/s, tiles %d x %d rows, host issue %.1f ms (max call %.2f ms)" %
-        (ooc_r["seconds"] / args.steps, ooc_rate, ooc_r["ntiles"], ooc_r["tile_rows"], ooc_r["issue_ms"],
-         ooc_r["max_call_ms"]))
+    log("out-of-core: %.3f s/step (median of %s ms), %.3g upd/s, tiles %d x %d rows, host issue %.1f ms "
+        "(max call %.2f ms: %s, after %d chains)" %
+        (ooc_r["seconds"] / args.steps, ooc_r["runs_ms_per_step"], ooc_rate, ooc_r["ntiles"], ooc_r["tile_rows"],
+         ooc_r["issue_ms"], ooc_r["max_call_ms"], ooc_r["max_call"]["kind"], ooc_r["max_call"]["chains_before"]))
 
     # ---- in core: same grid and kernels, every field resident
     inc_rate, inc_r = None, None
@@ -525,7 +785,7 @@ def main():
         app = w.make(0, ooc.FLAG_INCORE, incore=True)
         app.initialise()
         log("in-core setup %.1f s" % (time.perf_counter() - t))
-        inc_r = timed_run(app, args.steps, args.warmup, w.knames, w.dominant)
+        inc_r = timed_run(app, args.steps, args.warmup, w.knames, w.dominant, repeats=args.repeats)
         app.close()
         del app
         torch.cuda.empty_cache()
@@ -539,7 +799,8 @@ def main():
             t = time.perf_counter()
             app = w.make(w.budget, vflags, **vopts)
             app.initialise()
-            r = timed_run(app, args.steps, args.warmup, w.knames, timing=False)
+            runner = summary_runner(app, *vopts["summary"]) if "summary" in vopts else None
+            r = timed_run(app, args.steps, args.warmup, w.knames, timing=False, run=runner)
             app.close()
             del app
             torch.cuda.empty_cache()
@@ -549,6 +810,9 @@ def main():
                                "h2d_GBs": round(r["bytes_h2d"] / r["seconds"] / 1e9, 2),
                                "d2h_GBs": round(r["bytes_d2h"] / r["seconds"] / 1e9, 2),
                                "tiles": r["ntiles"], "tile_rows": r["tile_rows"]}
+            if "summary" in vopts:
+                variants[vname]["ms_per_step_over_headline"] = round(
+                    (r["seconds"] - ooc_r["seconds"]) / args.steps * 1e3, 3)
             log("variant %s: %.3f s/step, %.3g upd/s (setup+run %.1f s)" %
                 (vname, r["seconds"] / args.steps, rate, time.perf_counter() - t))
     if args.copy_probe:
@@ -581,8 +845,11 @@ def main():
         import oracle
         val, sample = w.cpu_baseline()
         cpu = {"value": val, "unit": "grid-point updates/s", "cores": int(oracle.load().oracle_threads()),
-               "kind": "oracle", "sample": sample, "cpu_model": cpu_model()}
-        log("cpu oracle: %.3g upd/s on %d threads" % (cpu["value"], cpu["cores"]))
+               "kind": "oracle", "sample": sample, "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+               "affinity_cpus": len(os.sched_getaffinity(0)),
+               "one_thread": cpu_one_thread(args.workload, args.n)}
+        log("cpu oracle: %.3g upd/s on %d threads; one thread: %s" % (cpu["value"], cpu["cores"],
+                                                                     cpu["one_thread"]))
 
     ms_step = ooc_r["seconds"] / args.steps * 1e3
     config = {"workload": w.describe(), "cells": w.cells,
@@ -602,6 +869,9 @@ def main():
         "incore_value": inc_rate,
         "pct_of_incore": round(100.0 * ooc_rate / inc_rate, 2) if inc_rate else None,
         "incore_ms_per_step": round(inc_r["seconds"] / args.steps * 1e3, 3) if inc_r else None,
+        "runs_ms_per_step": ooc_r["runs_ms_per_step"],
+        "incore_runs_ms_per_step": inc_r["runs_ms_per_step"] if inc_r else None,
+        "max_runtime_call": ooc_r["max_call"],
         "average_bandwidth_GBs": round(avg_bw, 1),
         "alg_bytes_per_cell_step": round(ooc_r["bytes_hbm_alg"] / (w.cells * args.steps), 1),
         "roofline": roofline,

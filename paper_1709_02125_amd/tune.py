@@ -122,6 +122,38 @@ class CostModel:
             self.net.close()
 
 
+def candidate_features(plan_ctx, queue_steps, cells, row_bytes, budget, candidates):
+    """((h, k, S), features) of every candidate the budget admits, from
+    planning alone (nothing runs)."""
+    out = []
+    for c in candidates:
+        f = plan_features(plan_ctx, queue_steps, cells, row_bytes, budget, *c)
+        if f is not None:
+            out.append((c, f.tolist()))
+    return out
+
+
+def transfer_regret(train_records, target_records, n_hidden=32, seed=1709, epochs=4000, lr=3e-3):
+    """Train the cost model on one sweep's records and let it pick among the
+    schedules of another configuration (their features from planning alone);
+    judge the pick against that configuration's exhaustive sweep.  Returns
+    the pick, its regret against the best measured schedule of the target,
+    and its gain over the target's default schedule."""
+    model = CostModel(n_hidden=n_hidden, seed=seed)
+    try:
+        loss = model.fit(train_records, epochs=epochs, lr=lr)
+        (h, k, S), pred = model.propose([((r["h"], r["k"], r["S"]), r["features"]) for r in target_records])
+    finally:
+        model.close()
+    t = {(r["h"], r["k"], r["S"]): r["sec_per_cell_step"] for r in target_records}
+    best = min(t, key=t.get)
+    d = default_schedule(target_records)
+    return {"loss": loss, "pick": [h, k, S], "predicted_sec_per_cell_step": pred,
+            "measured_sec_per_cell_step": t[(h, k, S)], "best": list(best), "best_sec_per_cell_step": t[best],
+            "regret": t[(h, k, S)] / t[best] - 1.0,
+            "gain_over_default": (d["sec_per_cell_step"] / t[(h, k, S)]) if d else None}
+
+
 def default_schedule(records):
     """The schedule the library uses without guidance: largest tile height
     that fits (h = 0), one step per chain, 3 slots."""
@@ -156,15 +188,19 @@ def holdout_regret(records, train_frac=0.5, seed=1709, n_hidden=32, epochs=4000,
 
 
 # ------------------------------------------------------------ workloads
-def hydro2d_workload(n: int, budget: int, flags: int = 0):
+def hydro2d_workload(n: int, budget: int, flags: int = 0, resident_geometry: bool = False):
     """The same for the 2D hydro proxy at n^2 (one step per chain: the time
-    step is a reduction read by the next step)."""
+    step is a reduction read by the next step); resident_geometry keeps the
+    read-only geometry on the device."""
     from . import hydro2d as h2
     from .inputs import hydro_initial_state
     rho, ene = hydro_initial_state((n, n))
-    app = h2.Hydro2D(n, n, rho, ene, budget=budget, flags=flags | ooc.FLAG_PREFETCH)
+    app = h2.Hydro2D(n, n, rho, ene, budget=budget, flags=flags | ooc.FLAG_PREFETCH,
+                     resident_geometry=resident_geometry)
+    del rho, ene
     app.initialise()
-    planner = h2.Hydro2D(n, n, None, None, budget=budget, flags=flags, plan_only=True)
+    planner = h2.Hydro2D(n, n, None, None, budget=budget, flags=flags, plan_only=True,
+                         resident_geometry=resident_geometry)
     planner.ctx.set_flags(ooc.FLAG_CYCLIC, 0)
 
     def queue_steps(k):
@@ -176,14 +212,15 @@ def hydro2d_workload(n: int, budget: int, flags: int = 0):
     return app, planner.ctx, queue_steps, n * n, row_bytes
 
 
-def ns3d_workload(n: int, budget: int, flags: int = 0):
+def ns3d_workload(n: int, budget: int, flags: int = 0, fused: bool = False):
     """(live app, plan-only context, queue_steps, cells, row_bytes) for the
-    Navier-Stokes proxy at n^3 (Taylor-Green input)."""
+    Navier-Stokes proxy at n^3 (Taylor-Green input); fused: the 15-field
+    chain whose residual evaluates the gradients itself."""
     from . import ns3d as N
     from .inputs import tgv_initial_state
-    app = N.NS3D(n, tgv_initial_state(n), budget=budget, flags=flags | ooc.FLAG_PREFETCH)
+    app = N.NS3D(n, tgv_initial_state(n), budget=budget, flags=flags | ooc.FLAG_PREFETCH, fused=fused)
     app.initialise()
-    planner = N.NS3D(n, None, budget=budget, flags=flags, plan_only=True)
+    planner = N.NS3D(n, None, budget=budget, flags=flags, plan_only=True, fused=fused)
     planner.ctx.set_flags(ooc.FLAG_CYCLIC, 0)
 
     def queue_steps(k):

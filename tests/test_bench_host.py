@@ -19,7 +19,7 @@ def test_more_than_one_gpu_is_refused():
 @pytest.mark.parametrize("name,n", [("hydro2d", 64), ("hydro3d", 16), ("ns3d", 16)])
 def test_workloads_build_on_host(name, n):
     args = types.SimpleNamespace(n=n, budget=0, resident_geometry=False, resident_state=False, no_cyclic=False, chain_steps=3,
-                                 tile_rows=0, slots=0)
+                                 tile_rows=0, slots=0, stored_gradients=False)
     w = bench.WORKLOADS[name](args)
     assert w.cells > 0 and w.footprint > 0 and w.budget > 0
     assert name in w.describe()
@@ -67,6 +67,9 @@ def test_benchmark_configurations_plan_as_measured():
     a = N.NS3D(512, None, budget=N.footprint_bytes(512) // 3, flags=pf, plan_only=True)
     a.ctx.set_schedule(tile_rows=24, chain_steps=3, slots=2)
     cases.append((a, 3, N.footprint_bytes(512) // 3, 22, 24))
+    a = N.NS3D(512, None, budget=N.footprint_bytes(512, True) // 3, flags=pf, plan_only=True, fused=True)
+    a.ctx.set_schedule(tile_rows=0, chain_steps=3, slots=2)
+    cases.append((a, 3, N.footprint_bytes(512, True) // 3, 38, 14))
     for app, steps, budget, tiles, rows in cases:
         app.ctx.set_flags(ooc.FLAG_CYCLIC, 0)
         for _ in range(steps):
