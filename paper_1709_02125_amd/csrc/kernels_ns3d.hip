@@ -303,7 +303,6 @@ __global__ void __launch_bounds__(64 * PH) k_ns_rhs(const KArgs *__restrict__ ap
 // values as in k_ns_grads and k_ns_rhs, so the results are bit-identical to
 // the stored-gradient chain.
 constexpr int kFusedRows = 4;
-constexpr bool kFusedYRing = true;
 // planes of a fused z-segment at least (each re-reads 8 planes of primitives)
 constexpr int kFusedMinSegPlanes = 16;
 
@@ -339,7 +338,7 @@ __device__ __forceinline__ void ns_inputs(const double (&sv)[4][R][C], int sy, i
   v[GTX + 2] = deriv(zc[0][3], zc[1][3], zc[3][3], zc[4][3], inv);
 }
 
-template <bool kFirst, int PH, bool kYRing>
+template <bool kFirst, int PH>
 __global__ void __launch_bounds__(64 * PH) k_ns_rhs_fused(const KArgs *__restrict__ ap) {
   ARGS
   // u, v, w, T at plane c: rows y = j0-4 .. j0+PH+3, columns x = i0-4 .. i0+67
@@ -368,66 +367,52 @@ __global__ void __launch_bounds__(64 * PH) k_ns_rhs_fused(const KArgs *__restric
   const int64_t ycol = (int64_t)hy * a.pitch + i;
   const int64_t ocol = (int64_t)oy * a.pitch + i, hcol = (int64_t)hy * a.pitch + hx;
   const int64_t xcol = (int64_t)j * a.pitch + ox;
-  double za[5][4], zb[5][4];  // own / y-halo column: u, v, w, T at planes c-2 .. c+2
-  double ra[3][2], rb[3][2];  // own / y-halo column: rho, p at planes c .. c+2
-  double fz[5][5];            // own column's z-flux, planes k-2 .. k+2
-  double rxy[3][5];           // own column's x/y residual part, planes k .. k+2
-  auto load_ring = [&](bool ok, int64_t o, double (&z)[5][4], double (&r)[3][2], int zq, int rq) {
-    if (ok) {
-      ns_uvwt(a, o, gm2, z[zq]);
-      if (rq >= 0) {
-        r[rq][0] = gp(a.p[FPR])[o];
-        r[rq][1] = gp(a.p[FPR + 4])[o];
-      }
-    }
+  // own / y-halo column: u, v, w, T at planes c-2 .. c+2 (the newest plane
+  // holds p until its T is formed), rho, p at planes c .. c+2
+  double za[5][4], zb[5][4], ra[3][2], rb[3][2];
+  double fz[5][5];   // own column's z-flux, planes k-2 .. k+2
+  double rxy[3][5];  // own column's x/y residual part, planes k .. k+2
+  // ring columns are loaded unconditionally, from a column clamped into the
+  // primitives' extent where the thread's own one lies outside (its values
+  // are then never used): no branch around the loads, so the wait for the
+  // staging loads before them does not also wait for these
+  const int64_t col_ld = own_ld ? col : (int64_t)(j < yh ? j : yh - 1) * a.pitch + (i < xl ? xl : (i < xh ? i : xh - 1));
+  const int hyc = hy < yl ? yl : (hy < yh ? hy : yh - 1);
+  const int64_t ycol_ld = yh_ld ? ycol : (int64_t)hyc * a.pitch + (i < xl ? xl : (i < xh ? i : xh - 1));
+  auto load_raw = [&](int64_t o, double z[4], double r[2]) {
+    z[0] = gp(a.p[FPR + 1])[o];
+    z[1] = gp(a.p[FPR + 2])[o];
+    z[2] = gp(a.p[FPR + 3])[o];
+    r[0] = gp(a.p[FPR])[o];
+    r[1] = gp(a.p[FPR + 4])[o];
   };
+  auto form_t = [&](double z[4], const double r[2]) { z[3] = (gm2 * r[1]) / r[0]; };
 #pragma unroll
   for (int q = 0; q < 4; q++) {  // planes kb-4 .. kb-1
     const int64_t pq = (int64_t)(kb - 4 + q) * a.plane;
-    load_ring(own_ld, pq + col, za, ra, q, q >= 2 ? q - 2 : -1);
-    if (kYRing) load_ring(yh_ld, pq + ycol, zb, rb, q, q >= 2 ? q - 2 : -1);
+    double r[2], s2[2];
+    load_raw(pq + col_ld, za[q], r);
+    load_raw(pq + ycol_ld, zb[q], s2);
+    form_t(za[q], r);
+    form_t(zb[q], s2);
+    if (q >= 2) {
+      ra[q - 2][0] = r[0];
+      ra[q - 2][1] = r[1];
+      rb[q - 2][0] = s2[0];
+      rb[q - 2][1] = s2[1];
+    }
   }
 #pragma unroll 1
   for (int c = kb - 2; c < ke + 2; c++) {
-    const int64_t pc = (int64_t)c * a.plane, pm = pc + 2 * a.plane;
-    load_ring(own_ld, pm + col, za, ra, 4, 2);
-    double yv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // without the ring: the y-halo column's rho, u, v, w, p at plane c
-    if (kYRing) {
-      load_ring(yh_ld, pm + ycol, zb, rb, 4, 2);
-    } else if (yh_ld) {
-      const int64_t o = pc + ycol;
-      yv[0] = gp(a.p[FPR])[o];
-      yv[1] = gp(a.p[FPR + 1])[o];
-      yv[2] = gp(a.p[FPR + 2])[o];
-      yv[3] = gp(a.p[FPR + 3])[o];
-      yv[4] = gp(a.p[FPR + 4])[o];
-    }
+    const int64_t pc = (int64_t)c * a.plane;
     const bool xy = c >= kb && c < ke;  // the same for the whole block
-    // ---- stage plane c
-    double hv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // the x-halo flux column's rho, u, v, w, p at plane c
-#pragma unroll
-    for (int f = 0; f < 4; f++) {
-      if (own_ld) sv[f][ty + 4][tx + 4] = za[2][f];
-      if (kYRing && yh_ld) sv[f][hn + 2][tx + 4] = zb[2][f];
-    }
-    if (!kYRing && yh_ld) {
-      sv[0][hn + 2][tx + 4] = yv[1];
-      sv[1][hn + 2][tx + 4] = yv[2];
-      sv[2][hn + 2][tx + 4] = yv[3];
-      sv[3][hn + 2][tx + 4] = (gm2 * yv[4]) / yv[0];
-    }
-    if (oy_ld) {
-      double v[4];
-      ns_uvwt(a, pc + ocol, gm2, v);
-#pragma unroll
-      for (int f = 0; f < 4; f++) sv[f][orow][tx + 4] = v[f];
-    }
-    if (hxy_ld) {
-      double v[4];
-      ns_uvwt(a, pc + hcol, gm2, v);
-#pragma unroll
-      for (int f = 0; f < 4; f++) sv[f][hn + 2][hm + 2] = v[f];
-    }
+    // ---- loads of plane c for the staging first, then the leading plane
+    // m = c + 2 of the rings:
+    // the staging waits only for the former, the rings' loads complete
+    // behind it and are used after the barrier
+    double ov[4], hxv[4], hv[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, zc[5][4];
+    if (oy_ld) ns_uvwt(a, pc + ocol, gm2, ov);
+    if (hxy_ld) ns_uvwt(a, pc + hcol, gm2, hxv);
     if (ox_ld) {
       const int64_t o = pc + xcol;
       hv[0] = gp(a.p[FPR])[o];
@@ -435,12 +420,29 @@ __global__ void __launch_bounds__(64 * PH) k_ns_rhs_fused(const KArgs *__restric
       hv[2] = gp(a.p[FPR + 2])[o];
       hv[3] = gp(a.p[FPR + 3])[o];
       hv[4] = gp(a.p[FPR + 4])[o];
+    }
+    load_raw(pc + 2 * a.plane + col_ld, za[4], ra[2]);
+    load_raw(pc + 2 * a.plane + ycol_ld, zb[4], rb[2]);
+    // ---- stage plane c
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+      if (own_ld) sv[f][ty + 4][tx + 4] = za[2][f];
+      if (yh_ld) sv[f][hn + 2][tx + 4] = zb[2][f];
+      if (oy_ld) sv[f][orow][tx + 4] = ov[f];
+      if (hxy_ld) sv[f][hn + 2][hm + 2] = hxv[f];
+    }
+    if (ox_ld) {
       sv[0][ty + 4][om] = hv[1];
       sv[1][ty + 4][om] = hv[2];
       sv[2][ty + 4][om] = hv[3];
       sv[3][ty + 4][om] = (gm2 * hv[4]) / hv[0];
     }
     __syncthreads();
+    // keep the scheduler from forming T (which waits for the rings' loads)
+    // before the barrier
+    __builtin_amdgcn_sched_barrier(0);
+    form_t(za[4], ra[2]);
+    form_t(zb[4], rb[2]);
     // ---- fluxes of plane c
     if (own) {
       double v[17];
@@ -459,40 +461,19 @@ __global__ void __launch_bounds__(64 * PH) k_ns_rhs_fused(const KArgs *__restric
     if (xy) {
       if (yh_flux) {
         double v[17], f[5];
-        if (kYRing) {
-          ns_inputs(sv, hn + 2, tx + 4, zb, rb[0][0], rb[0][1], inv, v);
-        } else {
-          double zc[5][4];
-#pragma unroll
-          for (int q = 0; q < 5; q++) {
-            if (q == 2) {
-              zc[2][0] = yv[1];
-              zc[2][1] = yv[2];
-              zc[2][2] = yv[3];
-              zc[2][3] = 0.0;  // T at the point itself is not used by its derivatives
-            } else {
-              ns_uvwt(a, pc + (int64_t)(q - 2) * a.plane + ycol, gm2, zc[q]);
-            }
-          }
-          ns_inputs(sv, hn + 2, tx + 4, zc, yv[0], yv[4], inv, v);
-        }
+        ns_inputs(sv, hn + 2, tx + 4, zb, rb[0][0], rb[0][1], inv, v);
         ns_flux<1>(v, mu, kappa, f);
 #pragma unroll
         for (int q = 0; q < 5; q++) sfy[q][hn][tx] = f[q];
       }
       if (xh_flux) {
-        double zc[5][4];
 #pragma unroll
-        for (int q = 0; q < 5; q++) {
-          if (q == 2) {
-            zc[2][0] = hv[1];
-            zc[2][1] = hv[2];
-            zc[2][2] = hv[3];
-            zc[2][3] = 0.0;  // T at the point itself is not used by its derivatives
-          } else {
-            ns_uvwt(a, pc + (int64_t)(q - 2) * a.plane + xcol, gm2, zc[q]);
-          }
-        }
+        for (int q = 0; q < 5; q++)
+          if (q != 2) ns_uvwt(a, pc + (int64_t)(q - 2) * a.plane + xcol, gm2, zc[q]);
+        zc[2][0] = hv[1];
+        zc[2][1] = hv[2];
+        zc[2][2] = hv[3];
+        zc[2][3] = 0.0;  // T at the point itself is not used by its derivatives
         double v[17], f[5];
         ns_inputs(sv, ty + 4, om, zc, hv[0], hv[4], inv, v);
         ns_flux<0>(v, mu, kappa, f);
@@ -522,20 +503,18 @@ __global__ void __launch_bounds__(64 * PH) k_ns_rhs_fused(const KArgs *__restric
       }
     }
 #pragma unroll
-    for (int q = 0; q < 4; q++)
+    for (int f = 0; f < 4; f++)
 #pragma unroll
-      for (int f = 0; f < 4; f++) {
+      for (int q = 0; q < 4; q++) {
         za[q][f] = za[q + 1][f];
-        if (kYRing) zb[q][f] = zb[q + 1][f];
+        zb[q][f] = zb[q + 1][f];
       }
 #pragma unroll
     for (int q = 0; q < 2; q++) {
       ra[q][0] = ra[q + 1][0];
       ra[q][1] = ra[q + 1][1];
-      if (kYRing) {
-        rb[q][0] = rb[q + 1][0];
-        rb[q][1] = rb[q + 1][1];
-      }
+      rb[q][0] = rb[q + 1][0];
+      rb[q][1] = rb[q + 1][1];
     }
 #pragma unroll
     for (int q = 0; q < 5; q++) {
@@ -573,10 +552,10 @@ void l_rhs(const KArgs &a, const KArgs *d, int nd, void *s) {
   launch_zmarch<kRhsRows>(k_ns_rhs<false, kRhsRows>, a, d, nd, s);
 }
 void l_rhs_fused_first(const KArgs &a, const KArgs *d, int nd, void *s) {
-  launch_zmarch_seg<kFusedRows, kFusedMinSegPlanes>(k_ns_rhs_fused<true, kFusedRows, kFusedYRing>, a, d, nd, s);
+  launch_zmarch_seg<kFusedRows, kFusedMinSegPlanes>(k_ns_rhs_fused<true, kFusedRows>, a, d, nd, s);
 }
 void l_rhs_fused(const KArgs &a, const KArgs *d, int nd, void *s) {
-  launch_zmarch_seg<kFusedRows, kFusedMinSegPlanes>(k_ns_rhs_fused<false, kFusedRows, kFusedYRing>, a, d, nd, s);
+  launch_zmarch_seg<kFusedRows, kFusedMinSegPlanes>(k_ns_rhs_fused<false, kFusedRows>, a, d, nd, s);
 }
 #undef L
 
