@@ -201,11 +201,15 @@ class NS3DWork(Workload):
     def variants(self):
         from paper_1709_02125_amd import ooc
         pf = ooc.FLAG_PREFETCH
-        return [*ablations(pf),
-                ("default_schedule_1_step_chains", pf, {"chain_steps": 1, "tile_rows": 0, "slots": 3}),
-                ("chains_of_2_steps_largest_tiles", pf, {"chain_steps": 2, "tile_rows": 0, "slots": 3}),
-                ("fp32_stream_swept_schedule", pf | ooc.FLAG_FP32_STREAM,
-                 {"chain_steps": 2, "tile_rows": 32, "slots": 2})]
+        ring = 0 if self.args.slots_mode else ooc.FLAG_RING
+        # the paper's slots with edge copies, with Prefetch and Cyclic, then
+        # its two ablations; the ring-slab headline's other chain lengths;
+        # float32 streaming of the same schedule
+        return [("slots_edge_copies", pf, {}), ("slots_no_prefetch_cyclic", 0, {}),
+                ("slots_no_prefetch_no_cyclic", 0, {"cyclic": False}),
+                ("chains_of_1_step", pf | ring, {"chain_steps": 1}),
+                ("chains_of_2_steps", pf | ring, {"chain_steps": 2}),
+                ("fp32_stream", pf | ring | ooc.FLAG_FP32_STREAM, {})]
 
     def describe(self):
         form = ("15 fields (gradients evaluated in the residual kernel), 42 loops per step" if self.fused else
@@ -552,19 +556,22 @@ def c5_main(args):
         from paper_1709_02125_amd import ns3d as N
         from paper_1709_02125_amd.inputs import tgv_initial_state
         n = args.n or 512
-        budget = int(args.budget) if args.budget else N.footprint_bytes(n) // 3
-        cands = tune.grid([8, 16, 24, 32, 48, 0], [1, 2, 3], [2, 3, 4])
-        workload = lambda fl: tune.ns3d_workload(n, budget, fl)
+        fused = not args.stored_gradients
+        ring = 0 if args.slots_mode else ooc.FLAG_RING
+        budget = int(args.budget) if args.budget else N.footprint_bytes(n, fused) // 3
+        cands = tune.grid([8, 16, 24, 32, 48, 0], [1, 2, 3, 4], [2, 3, 4])
+        workload = lambda fl: tune.ns3d_workload(n, budget, fl | ring, fused=fused)
         cells = n ** 3
         names = N.Q
 
         def fresh(h, k, S):
-            app = N.NS3D(n, tgv_initial_state(n), budget=budget, flags=ooc.FLAG_PREFETCH | f32)
+            app = N.NS3D(n, tgv_initial_state(n), budget=budget, flags=ooc.FLAG_PREFETCH | f32 | ring, fused=fused)
             app.ctx.set_schedule(tile_rows=h, chain_steps=k, slots=S)
             return app
 
         def incore():
-            return N.NS3D(n, tgv_initial_state(n), budget=N.device_footprint_bytes(n), flags=ooc.FLAG_INCORE)
+            return N.NS3D(n, tgv_initial_state(n), budget=N.device_footprint_bytes(n, fused), flags=ooc.FLAG_INCORE,
+                          fused=fused)
 
         def oracle_state():
             import oracle.ns3d as on
@@ -578,8 +585,9 @@ def c5_main(args):
             return out
 
         got_state = lambda app: {x: app.interior(x) for x in names}
-        form = ("ns3d proxy %d^3 (Taylor-Green, Mach 0.1), conserved fields stored and streamed as float32, "
-                "compute in FP64, device budget %.3g B (1/3 of the FP64 fields)" % (n, budget))
+        form = ("ns3d proxy %d^3 (Taylor-Green, Mach 0.1), %d fields, conserved fields stored and streamed as "
+                "float32, compute in FP64, %s, device budget %.3g B (1/3 of the FP64 fields)" %
+                (n, 15 if fused else 27, "ring slabs" if ring else "slots with edge copies", budget))
     else:
         from paper_1709_02125_amd import hydro2d as h2
         from paper_1709_02125_amd.inputs import hydro_initial_state
@@ -712,6 +720,10 @@ def main():
     ap.add_argument("--slots", type=int, default=None, help="slot count (default 3; ns3d: 2)")
     ap.add_argument("--tile-rows", type=int, default=None, help="tile height (default: largest that fits; ns3d: 24)")
     ap.add_argument("--chain-steps", type=int, default=3, help="ns3d: time steps per chain")
+    ap.add_argument("--slots-mode", action="store_true",
+                    help="ns3d: the paper's per-tile slots with edge copies instead of ring slabs (the default "
+                         "for ns3d)")
+    ap.add_argument("--ring", action="store_true", help="hydro proxies: ring slabs instead of slots")
     ap.add_argument("--stored-gradients", action="store_true",
                     help="ns3d: the 27-field chain with a gradient loop and stored gradients (default: the "
                          "15-field chain whose residual evaluates the gradients itself)")
@@ -755,6 +767,8 @@ def main():
 
     # ---- out of core: budget capped, tiles streamed through HBM
     flags = 0 if args.no_prefetch else ooc.FLAG_PREFETCH
+    if args.ring or (ns and not args.slots_mode):
+        flags |= ooc.FLAG_RING
     if args.fp32:
         flags |= ooc.FLAG_FP32_STREAM
     if args.kernel_copy:
@@ -798,12 +812,20 @@ def main():
         for vname, vflags, vopts in w.variants():
             t = time.perf_counter()
             app = w.make(w.budget, vflags, **vopts)
-            app.initialise()
-            runner = summary_runner(app, *vopts["summary"]) if "summary" in vopts else None
-            r = timed_run(app, args.steps, args.warmup, w.knames, timing=False, run=runner)
-            app.close()
-            del app
-            torch.cuda.empty_cache()
+            try:
+                app.initialise()
+                runner = summary_runner(app, *vopts["summary"]) if "summary" in vopts else None
+                r = timed_run(app, args.steps, args.warmup, w.knames, timing=False, run=runner)
+            except ooc.OocError as e:
+                if e.code != ooc.E_BUDGET:
+                    raise
+                variants[vname] = {"infeasible": str(e)}  # the schedule does not fit this form's budget
+                log("variant %s: %s" % (vname, e))
+                continue
+            finally:
+                app.close()
+                del app
+                torch.cuda.empty_cache()
             rate = w.cells * args.steps / r["seconds"]
             variants[vname] = {"value": rate, "ms_per_step": round(r["seconds"] / args.steps * 1e3, 3),
                                "pct_of_incore": round(100.0 * rate / inc_rate, 2) if inc_rate else None,

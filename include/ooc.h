@@ -79,10 +79,20 @@ enum {
   OOC_FLAG_DEBUG_POISON = 64, /* fill every slot with NaN before use (finds missing uploads) */
   OOC_FLAG_DEBUG_SYNC = 128,  /* serialise the three streams (separates races from plan bugs) */
   OOC_FLAG_PLAN_ONLY = 256,   /* no host or device storage: for ooc_debug_plan only (schedule search) */
-  OOC_FLAG_KERNEL_COPY = 512  /* uploads too by a copy kernel on the pinned arrays' device mapping
+  OOC_FLAG_KERNEL_COPY = 512, /* uploads too by a copy kernel on the pinned arrays' device mapping
                                  (one launch per tile; FP32 converted in flight) instead of runtime
                                  memcpy calls.  Downloads always go by copy kernel when the host
                                  arrays are device-mapped (pinned by ooc_bind_device) */
+  OOC_FLAG_RING = 1024        /* ring slabs instead of slots: each streamed field lives in one ring
+                                 of device memory mapped twice at consecutive virtual addresses
+                                 (HIP virtual memory API), so the rows two tiles share stay in
+                                 place -- no edge copy -- and a ring only holds the rows of the S
+                                 tiles in flight.  The rings are allocated by the library within
+                                 the budget (the arena given to ooc_bind_device then only needs
+                                 the reductions and resident fields, or may be NULL with 0 bytes:
+                                 the library allocates that too).  A chain's first tile waits for
+                                 the previous chain's last download.  Fixed at creation;
+                                 OOC_E_ARG at the first flush if the device lacks the API. */
 };
 
 /* per-field flags for ooc_decl_field */
@@ -133,7 +143,8 @@ int ooc_create(ooc_ctx **out, int ndim, const int64_t dims[3], int halo,
  * and its three streams: host-to-device, compute, device-to-host (Section 4:
  * streams 1, 0 and 2 of Algorithm 1).  Streams are hipStream_t values; the
  * arena and the streams stay owned by the caller and must outlive the
- * context.  If never called, the first flush allocates its own. */
+ * context.  If never called, the first flush allocates its own.  With
+ * OOC_FLAG_RING the arena may be NULL with arena_bytes 0 (see the flag). */
 int ooc_bind_device(ooc_ctx *ctx, void *arena, size_t arena_bytes,
                     void *stream_h2d, void *stream_compute, void *stream_d2h);
 
@@ -282,6 +293,8 @@ typedef struct {
   const int64_t *down;        /* [ndown][4]: field, tile, row_lo, row_hi (downloaded after tile) */
   const int64_t *edge;        /* [nedge][4]: field, tile, row_lo, row_hi (copied tile-1 -> tile) */
   const int32_t *temporary;   /* [nfields]: 1 if no element is read before written in the chain */
+  int32_t ring;               /* 1 with OOC_FLAG_RING: then no edge copies are made, and ... */
+  const int64_t *ring_rows;   /* [nfields]: ... rows of each field's ring (0 if not streamed) */
 } ooc_plan_info;
 
 int ooc_debug_plan(ooc_ctx *ctx, ooc_plan_info *out);

@@ -150,6 +150,13 @@ struct Plan {
   std::vector<int64_t> resA, resB;  // [nfields][T] stored-row residency
   std::vector<int64_t> cap;         // [nfields] slab rows
   std::vector<uint64_t> slab_off;   // [nfields] byte offset of the slab inside a slot
+  // ring slabs (PlanInput::ring): per field one ring of ring_rows rows in
+  // ring_bytes (a multiple of the ring granule), then S staging areas of
+  // stage_bytes; slot_bytes is then the whole: rings plus staging
+  bool ring = false;
+  std::vector<int64_t> ring_rows;   // [nfields]
+  std::vector<uint64_t> ring_bytes; // [nfields]
+  uint64_t stage_bytes = 0;
   uint64_t slot_bytes = 0;
   uint64_t stage_up_off = 0, stage_down_off = 0;  // float32 staging inside a slot
   std::vector<Run> up, down, edge;
@@ -169,8 +176,16 @@ struct PlanInput {
   bool cyclic = false;
   int S = 3;
   int64_t forced_h = 0;
-  uint64_t slot_capacity = 0;  // bytes available to one slot
+  uint64_t slot_capacity = 0;  // bytes available to one slot (ring: to all rings and staging)
+  bool ring = false;           // ring slabs instead of slots
+  uint64_t ring_granule = 1u << 16;  // rings are sized in multiples of this
 };
+
+// Ring slabs: every streamed field lives in one ring of device memory mapped
+// twice at consecutive virtual addresses, so a tile's rows are contiguous
+// wherever they wrap; rings are sized in whole units of at least this many
+// bytes (and of the device's mapping granularity).
+constexpr uint64_t kRingGranule = 1u << 16;
 
 inline bool writes_access(int a) { return a == OOC_WRITE || a == OOC_RW || a == OOC_INC; }
 inline bool reads_access(int a) { return a == OOC_READ || a == OOC_RW || a == OOC_INC; }

@@ -141,6 +141,9 @@ int make_plan(const PlanInput &in, Plan &P, std::string &err) {
     P.resB.assign(nf, 0);
     P.cap.assign(nf, 0);
     P.slab_off.assign(nf, 0);
+    P.ring = in.ring;
+    P.ring_rows.assign(nf, 0);
+    P.ring_bytes.assign(nf, 0);
     return OOC_OK;
   }
 
@@ -335,9 +338,38 @@ int make_plan(const PlanInput &in, Plan &P, std::string &err) {
         sup = std::max(sup, u);
         sdown = std::max(sdown, d);
       }
-    Q.stage_up_off = bytes;
-    Q.stage_down_off = bytes + sup;
-    Q.slot_bytes = bytes + sup + sdown;
+    if (!in.ring) {
+      Q.stage_up_off = bytes;
+      Q.stage_down_off = bytes + sup;
+      Q.slot_bytes = bytes + sup + sdown;
+      return Q.slot_bytes;
+    }
+    // ring slabs: a field's ring holds the rows of S consecutive tiles (the
+    // tiles that can be in flight together), from the first held row of the
+    // oldest to the last held row of the newest
+    Q.ring = true;
+    Q.ring_rows.assign(nf, 0);
+    Q.ring_bytes.assign(nf, 0);
+    uint64_t rbytes = 0;
+    for (int f : P.slot_fields) {
+      int64_t need = 0;
+      for (int t = 0; t < T; t++) {
+        if (Q.resB[(size_t)f * T + t] <= Q.resA[(size_t)f * T + t]) continue;
+        const int64_t lo = Q.resA[(size_t)f * T + t];
+        int64_t hi = Q.resB[(size_t)f * T + t];
+        for (int u = t + 1; u < std::min(T, t + in.S); u++)
+          if (Q.resB[(size_t)f * T + u] > Q.resA[(size_t)f * T + u]) hi = std::max(hi, Q.resB[(size_t)f * T + u]);
+        need = std::max(need, hi - lo);
+      }
+      Q.ring_rows[f] = need;
+      const uint64_t b = (uint64_t)need * F[f].row_bytes_dev();
+      Q.ring_bytes[f] = (b + in.ring_granule - 1) / in.ring_granule * in.ring_granule;
+      rbytes += Q.ring_bytes[f];
+    }
+    Q.stage_up_off = 0;
+    Q.stage_down_off = sup;
+    Q.stage_bytes = (sup + sdown + 255) / 256 * 256;
+    Q.slot_bytes = rbytes + (uint64_t)in.S * Q.stage_bytes;
     return Q.slot_bytes;
   };
 
@@ -348,14 +380,16 @@ int make_plan(const PlanInput &in, Plan &P, std::string &err) {
     h = std::min(in.forced_h, span);
     if (tile_plan(h, Q) > in.slot_capacity) {
       err = "tile height " + std::to_string(h) + " needs " + std::to_string(Q.slot_bytes) +
-            " bytes per slot, more than the " + std::to_string(in.slot_capacity) + " available";
+            (in.ring ? " bytes of rings" : " bytes per slot") + ", more than the " +
+            std::to_string(in.slot_capacity) + " available";
       return OOC_E_BUDGET;
     }
   } else if (tile_plan(span, Q) <= in.slot_capacity) {
     h = span;
   } else {
     if (tile_plan(1, Q) > in.slot_capacity) {
-      err = "even one-row tiles need " + std::to_string(Q.slot_bytes) + " bytes per slot, more than the " +
+      err = "even one-row tiles need " + std::to_string(Q.slot_bytes) +
+            (in.ring ? " bytes of rings" : " bytes per slot") + ", more than the " +
             std::to_string(in.slot_capacity) + " available";
       return OOC_E_BUDGET;
     }
@@ -377,6 +411,10 @@ int make_plan(const PlanInput &in, Plan &P, std::string &err) {
   P.slot_bytes = Q.slot_bytes;
   P.stage_up_off = Q.stage_up_off;
   P.stage_down_off = Q.stage_down_off;
+  P.ring = Q.ring;
+  P.ring_rows.swap(Q.ring_rows);
+  P.ring_bytes.swap(Q.ring_bytes);
+  P.stage_bytes = Q.stage_bytes;
   P.slab_off.assign(nf, 0);
   {
     uint64_t off = 0;

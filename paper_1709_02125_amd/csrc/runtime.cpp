@@ -96,13 +96,28 @@ struct ooc_ctx {
   hipStream_t s_up = nullptr, s_comp = nullptr, s_down = nullptr;
   char *slot_base = nullptr;
   uint64_t slot_stride = 0;
+  // ring slabs (OOC_FLAG_RING): per field one ring of device memory mapped
+  // twice at consecutive virtual addresses, and the staging areas of the S
+  // tiles in flight
+  struct Ring {
+    char *va = nullptr;
+    uint64_t bytes = 0;
+    hipMemGenericAllocationHandle_t h{};
+    bool created = false;
+    int maps = 0;
+  };
+  std::vector<Ring> rings;
+  char *stage_base = nullptr;
+  uint64_t stage_stride = 0, stage_alloc = 0;
+  uint64_t ring_granule = kRingGranule;
+  int device = 0;
   // tiles and events
   int64_t gtile = 0, gbase = 0, gsynced = -1;
   int64_t prev_last_tile = -1;  // last tile of the previously issued chain
   std::vector<hipEvent_t> ev_up, ev_comp, ev_down;  // indexed by g - gbase
   std::map<std::string, Plan> plans;
   Plan dbg;
-  std::vector<int64_t> dbg_loop_rows, dbg_res, dbg_up, dbg_down, dbg_edge;
+  std::vector<int64_t> dbg_loop_rows, dbg_res, dbg_up, dbg_down, dbg_edge, dbg_ring;
   ooc_stats st{};
   bool timing = false;
   int timing_kid = -1;  // with timing: only this kernel id (-1: every loop)
@@ -392,19 +407,117 @@ uint64_t reserved_bytes(const ooc_ctx *c) {
   return used;
 }
 
+// Ring slabs: device bytes available to the rings and the staging areas.
+uint64_t ring_capacity(const ooc_ctx *c) {
+  const uint64_t used = reserved_bytes(c);
+  return c->budget > used ? c->budget - used : 0;
+}
+
+void free_rings(ooc_ctx *c) {
+  for (ooc_ctx::Ring &r : c->rings) {
+    if (r.maps > 1) (void)hipMemUnmap(r.va + r.bytes, r.bytes);
+    if (r.maps > 0) (void)hipMemUnmap(r.va, r.bytes);
+    if (r.va) (void)hipMemAddressFree(r.va, 2 * r.bytes);
+    if (r.created) (void)hipMemRelease(r.h);
+    r = ooc_ctx::Ring();
+  }
+  if (c->stage_base) (void)hipFree(c->stage_base);
+  c->stage_base = nullptr;
+  c->stage_alloc = 0;
+}
+
+// Give every field of the plan a ring at least as large as the plan needs.
+// When one is short, all rings are released, once the device is done with
+// them, and allocated afresh at the plan's sizes (which fit the budget):
+// data does not live in the rings between chains.  Launch arguments cached
+// for earlier chains point into the old rings and are dropped.
+void ensure_rings(ooc_ctx *c, const Plan &P) {
+  bool ok = c->stage_alloc >= (uint64_t)c->slots * P.stage_bytes;
+  for (int f : P.slot_fields) ok = ok && c->rings[f].bytes >= P.ring_bytes[f];
+  if (ok) return;
+  for (hipStream_t st : {c->s_up, c->s_comp, c->s_down}) HIPCHK(hipStreamSynchronize(st));
+  drop_graphs(c);
+  c->argtab_cache.clear();
+  c->argtab_used = 0;
+  free_rings(c);
+  hipMemAllocationProp prop = {};
+  prop.type = hipMemAllocationTypePinned;
+  prop.location.type = hipMemLocationTypeDevice;
+  prop.location.id = c->device;
+  hipMemAccessDesc acc = {};
+  acc.location = prop.location;
+  acc.flags = hipMemAccessFlagsProtReadWrite;
+  for (int f : P.slot_fields) {
+    ooc_ctx::Ring &r = c->rings[f];
+    if (!P.ring_bytes[f]) continue;
+    r.bytes = P.ring_bytes[f];
+    HIPCHK(hipMemCreate(&r.h, r.bytes, &prop, 0));
+    r.created = true;
+    void *va = nullptr;
+    HIPCHK(hipMemAddressReserve(&va, 2 * r.bytes, c->ring_granule, nullptr, 0));
+    r.va = (char *)va;
+    HIPCHK(hipMemMap(r.va, r.bytes, 0, r.h, 0));
+    r.maps = 1;
+    HIPCHK(hipMemMap(r.va + r.bytes, r.bytes, 0, r.h, 0));
+    r.maps = 2;
+    HIPCHK(hipMemSetAccess(r.va, 2 * r.bytes, &acc, 1));
+  }
+  c->stage_stride = P.stage_bytes;
+  if (P.stage_bytes) {
+    HIPCHK(hipMalloc((void **)&c->stage_base, (uint64_t)c->slots * P.stage_bytes));
+    c->stage_alloc = (uint64_t)c->slots * P.stage_bytes;
+  }
+}
+
+// Device address of stored row `row` of field f in tile t: in the tile's
+// slot, or in the field's ring (row r at byte (r * row bytes) mod ring bytes
+// of the first mapping, the window of the tile contiguous from there on).
+char *row_ptr(ooc_ctx *c, const Plan &P, int f, int t, char *slot, int64_t row) {
+  const Field &fd = c->fields[f];
+  const int64_t A = P.resA[(size_t)f * P.T + t];
+  if (P.ring) {
+    const ooc_ctx::Ring &r = c->rings[f];
+    if (!r.bytes) return r.va;  // not held in this chain
+    return r.va + (uint64_t)A * fd.row_bytes_dev() % r.bytes + (row - A) * fd.row_bytes_dev();
+  }
+  return slot + P.slab_off[f] + (row - A) * fd.row_bytes_dev();
+}
+
 void setup_device(ooc_ctx *c) {
   if (c->ready) return;
   if (!c->bound) {
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n == 0) throw DeviceError("no HIP device available");
-    HIPCHK(hipMalloc((void **)&c->arena, c->budget));
-    c->arena_bytes = c->budget;
-    c->own_arena = true;
+    if (!(c->flags & OOC_FLAG_RING)) {  // ring slabs allocate their own memory below
+      HIPCHK(hipMalloc((void **)&c->arena, c->budget));
+      c->arena_bytes = c->budget;
+      c->own_arena = true;
+    }
     HIPCHK(hipStreamCreateWithFlags(&c->s_up, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&c->s_comp, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&c->s_down, hipStreamNonBlocking));
     c->own_streams = true;
     c->bound = true;
+  }
+  HIPCHK(hipGetDevice(&c->device));
+  if (c->flags & OOC_FLAG_RING) {
+    int vmm = 0;
+    HIPCHK(hipDeviceGetAttribute(&vmm, hipDeviceAttributeVirtualMemoryManagementSupported, c->device));
+    if (!vmm) throw ArgError(OOC_E_ARG, "ring slabs need the HIP virtual memory API, which this device lacks");
+    hipMemAllocationProp prop = {};
+    prop.type = hipMemAllocationTypePinned;
+    prop.location.type = hipMemLocationTypeDevice;
+    prop.location.id = c->device;
+    size_t g = 0;
+    HIPCHK(hipMemGetAllocationGranularity(&g, &prop, hipMemAllocationGranularityMinimum));
+    if (g > 0) c->ring_granule = (kRingGranule + g - 1) / g * g;
+    c->rings.assign(c->fields.size(), ooc_ctx::Ring());
+    if (!c->arena) {  // bound without an arena: reductions and resident fields get their own
+      const uint64_t need = std::max<uint64_t>(reserved_bytes(c), 256);
+      HIPCHK(hipMalloc((void **)&c->arena, need));
+      c->arena_bytes = need;
+      c->own_arena = true;
+    }
   }
   // pin host arrays declared before the device was bound
   for (size_t k = 0; k < c->fields.size(); k++) {
@@ -443,7 +556,7 @@ void setup_device(ooc_ctx *c) {
     throw ArgError(OOC_E_BUDGET, "resident fields and reductions need " + std::to_string(off) +
                                      " bytes, more than the budget of " + std::to_string(budget));
   c->slot_base = c->arena + off;
-  c->slot_stride = (budget - off) / c->slots / 256 * 256;
+  c->slot_stride = (c->flags & OOC_FLAG_RING) ? ring_capacity(c) : (budget - off) / c->slots / 256 * 256;
   // initial device state: reductions, resident fields
   for (Reduction &r : c->reds) {
     double v = r.host_set ? r.host_value : 0.0;
@@ -499,8 +612,12 @@ const Plan &get_plan(ooc_ctx *c, const LoopRec *L, int n) {
   in.cyclic = (c->flags & OOC_FLAG_CYCLIC) != 0;
   in.S = c->slots;
   in.forced_h = c->tile_rows;
+  in.ring = (c->flags & OOC_FLAG_RING) != 0;
+  in.ring_granule = c->ring_granule;
   in.slot_capacity = c->ready ? c->slot_stride : UINT64_MAX;
-  if (!c->ready) {
+  if (in.ring) {
+    in.slot_capacity = ring_capacity(c);
+  } else if (!c->ready) {
     // planning before the device exists (inspection): use the budget minus
     // what resident fields and reductions will take
     const uint64_t used = reserved_bytes(c);
@@ -522,8 +639,8 @@ double *field_ptr(ooc_ctx *c, int f, const Plan &P, int t, char *slot) {
     base = (char *)fd.dev_res;
     A = 0;
   } else {
-    base = slot + P.slab_off[f];
     A = P.resA[(size_t)f * P.T + t];
+    base = row_ptr(c, P, f, t, slot, A);
   }
   int64_t shift = -A * fd.row_elems + kXOrigin - fd.lo[1] * c->pitch;
   if (c->ndim == 3) shift -= fd.lo[2] * c->plane;
@@ -623,7 +740,8 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
   auto issue0 = std::chrono::steady_clock::now();
   const Plan &P = get_plan(c, L, n);
   if ((uint64_t)P.slot_bytes > c->slot_stride)
-    throw ArgError(OOC_E_BUDGET, "plan does not fit its slot");
+    throw ArgError(OOC_E_BUDGET, P.ring ? "plan does not fit the ring capacity" : "plan does not fit its slot");
+  if (P.ring) ensure_rings(c, P);
   const int T = P.T, S = c->slots;
   const bool dbg_sync = (c->flags & OOC_FLAG_DEBUG_SYNC) != 0;
   // reductions written in this chain: start from the operator's identity
@@ -646,8 +764,12 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
   };
   std::vector<Launch> launches;
   std::vector<KArgs> hostargs;
+  // a tile's slot (ring slabs: its staging area)
+  auto slot_of = [&](int64_t g) {
+    return P.ring ? c->stage_base + (uint64_t)(g % S) * c->stage_stride : c->slot_base + (uint64_t)(g % S) * c->slot_stride;
+  };
   for (int t = 0; t < T; t++) {
-    char *slot = c->slot_base + (uint64_t)((g0 + t) % S) * c->slot_stride;
+    char *slot = slot_of(g0 + t);
     for (int i = 0; i < n; i++)
       if (P.s(i, t) < P.en(i, t) && loop_nonempty(L[i], c->ndim)) {
         uint64_t b = 0;
@@ -710,7 +832,8 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
   // stores); otherwise 16-byte stores move the rows faster (hydro2d 15360^2
   // FP32 with resident geometry: 102 against 122 ms).
   const int f32_down_mode = P.alg_bytes > 60 * (chain_up + chain_down) ? 2 : 3;
-  for (const Run &r : P.edge) c->st.bytes_edge += (uint64_t)(r.hi - r.lo) * c->fields[r.f].row_elems * 8;
+  if (!P.ring)  // in rings the rows two tiles share stay in place
+    for (const Run &r : P.edge) c->st.bytes_edge += (uint64_t)(r.hi - r.lo) * c->fields[r.f].row_elems * 8;
   const uint64_t launches0 = c->st.launches;
 
   auto body = [&]() {
@@ -722,13 +845,26 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
   size_t li = 0;
   for (int t = 0; t < T; t++) {
     const int64_t g = c->gtile++;
-    char *slot = c->slot_base + (uint64_t)(g % S) * c->slot_stride;
+    char *slot = slot_of(g);
     // ---- upload: the rows of the tile's footprint that the previous tile
     // does not hand over (Algorithm 1's upload stage)
     wait_tile(c, c->s_up, c->ev_down, g - S);  // slot free again
     if (t == 0 && prev_last_tile >= 0 && !(c->flags & OOC_FLAG_PREFETCH))
       wait_tile(c, c->s_up, c->ev_comp, prev_last_tile);  // no early start of the next chain
-    if (c->flags & OOC_FLAG_DEBUG_POISON) {
+    // ring slabs: the first tile's rows may map onto ring positions of the
+    // previous chain's last tiles, so it starts once they are downloaded
+    if (P.ring && t == 0 && prev_last_tile >= 0) wait_tile(c, c->s_up, c->ev_down, prev_last_tile);
+    if (P.ring && (c->flags & OOC_FLAG_DEBUG_POISON)) {
+      // poison the rows the tile brings into its rings (before the uploads)
+      for (int f : P.slot_fields) {
+        const int64_t A = P.resA[(size_t)f * T + t], B = P.resB[(size_t)f * T + t];
+        if (B <= A) continue;
+        const bool prev = t > 0 && P.resB[(size_t)f * T + t - 1] > P.resA[(size_t)f * T + t - 1];
+        const int64_t new0 = prev ? std::max(A, P.resB[(size_t)f * T + t - 1]) : A;
+        if (new0 < B)
+          launch_fill((double *)row_ptr(c, P, f, t, slot, new0), (B - new0) * c->fields[f].row_elems, NAN, c->s_up);
+      }
+    } else if (c->flags & OOC_FLAG_DEBUG_POISON) {
       // a slot with an incoming edge was poisoned on the compute stream just
       // before that edge copy (see below); order this tile's uploads after it
       if (t == 0) launch_fill((double *)slot, P.slot_bytes / 8, NAN, c->s_up);
@@ -750,8 +886,7 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
         wait_tile(c, c->s_up, c->ev_down, dep);
         waited = dep;
       }
-      const int64_t A = P.resA[(size_t)r->f * T + t];
-      char *dst = slot + P.slab_off[r->f] + (r->lo - A) * f.row_bytes_dev();
+      char *dst = row_ptr(c, P, r->f, t, slot, r->lo);
       const size_t nb = (size_t)(r->hi - r->lo) * f.row_bytes_host();
       const char *src = (const char *)f.host + r->lo * f.row_bytes_host();
       if (kcopy) {
@@ -818,7 +953,7 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
     if (c->tile_timing && c->capture_g0 < 0) tile_mark(c, 3, c->s_comp);
     // ---- hand the right edge to the next tile's slot (on the compute stream)
     const bool poison = (c->flags & OOC_FLAG_DEBUG_POISON) != 0;
-    if (t + 1 < T && (poison || !edge[t + 1].empty())) {
+    if (!P.ring && t + 1 < T && (poison || !edge[t + 1].empty())) {
       wait_tile(c, c->s_comp, c->ev_down, g + 1 - S);  // next slot free again
       char *nslot = c->slot_base + (uint64_t)((g + 1) % S) * c->slot_stride;
       if (poison) launch_fill((double *)nslot, P.slot_bytes / 8, NAN, c->s_comp);
@@ -852,8 +987,7 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
     std::vector<XferSeg> xdown;
     for (const Run *r : down[t]) {
       Field &f = c->fields[r->f];
-      const int64_t A = P.resA[(size_t)r->f * T + t];
-      const char *src = slot + P.slab_off[r->f] + (r->lo - A) * f.row_bytes_dev();
+      const char *src = row_ptr(c, P, r->f, t, slot, r->lo);
       const size_t nb = (size_t)(r->hi - r->lo) * f.row_bytes_host();
       char *dst = (char *)f.host + r->lo * f.row_bytes_host();
       // Downloads go by copy kernel into the device-mapped host rows.  DMA
@@ -1195,7 +1329,8 @@ int ooc_create(ooc_ctx **out, int ndim, const int64_t dims[3], int halo, size_t 
 int ooc_bind_device(ooc_ctx *c, void *arena, size_t arena_bytes, void *s_up, void *s_comp, void *s_down) {
   GUARD(c);
   if (c->ready || c->bound) return fail(c, OOC_E_STATE, "device already bound");
-  if (!arena || (uintptr_t)arena % 256 || !s_up || !s_comp || !s_down)
+  const bool no_arena = !arena && arena_bytes == 0 && (c->flags & OOC_FLAG_RING);
+  if ((!arena && !no_arena) || (uintptr_t)arena % 256 || !s_up || !s_comp || !s_down)
     return fail(c, OOC_E_ARG, "arena must be 256-byte aligned and all three streams given");
   if (s_up == s_comp || s_up == s_down || s_comp == s_down)
     return fail(c, OOC_E_ARG, "the three streams must be distinct");
@@ -1359,8 +1494,8 @@ int ooc_set_field(ooc_ctx *c, ooc_field h, const double *src, size_t bytes) {
 
 int ooc_set_flags(ooc_ctx *c, uint32_t set, uint32_t clear) {
   GUARD(c);
-  const uint32_t fixed = OOC_FLAG_FP32_STREAM | OOC_FLAG_INCORE | OOC_FLAG_PLAN_ONLY;
-  if ((set | clear) & fixed) return fail(c, OOC_E_STATE, "FP32_STREAM and INCORE are fixed at creation");
+  const uint32_t fixed = OOC_FLAG_FP32_STREAM | OOC_FLAG_INCORE | OOC_FLAG_PLAN_ONLY | OOC_FLAG_RING;
+  if ((set | clear) & fixed) return fail(c, OOC_E_STATE, "FP32_STREAM, INCORE and RING are fixed at creation");
   // Chain replay from a stream-captured graph is switched off: its first
   // capture ended the process with a host segmentation fault whose cause has
   // not been found in this library's code.
@@ -1380,7 +1515,7 @@ int ooc_set_schedule(ooc_ctx *c, int64_t tile_rows, int chain_steps, int slots) 
     int rc = flush(c);
     if (rc) return rc;
     const int s = slots ? slots : 3;
-    if (c->ready && s != c->slots) {
+    if (c->ready && s != c->slots && !(c->flags & OOC_FLAG_RING)) {
       const uint64_t base = (uint64_t)(c->slot_base - c->arena);
       const size_t budget = std::min(c->budget, c->arena_bytes);
       c->slot_stride = (budget - base) / s / 256 * 256;
@@ -1470,6 +1605,7 @@ int ooc_destroy(ooc_ctx *c) {
   for (size_t k = 0; k < c->fields.size(); k++) free_host(c->fields[k].host, c->pinned[k]);
   if (c->argtab_host) free_host(c->argtab_host, true);
   if (c->argtab_dev) (void)hipFree(c->argtab_dev);
+  free_rings(c);
   if (c->own_streams) {
     (void)hipStreamDestroy(c->s_up);
     (void)hipStreamDestroy(c->s_comp);
@@ -1551,6 +1687,11 @@ int ooc_debug_plan(ooc_ctx *c, ooc_plan_info *out) {
     out->down = c->dbg_down.data();
     out->edge = c->dbg_edge.data();
     out->temporary = P.temporary.data();
+    c->dbg_ring.assign(nf, 0);
+    if (P.ring)
+      for (int f : P.slot_fields) c->dbg_ring[f] = P.ring_rows[f];
+    out->ring = P.ring ? 1 : 0;
+    out->ring_rows = c->dbg_ring.data();
     return OOC_OK;
   });
 }

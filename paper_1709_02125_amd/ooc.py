@@ -20,6 +20,7 @@ ARG_DAT, ARG_RED, ARG_CONST, ARG_DEVSCALAR = 0, 1, 2, 3
 FLAG_CYCLIC, FLAG_PREFETCH, FLAG_FP32_STREAM, FLAG_INCORE = 1, 2, 4, 8
 FLAG_GRAPH, FLAG_FUSE, FLAG_DEBUG_POISON, FLAG_DEBUG_SYNC, FLAG_PLAN_ONLY = 16, 32, 64, 128, 256
 FLAG_KERNEL_COPY = 512
+FLAG_RING = 1024
 FIELD_RESIDENT = 1
 SCRATCH_DOUBLES = 524288  # OOC_MLP_SCRATCH_DOUBLES: static device scratch of ooc_mlp_predict_noalloc
 
@@ -65,7 +66,8 @@ class ooc_plan_info(ctypes.Structure):
                 ("loop_rows", ctypes.POINTER(ctypes.c_int64)), ("resident", ctypes.POINTER(ctypes.c_int64)),
                 ("nup", ctypes.c_int32), ("ndown", ctypes.c_int32), ("nedge", ctypes.c_int32),
                 ("up", ctypes.POINTER(ctypes.c_int64)), ("down", ctypes.POINTER(ctypes.c_int64)),
-                ("edge", ctypes.POINTER(ctypes.c_int64)), ("temporary", ctypes.POINTER(ctypes.c_int32))]
+                ("edge", ctypes.POINTER(ctypes.c_int64)), ("temporary", ctypes.POINTER(ctypes.c_int32)),
+                ("ring", ctypes.c_int32), ("ring_rows", ctypes.POINTER(ctypes.c_int64))]
 
 
 EXPORTS = ["ooc_create", "ooc_bind_device", "ooc_decl_field", "ooc_decl_reduction", "ooc_set_reduction",
@@ -200,10 +202,16 @@ class Context:
         self._keep = []
         if bind:
             import torch
-            nbytes = int(arena_bytes if arena_bytes is not None else budget)
-            self.arena = torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
             self.streams = [torch.cuda.Stream() for _ in range(3)]
-            self._check(self.lib.ooc_bind_device(self._h, ctypes.c_void_p(self.arena.data_ptr()), nbytes,
+            if flags & FLAG_RING:
+                # ring slabs: the library allocates the rings (and the small
+                # reduction / resident area) within the budget itself
+                self.arena, ptr, nbytes = None, None, 0
+            else:
+                nbytes = int(arena_bytes if arena_bytes is not None else budget)
+                self.arena = torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
+                ptr = self.arena.data_ptr()
+            self._check(self.lib.ooc_bind_device(self._h, ctypes.c_void_p(ptr), nbytes,
                                                  ctypes.c_void_p(self.streams[0].cuda_stream),
                                                  ctypes.c_void_p(self.streams[1].cuda_stream),
                                                  ctypes.c_void_p(self.streams[2].cuda_stream)))
@@ -381,6 +389,8 @@ class Context:
             "down": arr(p.down, p.ndown * 4, (p.ndown, 4)),
             "edge": arr(p.edge, p.nedge * 4, (p.nedge, 4)),
             "temporary": np.ctypeslib.as_array(p.temporary, shape=(F,)).copy() if F else np.zeros(0),
+            "ring": bool(p.ring),
+            "ring_rows": np.ctypeslib.as_array(p.ring_rows, shape=(F,)).copy() if F else np.zeros(0, np.int64),
         }
 
     def field_shape(self, f: int):

@@ -43,14 +43,20 @@ def test_hydro2d_c1_config_matches_oracle():
     (16, 3, ooc.FLAG_DEBUG_POISON, True), (33, 2, ooc.FLAG_PREFETCH, False), (0, 3, ooc.FLAG_DEBUG_SYNC, True),
     (6, 3, ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, True), pytest.param(5, 3, ooc.FLAG_GRAPH, True, marks=GRAPH_OFF),
     pytest.param(9, 2, ooc.FLAG_GRAPH | ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, True, marks=GRAPH_OFF), (4, 3, ooc.FLAG_KERNEL_COPY, True),
-    (11, 3, ooc.FLAG_KERNEL_COPY | ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, False)])
+    (11, 3, ooc.FLAG_KERNEL_COPY | ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, False),
+    # ring slabs (no edge copy)
+    (5, 2, ooc.FLAG_RING, True), (7, 3, ooc.FLAG_RING | ooc.FLAG_DEBUG_POISON | ooc.FLAG_PREFETCH, True),
+    (9, 2, ooc.FLAG_RING | ooc.FLAG_KERNEL_COPY, False), (3, 4, ooc.FLAG_RING | ooc.FLAG_DEBUG_SYNC, True)])
 def test_hydro2d_tiled_equals_untiled_bit_exact(tile_rows, slots, flags, cyclic):
     nx, ny, steps = 40, 51, 5  # several chains: graph mode replays its capture
     say("case: tiled vs in-core", tile_rows, slots, flags, cyclic)
     ref, rdts, _ = gpu_hydro(nx, ny, steps, incore=True)
-    # budget large enough for any forced tile height at this slot count
-    got, gdts, st = gpu_hydro(nx, ny, steps, budget=slots * h2.device_footprint_bytes(nx, ny),
-                              tile_rows=tile_rows, slots=slots, flags=flags, cyclic=cyclic)
+    # budget large enough for any forced tile height at this slot count (ring
+    # slabs: plus one 64 KiB granule per field, which at this tiny grid is
+    # more than a field's rows)
+    budget = slots * h2.device_footprint_bytes(nx, ny) + (len(h2.FIELDS) << 16 if flags & ooc.FLAG_RING else 0)
+    got, gdts, st = gpu_hydro(nx, ny, steps, budget=budget, tile_rows=tile_rows, slots=slots, flags=flags,
+                              cyclic=cyclic)
     if tile_rows:
         assert st["ntiles_last"] == -(-(ny + 4) // tile_rows) or st["ntiles_last"] >= 2
     for n in STATE:

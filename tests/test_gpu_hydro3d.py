@@ -57,13 +57,15 @@ def test_hydro3d_incore_matches_oracle():
     (1, 2, 0, False), (3, 3, ooc.FLAG_PREFETCH, True), (8, 4, ooc.FLAG_DEBUG_POISON, True),
     (13, 2, ooc.FLAG_PREFETCH, False), (4, 3, ooc.FLAG_DEBUG_SYNC, True),
     (5, 3, ooc.FLAG_FUSE | ooc.FLAG_PREFETCH, True), pytest.param(6, 3, ooc.FLAG_GRAPH, True, marks=GRAPH_OFF),
-    (7, 3, ooc.FLAG_KERNEL_COPY | ooc.FLAG_PREFETCH, True)])
+    (7, 3, ooc.FLAG_KERNEL_COPY | ooc.FLAG_PREFETCH, True),
+    (6, 2, ooc.FLAG_RING | ooc.FLAG_DEBUG_POISON, True), (9, 3, ooc.FLAG_RING | ooc.FLAG_PREFETCH, False)])
 def test_hydro3d_tiled_equals_untiled_bit_exact(tile_rows, slots, flags, cyclic):
     n, steps = (20, 18, 37), 3
     say("case: hydro3d tiled vs in-core", tile_rows, slots, flags, cyclic)
     ref, rdts, _, rmass = gpu_hydro3d(n, steps, incore=True)
-    got, gdts, st, mass = gpu_hydro3d(n, steps, budget=slots * h3.device_footprint_bytes(n), tile_rows=tile_rows,
-                                      slots=slots, flags=flags, cyclic=cyclic)
+    budget = slots * h3.device_footprint_bytes(n) + (len(h3.FIELDS) << 16 if flags & ooc.FLAG_RING else 0)
+    got, gdts, st, mass = gpu_hydro3d(n, steps, budget=budget, tile_rows=tile_rows, slots=slots, flags=flags,
+                                      cyclic=cyclic)
     assert st["ntiles_last"] >= 2
     for name in STATE3:
         assert np.array_equal(got[name], ref[name]), name

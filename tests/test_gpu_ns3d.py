@@ -49,6 +49,7 @@ def test_ns3d_tiled_matches_oracle():
 @pytest.mark.parametrize("tile_rows,chain_steps,slots,flags", [
     (2, 1, 3, ooc.FLAG_PREFETCH), (3, 2, 2, ooc.FLAG_PREFETCH), (5, 2, 4, 0), (7, 3, 3, ooc.FLAG_PREFETCH),
     (0, 1, 3, 0), (4, 1, 3, ooc.FLAG_FUSE), (6, 2, 3, ooc.FLAG_KERNEL_COPY | ooc.FLAG_PREFETCH),
+    (6, 2, 2, ooc.FLAG_RING | ooc.FLAG_PREFETCH), (3, 3, 3, ooc.FLAG_RING | ooc.FLAG_DEBUG_POISON),
     pytest.param(4, 1, 3, ooc.FLAG_FUSE | ooc.FLAG_GRAPH, marks=GRAPH_OFF)])
 def test_ns3d_tiled_equals_incore(tile_rows, chain_steps, slots, flags):
     n, steps = 20, 3
@@ -94,7 +95,8 @@ def test_ns3d_two_block_columns_match_oracle_and_incore():
 
 
 @pytest.mark.parametrize("tile_rows,chain_steps,slots,flags", [
-    (0, 1, 3, 0), (3, 2, 2, ooc.FLAG_PREFETCH), (5, 3, 2, ooc.FLAG_PREFETCH), (7, 1, 4, ooc.FLAG_FUSE)])
+    (0, 1, 3, 0), (3, 2, 2, ooc.FLAG_PREFETCH), (5, 3, 2, ooc.FLAG_PREFETCH), (7, 1, 4, ooc.FLAG_FUSE),
+    (4, 3, 2, ooc.FLAG_RING | ooc.FLAG_PREFETCH), (6, 2, 3, ooc.FLAG_RING | ooc.FLAG_DEBUG_POISON)])
 def test_ns3d_fused_residual_equals_stored_gradients(tile_rows, chain_steps, slots, flags):
     # The residual that evaluates the gradients itself (15 fields) against
     # the chain with the 12 stored gradient fields: bit for bit, in core and
@@ -130,8 +132,8 @@ def test_ns3d_fused_two_block_columns_match_oracle():
         assert np.array_equal(got[q], ref[q]), q
 
 
-@pytest.mark.parametrize("k", [6, 2])
-def test_ns3d_fp32_streaming_matches_oracle_with_the_same_roundings(k):
+@pytest.mark.parametrize("k,ring", [(6, False), (2, False), (2, True)])
+def test_ns3d_fp32_streaming_matches_oracle_with_the_same_roundings(k, ring):
     # Extension: the streamed fields are stored on the host and moved as
     # float32; compute stays float64 on the device.  The initial primitives
     # are rounded once on the way in, and every chain of k steps rounds the
@@ -143,7 +145,7 @@ def test_ns3d_fp32_streaming_matches_oracle_with_the_same_roundings(k):
     n, steps = 24, 6
     say("case: ns3d fp32 streaming, chains of", k)
     prims = tgv_initial_state(n)
-    flags = ooc.FLAG_FP32_STREAM | ooc.FLAG_PREFETCH
+    flags = ooc.FLAG_FP32_STREAM | ooc.FLAG_PREFETCH | (ooc.FLAG_RING if ring else 0)
     got, st = gpu_ns(n, steps, tile_rows=6, chain_steps=k, slots=2, flags=flags, prims=prims)
     assert st["ntiles_last"] >= 3
     if k == 6:

@@ -36,7 +36,8 @@ def test_random_chain_gpu_matches_untiled(seed):
     loops = random_chain(nx, ny, shapes, rng, int(rng.integers(3, 12)))
     rows = ny + 2 * H + 1
     for tile_rows, slots, flags in [(0, 3, ooc.FLAG_INCORE), (1, 2, 0), (3, 3, ooc.FLAG_DEBUG_POISON),
-                                    (rows // 2 + 1, 4, 0), (5, 3, ooc.FLAG_CYCLIC)]:
+                                    (rows // 2 + 1, 4, 0), (5, 3, ooc.FLAG_CYCLIC),
+                                    (2, 2, ooc.FLAG_RING | ooc.FLAG_DEBUG_POISON), (4, 3, ooc.FLAG_RING)]:
         say("case: toy seed", seed, "tile_rows", tile_rows, "slots", slots, "flags", flags)
         c, host, shapes2 = make_ctx_bound(nx, ny, nf, seed, flags)
         assert shapes2 == shapes
@@ -74,7 +75,7 @@ def test_prefetch_across_different_consecutive_chains(seed):
     rows = ny + 2 * H + 1
     for tile_rows, slots, flags in [(2, 2, ooc.FLAG_PREFETCH), (5, 3, ooc.FLAG_PREFETCH),
                                     (rows // 3 + 1, 4, ooc.FLAG_PREFETCH | ooc.FLAG_DEBUG_POISON),
-                                    (3, 3, 0)]:
+                                    (3, 3, 0), (4, 2, ooc.FLAG_PREFETCH | ooc.FLAG_RING | ooc.FLAG_DEBUG_POISON)]:
         say("case: toy prefetch seed", seed, "tile_rows", tile_rows, "slots", slots, "flags", flags)
         c, host, shapes2 = make_ctx_bound(nx, ny, nf, 100 + seed, flags)
         assert shapes2 == shapes

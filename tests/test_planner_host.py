@@ -411,3 +411,76 @@ def test_random_3d_chains_tiled_along_z_equal_untiled(seed):
                 assert lr[0, 0] == lp.rng[2][0] and lr[-1, 1] == lp.rng[2][1]
                 assert all(lr[t, 1] == lr[t + 1, 0] for t in range(p["ntiles"] - 1))
             c.close()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_chains_on_ring_slabs_equal_untiled(seed):
+    # Ring slabs (OOC_FLAG_RING): the same random toy chains replayed with
+    # one ring per field (row r at r mod R, no edge copy, new rows poisoned)
+    # against the untiled program, 2D and 3D; every ring holds the rows of
+    # the tiles the pipeline can have in flight.
+    rng = np.random.default_rng(200 + seed)
+    cyclic = bool(seed % 2)
+    flags = ooc.FLAG_RING | (ooc.FLAG_CYCLIC if cyclic else 0)
+    if seed < 5:
+        nx, ny = int(rng.integers(3, 9)), int(rng.integers(5, 14))
+        nf = int(rng.integers(2, 5))
+        _, _, shapes = make_ctx(nx, ny, nf, np.random.default_rng(seed))
+        loops = random_chain(nx, ny, shapes, rng, int(rng.integers(3, 12)))
+        rows, ndim = ny + 2 * H + 1, 2
+    else:
+        n = (int(rng.integers(3, 6)), int(rng.integers(3, 6)), int(rng.integers(5, 12)))
+        nf = int(rng.integers(2, 5))
+        cens = [CENTRINGS3[int(rng.integers(len(CENTRINGS3)))] for _ in range(nf)]
+        loops, rows, ndim = None, n[2] + 2 * H + 1, 3
+    for slots in (2, 3):
+        for h in range(1, rows + 1):
+            if ndim == 2:
+                c, host, shapes2 = make_ctx(nx, ny, nf, np.random.default_rng(seed), flags=flags)
+            else:
+                c = ooc.Context(3, n, H, 1 << 30, flags, bind=False)
+                frng = np.random.default_rng(seed)
+                host, shapes = {}, {}
+                for f in range(nf):
+                    init = frng.standard_normal(c.field_shape_for(cens[f]))
+                    hnd = c.decl_field("f%d" % f, cens[f], init)
+                    host[hnd], shapes[hnd] = init, cens[f]
+                if loops is None:
+                    loops = random_chain3(n, shapes, rng, int(rng.integers(3, 10)))
+            c.set_schedule(tile_rows=h, slots=slots)
+            queue(c, loops)
+            p = c.debug_plan()
+            assert p["ring"]
+            ref = (tile_sim.run_untiled if ndim == 2 else tile_sim.run_untiled3)(loops, host, H)
+            got = tile_sim.run_tiled_ring(loops, host, p, H, slots, ndim)
+            for f in host:
+                if cyclic and p["temporary"][f] and any(d[0] == f for lp in loops for d in lp.dats):
+                    continue  # host copy intentionally stale
+                assert np.array_equal(got[f], ref[f]), (seed, h, slots, f)
+            c.close()
+
+
+def test_ring_slabs_hold_taller_tiles_without_edge_copies():
+    # The 15-field Navier-Stokes chain at 512^3 on a third of its footprint,
+    # chains of 3 steps, 2 slots: rings hold each field's rows once, so the
+    # same budget fits taller tiles than slots that each hold a copy of the
+    # skew; ring sizes are whole multiples of the granule
+    from paper_1709_02125_amd import ns3d as N
+    n = 512
+    budget = N.footprint_bytes(n, True) // 3
+    rows = {}
+    for ring in (False, True):
+        app = N.NS3D(n, None, budget=budget, flags=ooc.FLAG_RING if ring else 0, plan_only=True, fused=True)
+        app.ctx.set_flags(ooc.FLAG_CYCLIC, 0)
+        app.ctx.set_schedule(tile_rows=0, chain_steps=3, slots=2)
+        for _ in range(3):
+            app.queue_step()
+        p = app.ctx.debug_plan()
+        assert p["ring"] == ring
+        assert p["slot_bytes"] * (1 if ring else p["slots"]) <= budget
+        if ring:
+            plane = ooc.row_pitch(n, N.NH) * (n + 2 * N.NH + 1) * 8
+            assert (p["ring_rows"] > 0).sum() == 15
+        rows[ring] = p["tile_rows"]
+        app.close()
+    assert rows[True] >= 2 * rows[False], rows

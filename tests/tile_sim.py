@@ -202,3 +202,68 @@ def run_tiled3(loops, host, plan, H, slots):
             A = res[f, t, 0]
             arr[f][r0:r1] = slot[(s, f)][r0 - A:r1 - A]
     return arr
+
+
+# ---- ring slabs: one ring per field, stored row (plane) r at position r mod R
+
+def run_tiled_ring(loops, host, plan, H, slots, ndim=2):
+    """Follow a ring-slab plan (OOC_FLAG_RING) in 2D (ndim=2: rows) or 3D
+    (planes): per field one ring of plan["ring_rows"] rows, stored row r at
+    position r mod R.  The rows a tile brings in are NaN-poisoned before its
+    uploads; the rows two tiles share stay where they are (no edge copy).
+    Also checks that each ring holds the rows of any `slots` consecutive
+    tiles (the tiles the pipeline can have in flight)."""
+    T = plan["ntiles"]
+    res = plan["resident"]
+    R = plan["ring_rows"]
+    assert plan["ring"]
+    arr = {f: a.copy() for f, a in host.items()}
+    used = sorted(set(f for lp in loops for (f, _, _) in lp.dats))
+    ring = {f: np.full((max(int(R[f]), 1),) + host[f].shape[1:], np.nan) for f in used}
+    up = {t: [r for r in plan["up"] if r[1] == t] for t in range(T)}
+    down = {t: [r for r in plan["down"] if r[1] == t] for t in range(T)}
+    pos = lambda f, r: np.asarray(r) % int(R[f])
+    for t in range(T):
+        for f in used:
+            A, B = res[f, t]
+            if B <= A:
+                continue
+            held = [res[f, u] for u in range(max(0, t - slots + 1), t + 1) if res[f, u, 1] > res[f, u, 0]]
+            assert max(b for _, b in held) - min(a for a, _ in held) <= R[f], \
+                "ring of field %d too small for %d tiles in flight at tile %d" % (f, slots, t)
+            prev = t > 0 and res[f, t - 1, 1] > res[f, t - 1, 0]
+            new0 = max(A, res[f, t - 1, 1]) if prev else A
+            if new0 < B:
+                ring[f][pos(f, np.arange(new0, B))] = np.nan
+        for f, _, r0, r1 in up[t]:
+            ring[f][pos(f, np.arange(r0, r1))] = arr[f][r0:r1]
+
+        if ndim == 2:
+            def get(f, I, J, t=t):
+                r = J + H
+                assert (r >= res[f, t, 0]).all() and (r < res[f, t, 1]).all()
+                return ring[f][pos(f, r), I + H]
+
+            def put(f, I, J, v, t=t):
+                r = J + H
+                assert (r >= res[f, t, 0]).all() and (r < res[f, t, 1]).all()
+                ring[f][pos(f, r), I + H] = v
+
+            for i, lp in enumerate(loops):
+                apply_loop(lp, get, put, tuple(plan["loop_rows"][i, t]))
+        else:
+            def get(f, I, J, K, t=t):
+                r = K + H
+                assert (r >= res[f, t, 0]).all() and (r < res[f, t, 1]).all()
+                return ring[f][pos(f, r), J + H, I + H]
+
+            def put(f, I, J, K, v, t=t):
+                r = K + H
+                assert (r >= res[f, t, 0]).all() and (r < res[f, t, 1]).all()
+                ring[f][pos(f, r), J + H, I + H] = v
+
+            for i, lp in enumerate(loops):
+                apply_loop3(lp, get, put, tuple(plan["loop_rows"][i, t]))
+        for f, _, r0, r1 in down[t]:
+            arr[f][r0:r1] = ring[f][pos(f, np.arange(r0, r1))]
+    return arr
