@@ -724,6 +724,8 @@ def main():
                     help="ns3d: the paper's per-tile slots with edge copies instead of ring slabs (the default "
                          "for ns3d)")
     ap.add_argument("--ring", action="store_true", help="hydro proxies: ring slabs instead of slots")
+    ap.add_argument("--cache-tiling", type=int, nargs="*", default=None,
+                    help="also time the in-core run cut into tiles of these heights (cache blocking, no transfers)")
     ap.add_argument("--stored-gradients", action="store_true",
                     help="ns3d: the 27-field chain with a gradient loop and stored gradients (default: the "
                          "15-field chain whose residual evaluates the gradients itself)")
@@ -809,9 +811,21 @@ def main():
     # ---- other schedules of the same grid and budget (not the headline)
     variants = {}
     if not args.no_variants:
-        for vname, vflags, vopts in w.variants():
+        vlist = list(w.variants())
+        if args.cache_tiling:
+            # every field resident, the chain still cut into skewed tiles of
+            # this many rows (planes), so a tile's rows can be reused from the
+            # caches across the chain's loops
+            vlist += [("incore_cache_tiled_%d" % h, ooc.FLAG_INCORE, {"incore_tile_rows": h})
+                      for h in args.cache_tiling]
+        for vname, vflags, vopts in vlist:
             t = time.perf_counter()
-            app = w.make(w.budget, vflags, **vopts)
+            if "incore_tile_rows" in vopts:
+                app = w.make(0, vflags, incore=True)
+                app.ctx.set_schedule(tile_rows=vopts["incore_tile_rows"], chain_steps=args.chain_steps if ns else 0,
+                                     slots=args.slots)
+            else:
+                app = w.make(w.budget, vflags, **vopts)
             try:
                 app.initialise()
                 runner = summary_runner(app, *vopts["summary"]) if "summary" in vopts else None

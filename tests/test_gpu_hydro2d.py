@@ -345,3 +345,19 @@ def test_hydro2d_tile_stage_timing_follows_the_pipeline():
         if prev is not None:
             assert prev["d2h_end_us"] <= r["h2d_begin_us"] + eps, (r["tile"], prev, r)
     assert recs[0]["h2d_begin_us"] == 0.0 and recs[-1]["d2h_end_us"] > 0.0
+
+
+def test_hydro2d_incore_cache_tiled_bit_exact():
+    # Cache blocking without transfers: every field resident, the chain still
+    # cut into skewed tiles (so a tile's rows are reused from cache across
+    # the chain's loops) -- bit-identical to the plain in-core run
+    nx, ny, steps = 64, 90, 4
+    say("case: in-core, tiled for cache")
+    ref, rdts, _ = gpu_hydro(nx, ny, steps, incore=True)
+    for h in (5, 16):
+        got, gdts, st = gpu_hydro(nx, ny, steps, incore=True, tile_rows=h)
+        assert st["ntiles_last"] >= ny // h
+        assert st["last_bytes_h2d"] == 0 and st["last_bytes_d2h"] == 0
+        for n in STATE:
+            assert np.array_equal(got[n], ref[n]), (h, n)
+        assert gdts == rdts

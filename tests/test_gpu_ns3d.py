@@ -173,3 +173,14 @@ def test_ns3d_fp32_streaming_matches_oracle_with_the_same_roundings(k, ring):
         e = rel_err(got[q], o.interior(q))
         say(q, e)
         assert e <= TOL, q
+
+
+def test_ns3d_incore_cache_tiled_bit_exact():
+    # every field resident, chains of 2 steps cut into skewed 5-plane tiles
+    n, steps = 24, 2
+    say("case: ns3d in-core, tiled for cache")
+    ref, _ = gpu_ns(n, steps, incore=True, fused=True)
+    got, st = gpu_ns(n, steps, incore=True, fused=True, tile_rows=5, chain_steps=2)
+    assert st["ntiles_last"] >= 5
+    for q in N.Q:
+        assert np.array_equal(got[q], ref[q]), q
