@@ -432,7 +432,10 @@ void free_rings(ooc_ctx *c) {
 // data does not live in the rings between chains.  Launch arguments cached
 // for earlier chains point into the old rings and are dropped.
 void ensure_rings(ooc_ctx *c, const Plan &P) {
-  bool ok = c->stage_alloc >= (uint64_t)c->slots * P.stage_bytes;
+  // the staging areas are laid out at the stride they were allocated with:
+  // that stride must hold this plan's staging, and the allocation one area
+  // per slot at that stride (the slot count may have grown since)
+  bool ok = c->stage_stride >= P.stage_bytes && c->stage_alloc >= (uint64_t)c->slots * c->stage_stride;
   for (int f : P.slot_fields) ok = ok && c->rings[f].bytes >= P.ring_bytes[f];
   if (ok) return;
   for (hipStream_t st : {c->s_up, c->s_comp, c->s_down}) HIPCHK(hipStreamSynchronize(st));
@@ -768,6 +771,9 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
   auto slot_of = [&](int64_t g) {
     return P.ring ? c->stage_base + (uint64_t)(g % S) * c->stage_stride : c->slot_base + (uint64_t)(g % S) * c->slot_stride;
   };
+  if (P.ring && P.stage_bytes &&
+      (c->stage_stride < P.stage_bytes || (uint64_t)S * c->stage_stride > c->stage_alloc))
+    throw ArgError(OOC_E_STATE, "ring staging areas do not cover the plan");
   for (int t = 0; t < T; t++) {
     char *slot = slot_of(g0 + t);
     for (int i = 0; i < n; i++)

@@ -9,6 +9,8 @@
 //     that tile, and inside the field's storage;
 //   - the slot holds every field's rows and fits the slot capacity;
 // and any memory error or undefined behaviour aborts the run.
+#include <algorithm>
+#include <climits>
 #include <cstdio>
 #include <cstdlib>
 #include <random>
@@ -119,6 +121,24 @@ void check_plan(const Case &c, const Plan &P, uint64_t capacity, int seed) {
   check(T >= 1, "at least one tile", seed);
   check((int)P.e.size() == n * T, "tile ends sized loops x tiles", seed);
   check(P.slot_bytes <= capacity, "slot fits its capacity", seed);
+  if (P.ring) {
+    check((int)P.ring_rows.size() == nf && (int)P.ring_bytes.size() == nf, "ring sizes per field", seed);
+    for (int f = 0; f < nf; f++) {
+      if (P.ring_bytes.size() != (size_t)nf) break;
+      check(P.ring_bytes[f] >= (uint64_t)P.ring_rows[f] * c.fields[f].row_bytes_dev(), "ring holds its rows", seed);
+      // the rows of S consecutive tiles fit the ring
+      for (int t = 0; t < T; t++) {
+        int64_t lo = INT64_MAX, hi = INT64_MIN;
+        for (int u = t; u < std::min(T, t + P.S); u++) {
+          const int64_t A = P.resA[(size_t)f * T + u], B = P.resB[(size_t)f * T + u];
+          if (B <= A) continue;
+          lo = std::min(lo, A);
+          hi = std::max(hi, B);
+        }
+        if (hi > lo) check(hi - lo <= P.ring_rows[f], "tiles in flight fit the ring", seed);
+      }
+    }
+  }
   for (int i = 0; i < n; i++) {
     if (P.lo[i] >= P.hi[i]) continue;
     check(P.s(i, 0) == P.lo[i], "first tile starts at the loop start", seed);
@@ -152,7 +172,7 @@ int main(int argc, char **argv) {
   for (int seed = 0; seed < ncases; seed++) {
     std::mt19937_64 rng(0x9e3779b97f4a7c15ull ^ (uint64_t)seed);
     Case c = random_case(rng, seed);
-    for (int cyclic = 0; cyclic < 2; cyclic++)
+    for (int mode = 0; mode < 4; mode++)
       for (int S = 2; S <= 4; S++)
         for (int64_t h : {0, 1, 2, 3, 5, 8, 13, 40}) {
           for (uint64_t capacity : {UINT64_MAX, (uint64_t)1 << 16, (uint64_t)1 << 20, (uint64_t)0}) {
@@ -163,7 +183,9 @@ int main(int argc, char **argv) {
             in.fields = &c.fields;
             in.loops = c.loops.data();
             in.nloops = (int)c.loops.size();
-            in.cyclic = cyclic != 0;
+            const bool cyclic = (mode & 1) != 0;
+            in.cyclic = cyclic;
+            in.ring = (mode & 2) != 0;  // ring slabs
             in.S = S;
             in.forced_h = h;
             in.slot_capacity = capacity;

@@ -184,3 +184,27 @@ def test_ns3d_incore_cache_tiled_bit_exact():
     assert st["ntiles_last"] >= 5
     for q in N.Q:
         assert np.array_equal(got[q], ref[q]), q
+
+
+def test_ns3d_fp32_ring_schedule_changes_equal_slots():
+    # Ring slabs keep their float32 staging areas across schedule changes only
+    # while the allocation holds one area per slot at its stride: a
+    # sweep-like sequence -- a long first tile, then a shorter one, then more
+    # slots -- must end in the same state as the same sequence on slots (the
+    # float32 roundings fall at the same chain ends)
+    n = 24
+    say("case: ns3d fp32 ring slabs across schedule changes")
+    prims = tgv_initial_state(n)
+    seq = [(2, 4, 2, 4), (6, 1, 2, 2), (6, 1, 3, 2), (4, 2, 4, 2)]
+    outs = []
+    for ring in (False, True):
+        flags = ooc.FLAG_FP32_STREAM | ooc.FLAG_PREFETCH | (ooc.FLAG_RING if ring else 0)
+        app = N.NS3D(n, prims, budget=16 * N.device_footprint_bytes(n, True), flags=flags, fused=True)
+        app.initialise()
+        for h, k, S, steps in seq:
+            app.ctx.set_schedule(tile_rows=h, chain_steps=k, slots=S)
+            app.run(steps)
+        outs.append({q: app.interior(q) for q in N.Q})
+        app.close()
+    for q in N.Q:
+        assert np.array_equal(outs[0][q], outs[1][q]), q
