@@ -205,10 +205,12 @@ class NS3DWork(Workload):
         # the paper's slots with edge copies, with Prefetch and Cyclic, then
         # its two ablations; the ring-slab headline's other chain lengths;
         # float32 streaming of the same schedule
-        return [("slots_edge_copies", pf, {}), ("slots_no_prefetch_cyclic", 0, {}),
-                ("slots_no_prefetch_no_cyclic", 0, {"cyclic": False}),
+        k3 = {"chain_steps": 3}  # the longest chain whose skew slots can hold at this budget
+        return [("slots_edge_copies_chains_of_3", pf, k3), ("slots_no_prefetch_cyclic_chains_of_3", 0, k3),
+                ("slots_no_prefetch_no_cyclic_chains_of_3", 0, {"cyclic": False, **k3}),
                 ("chains_of_1_step", pf | ring, {"chain_steps": 1}),
                 ("chains_of_2_steps", pf | ring, {"chain_steps": 2}),
+                ("chains_of_3_steps", pf | ring, k3),
                 ("fp32_stream", pf | ring | ooc.FLAG_FP32_STREAM, {})]
 
     def describe(self):
@@ -719,7 +721,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--slots", type=int, default=None, help="slot count (default 3; ns3d: 2)")
     ap.add_argument("--tile-rows", type=int, default=None, help="tile height (default: largest that fits; ns3d: 24)")
-    ap.add_argument("--chain-steps", type=int, default=3, help="ns3d: time steps per chain")
+    ap.add_argument("--chain-steps", type=int, default=4, help="ns3d: time steps per chain")
     ap.add_argument("--slots-mode", action="store_true",
                     help="ns3d: the paper's per-tile slots with edge copies instead of ring slabs (the default "
                          "for ns3d)")
@@ -751,10 +753,11 @@ def main():
         return c5_main(args)
     if args.steps is None:
         args.steps = 20 if args.workload == "hydro2d" else 10
-    # ns3d runs chains of 3 steps on 2 slots: with stored gradients the sweep
-    # of this grid and budget found 24-plane tiles fastest (the largest tile
-    # within 2.5 % in the sweep, 6 % slower over 10 steps); the 15-field chain
-    # takes the largest tile that fits (14 planes at 3-step chains).  The
+    # ns3d runs on ring slabs with chains of 4 steps, the largest tile that
+    # fits and 2 slots: the fastest of the exhaustive sweep of this grid and
+    # budget (tile heights 8 .. largest, chains of 1 .. 4 steps, 2 .. 4 slots;
+    # chains of 3 steps 10 % slower).  With stored gradients and slots the
+    # round-one sweep found 24-plane tiles, chains of 3 steps, 2 slots.  The
     # hydro proxies default to the largest tile and 3 slots.
     ns = args.workload == "ns3d"
     if args.slots is None:
