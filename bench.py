@@ -544,7 +544,11 @@ def c5_main(args):
     of an exhaustive sweep of the FP64 form of the same grid (the schedule
     sweep configuration 4 records) and picks among the float32 form's
     schedules from their planned features alone; the exhaustive float32 sweep
-    that follows is its yardstick (regret) and fallback.  The picked schedule
+    that follows is its yardstick (regret) and fallback.  For hydro2d the
+    training set also holds a float32 sweep of a smaller grid (10240^2 at the
+    same oversubscription): the FP64 form is bound by its uploads whatever
+    the slot count, so its timings carry nothing of the float32 form's
+    download-to-upload slot dependence.  The picked schedule
     then runs `--steps` steps from the initial state (the error of every state
     field against the FP64 oracle after those steps is stated) and, warmed,
     `--steps` more timed ones (the throughput)."""
@@ -587,6 +591,7 @@ def c5_main(args):
             return out
 
         got_state = lambda app: {x: app.interior(x) for x in names}
+        small = None
         form = ("ns3d proxy %d^3 (Taylor-Green, Mach 0.1), %d fields, conserved fields stored and streamed as "
                 "float32, compute in FP64, %s, device budget %.3g B (1/3 of the FP64 fields)" %
                 (n, 15 if fused else 27, "ring slabs" if ring else "slots with edge copies", budget))
@@ -599,6 +604,10 @@ def c5_main(args):
         workload = lambda fl: tune.hydro2d_workload(n, budget, fl, resident_geometry=bool(fl & f32))
         cells = n * n
         names = ("rho0", "e0", "u0", "v0")
+        n_small = n * 2 // 3 // 128 * 128
+        small = (n_small, lambda fl: tune.hydro2d_workload(n_small, budget * n_small ** 2 // n ** 2, fl,
+                                                            resident_geometry=True),
+                 budget * n_small ** 2 // n ** 2)
 
         def fresh(h, k, S):
             rho, ene = hydro_initial_state((n, n))
@@ -628,10 +637,10 @@ def c5_main(args):
         form = ("hydro2d proxy %dx%d, state fields stored and streamed as float32, geometry resident, compute "
                 "in FP64, device budget %.3g B" % (n, n, budget))
 
-    def run_sweep(fl, what):
+    def run_sweep(fl, what, wl=workload, bud=budget):
         t = time.perf_counter()
-        app, plan_ctx, q, cl, rb = workload(fl)
-        recs = tune.sweep(app, plan_ctx, q, cl, rb, budget, cands, chains=2,
+        app, plan_ctx, q, cl, rb = wl(fl)
+        recs = tune.sweep(app, plan_ctx, q, cl, rb, bud, cands, chains=2,
                           log=lambda m: log("%s sweep: %s" % (what, m)))
         app.close()
         del app
@@ -639,7 +648,9 @@ def c5_main(args):
         log("%s sweep: %d schedules, %.0f s" % (what, len(recs), time.perf_counter() - t))
         return recs
 
-    train = run_sweep(0, "FP64 (training)")
+    train_fp64 = run_sweep(0, "FP64 (training)")
+    train_small = run_sweep(f32, "FP32 %d^2 (training)" % small[0], small[1], small[2]) if small else []
+    train = train_fp64 + train_small
     target = run_sweep(f32, "FP32 (yardstick)")
     picks = [tune.transfer_regret(train, target, seed=seed) for seed in (1709, 1, 2)]
     for r in picks:
@@ -686,11 +697,14 @@ def c5_main(args):
            "warmup": steps, "ms_per_step": round(sec / steps * 1e3, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": form, "cells": cells, "schedule": {"tile_rows": h, "chain_steps": k, "slots": S},
-                      "tiles": st["ntiles_last"], "picked_by": "cost model trained on the FP64 sweep"},
+                      "tiles": st["ntiles_last"],
+                      "picked_by": "cost model trained on the FP64 sweep" +
+                                   (" and the FP32 sweep of %d^2" % small[0] if small else "")},
            "incore_value": inc_rate, "pct_of_incore": round(100.0 * rate / inc_rate, 2),
            "incore_ms_per_step": round(inc_sec / steps * 1e3, 3),
            "cost_model": {"picks": picks, "train_schedules": len(train), "target_schedules": len(target)},
-           "sweep_fp64": [{k_: r[k_] for k_ in ("h", "k", "S", "sec_per_cell_step")} for r in train],
+           "sweep_fp64": [{k_: r[k_] for k_ in ("h", "k", "S", "sec_per_cell_step")} for r in train_fp64],
+           "sweep_fp32_small": [{k_: r[k_] for k_ in ("h", "k", "S", "sec_per_cell_step")} for r in train_small],
            "sweep_fp32": [{k_: r[k_] for k_ in ("h", "k", "S", "sec_per_cell_step")} for r in target],
            "fp32_error_vs_fp64_oracle": {"steps": steps, "max_rel_err": errs}}
     if args.c5_records:

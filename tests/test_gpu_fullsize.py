@@ -164,20 +164,28 @@ def ns3d_oracle():
     return snap
 
 
-def test_ns3d_512_10_steps_equals_oracle_and_in_core(ns3d_oracle):
-    # the benchmark's schedule: 24-plane tiles, chains of 3 steps, 2 slots
+NS_CONFIGS = [
+    # the benchmark's headline: 15-field chain (gradients inside the residual)
+    # on ring slabs, largest tiles, chains of 4 steps, 2 slots
+    ("fused residual, ring slabs, largest tiles, 4-step chains, 2 slots", True, ooc.FLAG_RING, (0, 4, 2)),
+    # its variant with stored gradients on slots with edge copies
+    ("stored gradients, slots with edge copies, 24-plane tiles, 3-step chains, 2 slots", False, 0, (24, 3, 2)),
+]
+
+
+@pytest.mark.parametrize("what,fused,extra,sched", NS_CONFIGS, ids=["fused_ring", "stored_slots"])
+def test_ns3d_512_10_steps_equals_oracle_and_in_core(ns3d_oracle, what, fused, extra, sched):
     n, steps = 512, 10
     ref = ns3d_oracle[10]
     prims = tgv_initial_state(n)
     res = []
     for incore in (False, True):
-        say("case: ns3d 512^3 FP64 %s, 10 steps" %
-            ("in core" if incore else "third-of-footprint budget, 24-plane tiles, 3-step chains, 2 slots"))
-        flags = ooc.FLAG_INCORE if incore else ooc.FLAG_PREFETCH
-        budget = N.device_footprint_bytes(n) if incore else N.footprint_bytes(n) // 3
-        app = N.NS3D(n, prims, budget=budget, flags=flags)
+        say("case: ns3d 512^3 FP64 %s, 10 steps" % ("in core" if incore else "third-of-footprint budget, " + what))
+        flags = ooc.FLAG_INCORE if incore else ooc.FLAG_PREFETCH | extra
+        budget = N.device_footprint_bytes(n, fused) if incore else N.footprint_bytes(n, fused) // 3
+        app = N.NS3D(n, prims, budget=budget, flags=flags, fused=fused)
         if not incore:
-            app.ctx.set_schedule(tile_rows=24, chain_steps=3, slots=2)
+            app.ctx.set_schedule(tile_rows=sched[0], chain_steps=sched[1], slots=sched[2])
         app.initialise()
         app.run(steps)
         if not incore:
@@ -192,15 +200,17 @@ def test_ns3d_512_10_steps_equals_oracle_and_in_core(ns3d_oracle):
 
 
 def test_ns3d_512_fp32_stream_20_steps_error(ns3d_oracle):
-    # FP32 storage and transfer of the streamed fields with the schedule the
-    # benchmark's FP32 run uses (32-plane tiles, chains of 2 steps, 2 slots):
-    # stated error per field against the FP64 oracle after 20 steps
+    # FP32 storage and transfer of the streamed fields on the schedule the
+    # cost model picks for the FP32 form (15-field chain on ring slabs,
+    # 16-plane tiles, chains of 4 steps, 2 slots): stated error per field
+    # against the FP64 oracle after 20 steps
     n, steps = 512, 20
     ref = ns3d_oracle[20]
-    say("case: ns3d 512^3 FP32 streaming, third-of-footprint budget, 32-plane tiles, 2-step chains, 20 steps")
-    app = N.NS3D(n, tgv_initial_state(n), budget=N.footprint_bytes(n) // 3,
-                 flags=ooc.FLAG_PREFETCH | ooc.FLAG_FP32_STREAM)
-    app.ctx.set_schedule(tile_rows=32, chain_steps=2, slots=2)
+    say("case: ns3d 512^3 FP32 streaming, third-of-footprint budget, ring slabs, 16-plane tiles, 4-step chains, "
+        "20 steps")
+    app = N.NS3D(n, tgv_initial_state(n), budget=N.footprint_bytes(n, True) // 3,
+                 flags=ooc.FLAG_PREFETCH | ooc.FLAG_FP32_STREAM | ooc.FLAG_RING, fused=True)
+    app.ctx.set_schedule(tile_rows=16, chain_steps=4, slots=2)
     app.initialise()
     app.run(steps)
     got = {q: app.interior(q) for q in N.Q}

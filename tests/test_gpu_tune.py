@@ -1,43 +1,65 @@
-"""GPU: exhaustive schedule sweep on a 256^3 Navier-Stokes grid, then the
-device-trained MLP cost model: it must rank schedules well enough that its
-pick is close to the best measured one, and beat the default schedule."""
+"""GPU: the device-trained MLP cost model against the exhaustive autotuner
+on the Navier-Stokes proxy at 256^3 (the 15-field chain on ring slabs).
+
+The model is judged on schedules it was not trained on: it learns from the
+timings of one sweep (a third of the footprint as budget) and picks among
+the schedules of another configuration (a quarter of the footprint: other
+tile heights fit, other chains are feasible) from their planned features
+alone; its pick must be within 5 % of that configuration's best measured
+schedule and faster than the library's default schedule (largest tile,
+one-step chains, 3 slots).  A held-out split of one sweep is checked too."""
 import numpy as np
 import pytest
 
 from paper_1709_02125_amd import ns3d as N, ooc, tune
 from gpu_util import say
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
+N3 = 256
+CANDS = tune.grid([4, 8, 12, 16, 24, 0], [1, 2, 3, 4], [2, 3, 4])
 
 
-def test_cost_model_proposal_has_small_regret():
-    # a third of the footprint leaves room for 15 of these 36 schedules (the
-    # skew of a multi-step chain is a large part of a small grid)
-    n = 256
-    budget = N.footprint_bytes(n) // 3
-    say("case: tune sweep ns3d 256^3")
-    app, plan_ctx, q, cells, rb = tune.ns3d_workload(n, budget)
-    cands = tune.grid([4, 6, 8, 12, 16, 0], [1, 2], [2, 3, 4])
-    recs = tune.sweep(app, plan_ctx, q, cells, rb, budget, cands, chains=2, log=say)
-    app.close()
-    assert len(recs) >= 12
+@pytest.fixture(scope="module")
+def sweeps():
+    out = {}
+    for frac in (3, 4):
+        budget = N.footprint_bytes(N3, True) // frac
+        say("case: tune sweep ns3d 256^3, budget 1/%d of the footprint" % frac)
+        app, plan_ctx, q, cells, rb = tune.ns3d_workload(N3, budget, ooc.FLAG_RING, fused=True)
+        out[frac] = tune.sweep(app, plan_ctx, q, cells, rb, budget, CANDS, chains=3, log=say)
+        app.close()
+    return out
+
+
+def test_cost_model_picks_within_5_percent_on_another_budget(sweeps):
+    train, target = sweeps[3], sweeps[4]
+    assert len(train) >= 20 and len(target) >= 12
+    assert tune.default_schedule(target) is not None
+    picks = [tune.transfer_regret(train, target, seed=seed) for seed in (1709, 1, 2)]
+    for r in picks:
+        say("trained on 1/3, picked for 1/4:", r["pick"], "regret %.3f gain over default %.3f" %
+            (r["regret"], r["gain_over_default"]))
+    regrets = sorted(r["regret"] for r in picks)
+    assert regrets[1] <= 0.05
+    assert all(r["gain_over_default"] > 1.0 for r in picks)
+
+
+def test_cost_model_in_sample_and_held_out(sweeps):
+    recs = sweeps[3]
     t = np.array([r["sec_per_cell_step"] for r in recs])
-    best = t.min()
     model = tune.CostModel(n_hidden=32, seed=5)
     loss = model.fit(recs, epochs=4000, lr=3e-3)
     say("cost model training loss (standardised log time):", loss)
     (h, k, S), _ = model.propose([((r["h"], r["k"], r["S"]), r["features"]) for r in recs])
-    chosen = [r for r in recs if (r["h"], r["k"], r["S"]) == (h, k, S)][0]["sec_per_cell_step"]
-    regret = chosen / best - 1.0
-    default = [r for r in recs if (r["h"], r["k"], r["S"]) == (0, 1, 3)]
-    say("regret %.3f; default/best %.3f" % (regret, default[0]["sec_per_cell_step"] / best if default else -1))
-    assert regret <= 0.10
-    if default:
-        assert chosen <= default[0]["sec_per_cell_step"] * 1.05
     model.close()
+    chosen = [r for r in recs if (r["h"], r["k"], r["S"]) == (h, k, S)][0]["sec_per_cell_step"]
+    default = tune.default_schedule(recs)["sec_per_cell_step"]
+    say("in-sample pick", (h, k, S), "regret %.3f, default/chosen %.3f" % (chosen / t.min() - 1.0, default / chosen))
+    assert chosen / t.min() - 1.0 <= 0.05
+    assert default / chosen > 1.0
     # held out: trained on half of the measured schedules, it picks among all
     # of them from their planned features alone
     held = [tune.holdout_regret(recs, 0.5, seed) for seed in (1, 2, 3)]
     for r in held:
         say("held-out pick", r["pick"], "regret %.3f gain over default %s" % (r["regret"], r["gain_over_default"]))
-    assert sorted(r["regret"] for r in held)[1] <= 0.10
+    assert sorted(r["regret"] for r in held)[1] <= 0.05
