@@ -193,4 +193,29 @@ inline bool reads_access(int a) { return a == OOC_READ || a == OOC_RW || a == OO
 // Returns OOC_OK or OOC_E_BUDGET; fills plan.
 int make_plan(const PlanInput &in, Plan &plan, std::string &err);
 
+// Ring slabs across consecutive chains.  Rows do not stay in the rings from
+// one chain to the next, so each chain may place its rows anywhere: row r of
+// field f sits at byte (r * row bytes + origin[f]) mod ring bytes.  For the
+// next chain the origin of every ring is chosen among kRingOrigins evenly
+// spaced ones so that its first tiles take ring positions that the previous
+// chain's last tiles no longer hold; that lets the next chain's first
+// uploads start while the previous chain still computes (Prefetch, paper
+// Section 4.1), instead of after its last download.
+constexpr int kRingOrigins = 8;
+
+// The rows each tile of one chain holds, and where they sit in the rings.
+struct RingChain {
+  int T = 0;
+  const int64_t *resA = nullptr, *resB = nullptr;  // [f * T + t]: held rows [resA, resB)
+  const uint64_t *origin = nullptr;                 // per field, bytes
+};
+
+// nf fields; ring_bytes[f] (0: the field has no ring) and row_bytes[f].
+// Fills origin_out[f] for `next` (its own origin is not read) and, for each
+// of next's first S tiles t, wait_out[t]: the last tile of `prev` (index in
+// that chain, -1: none) whose ring positions tile t's rows overlap, whose
+// download must end before tile t's uploads begin.
+void choose_ring_origins(int nf, const uint64_t *ring_bytes, const uint64_t *row_bytes, const RingChain &prev,
+                         const RingChain &next, int S, uint64_t *origin_out, int64_t *wait_out);
+
 }  // namespace ooc

@@ -455,4 +455,56 @@ int make_plan(const PlanInput &in, Plan &P, std::string &err) {
   return OOC_OK;
 }
 
+namespace {
+
+// Do the byte ranges [a, a + la) and [b, b + lb) of a ring of R bytes meet?
+// (a, b < R; la, lb <= R)
+bool ring_ranges_meet(uint64_t a, uint64_t la, uint64_t b, uint64_t lb, uint64_t R) {
+  if (!la || !lb) return false;
+  return (b + R - a) % R < la || (a + R - b) % R < lb;
+}
+
+}  // namespace
+
+void choose_ring_origins(int nf, const uint64_t *ring_bytes, const uint64_t *row_bytes, const RingChain &prev,
+                         const RingChain &next, int S, uint64_t *origin_out, int64_t *wait_out) {
+  for (int t = 0; t < S; t++) wait_out[t] = -1;
+  std::vector<int64_t> w(S), best(S);
+  for (int f = 0; f < nf; f++) {
+    origin_out[f] = 0;
+    const uint64_t R = ring_bytes[f], rb = row_bytes[f];
+    if (!R) continue;
+    // Tile t of the next chain is issued after the download of the tile S
+    // before it; the previous chain's tiles after that one may still be in
+    // flight.  For each candidate origin, the last of those whose rows meet
+    // tile t's ring positions (lexicographically smallest over t wins).
+    bool have = false;
+    for (int q = 0; q < kRingOrigins; q++) {
+      const uint64_t O = (uint64_t)q * (R / kRingOrigins);
+      for (int t = 0; t < S; t++) {
+        w[t] = -1;
+        if (t >= next.T) continue;
+        const int64_t A = next.resA[(size_t)f * next.T + t], B = next.resB[(size_t)f * next.T + t];
+        if (B <= A) continue;
+        const uint64_t a = ((uint64_t)A * rb + O) % R, la = (uint64_t)(B - A) * rb;
+        for (int64_t u = prev.T - 1; u >= 0 && u > (int64_t)prev.T - S + t; u--) {
+          const int64_t pA = prev.resA[(size_t)f * prev.T + u], pB = prev.resB[(size_t)f * prev.T + u];
+          if (pB <= pA) continue;
+          const uint64_t b = ((uint64_t)pA * rb + prev.origin[f]) % R, lb = (uint64_t)(pB - pA) * rb;
+          if (ring_ranges_meet(a, la, b, lb, R)) {
+            w[t] = u;
+            break;
+          }
+        }
+      }
+      if (!have || std::lexicographical_compare(w.begin(), w.end(), best.begin(), best.end())) {
+        best = w;
+        origin_out[f] = O;
+        have = true;
+      }
+    }
+    for (int t = 0; t < S; t++) wait_out[t] = std::max(wait_out[t], best[t]);
+  }
+}
+
 }  // namespace ooc

@@ -107,6 +107,15 @@ struct ooc_ctx {
     int maps = 0;
   };
   std::vector<Ring> rings;
+  // where each ring holds the current chain's rows (bytes; row r at
+  // (r * row bytes + origin) mod ring bytes), and the previous chain's held
+  // rows and origins, from which the next chain's origins are chosen
+  std::vector<uint64_t> ring_origin;
+  bool ring_prev_valid = false;
+  int64_t ring_prev_g0 = 0;
+  int ring_prev_T = 0;
+  std::vector<int64_t> ring_prev_resA, ring_prev_resB;
+  std::vector<uint64_t> ring_prev_origin;
   char *stage_base = nullptr;
   uint64_t stage_stride = 0, stage_alloc = 0;
   uint64_t ring_granule = kRingGranule;
@@ -397,7 +406,8 @@ int64_t sum_partials(const ooc_ctx *c) {
 }
 
 // Device bytes taken ahead of the slots: reduction buffers and resident fields.
-constexpr size_t kArgTableBytes = 8u << 20;  // initial size of the launch-argument table
+constexpr size_t kArgTableBytes = 8u << 20;      // initial size of the launch-argument table
+constexpr size_t kArgTableMaxBytes = 256u << 20;  // it grows while full up to this size
 
 uint64_t reserved_bytes(const ooc_ctx *c) {
   uint64_t used = 0;
@@ -443,6 +453,8 @@ void ensure_rings(ooc_ctx *c, const Plan &P) {
   c->argtab_cache.clear();
   c->argtab_used = 0;
   free_rings(c);
+  c->ring_prev_valid = false;  // the device is done with every earlier chain
+  std::fill(c->ring_origin.begin(), c->ring_origin.end(), 0);
   hipMemAllocationProp prop = {};
   prop.type = hipMemAllocationTypePinned;
   prop.location.type = hipMemLocationTypeDevice;
@@ -473,15 +485,16 @@ void ensure_rings(ooc_ctx *c, const Plan &P) {
 }
 
 // Device address of stored row `row` of field f in tile t: in the tile's
-// slot, or in the field's ring (row r at byte (r * row bytes) mod ring bytes
-// of the first mapping, the window of the tile contiguous from there on).
+// slot, or in the field's ring (row r at byte (r * row bytes + the chain's
+// origin) mod ring bytes of the first mapping, the window of the tile
+// contiguous from there on).
 char *row_ptr(ooc_ctx *c, const Plan &P, int f, int t, char *slot, int64_t row) {
   const Field &fd = c->fields[f];
   const int64_t A = P.resA[(size_t)f * P.T + t];
   if (P.ring) {
     const ooc_ctx::Ring &r = c->rings[f];
     if (!r.bytes) return r.va;  // not held in this chain
-    return r.va + (uint64_t)A * fd.row_bytes_dev() % r.bytes + (row - A) * fd.row_bytes_dev();
+    return r.va + ((uint64_t)A * fd.row_bytes_dev() + c->ring_origin[f]) % r.bytes + (row - A) * fd.row_bytes_dev();
   }
   return slot + P.slab_off[f] + (row - A) * fd.row_bytes_dev();
 }
@@ -515,6 +528,7 @@ void setup_device(ooc_ctx *c) {
     HIPCHK(hipMemGetAllocationGranularity(&g, &prop, hipMemAllocationGranularityMinimum));
     if (g > 0) c->ring_granule = (kRingGranule + g - 1) / g * g;
     c->rings.assign(c->fields.size(), ooc_ctx::Ring());
+    c->ring_origin.assign(c->fields.size(), 0);
     if (!c->arena) {  // bound without an arena: reductions and resident fields get their own
       const uint64_t need = std::max<uint64_t>(reserved_bytes(c), 256);
       HIPCHK(hipMalloc((void **)&c->arena, need));
@@ -759,6 +773,34 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
   for (const Run &r : P.down) down[r.t].push_back(&r);
   for (const Run &r : P.edge) edge[r.t].push_back(&r);
   const int64_t g0 = c->gtile;
+  // ring slabs: each ring's origin for this chain, and for its first S tiles
+  // the previous chain's tile whose download must end first (-1: none)
+  std::vector<int64_t> ring_wait(S, -1);
+  if (P.ring) {
+    const int64_t prev_end = c->ring_prev_g0 + c->ring_prev_T;
+    if (!c->ring_prev_valid || prev_end != g0 || prev_end - 1 <= c->gsynced) {
+      std::fill(c->ring_origin.begin(), c->ring_origin.end(), 0);  // the device is done with the previous chain
+    } else {
+      const int nf = (int)c->fields.size();
+      std::vector<uint64_t> rbytes(nf), rowb(nf);
+      for (int f = 0; f < nf; f++) {
+        rbytes[f] = c->rings[f].bytes;
+        rowb[f] = c->fields[f].row_bytes_dev();
+      }
+      RingChain pv, nx;
+      pv.T = c->ring_prev_T;
+      pv.resA = c->ring_prev_resA.data();
+      pv.resB = c->ring_prev_resB.data();
+      pv.origin = c->ring_prev_origin.data();
+      nx.T = T;
+      nx.resA = P.resA.data();
+      nx.resB = P.resB.data();
+      std::vector<int64_t> w(S);
+      choose_ring_origins(nf, rbytes.data(), rowb.data(), pv, nx, S, c->ring_origin.data(), w.data());
+      for (int t = 0; t < S; t++)
+        if (w[t] >= 0) ring_wait[t] = c->ring_prev_g0 + w[t];
+    }
+  }
   // launch arguments of the whole chain, built and uploaded once per distinct
   // (chain, slot phase) and reused by every later identical chain
   struct Launch {
@@ -789,6 +831,7 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       if (g.kind == OOC_ARG_CONST) akey.append((const char *)&g.value, 8);
   const int64_t phase = g0 % S;
   akey.append((const char *)&phase, 8);
+  if (P.ring) akey.append((const char *)c->ring_origin.data(), c->ring_origin.size() * sizeof(uint64_t));
   size_t abase;
   auto hit = c->argtab_cache.find(akey);
   if (hit != c->argtab_cache.end()) {
@@ -796,11 +839,17 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
   } else {
     if (hostargs.size() > c->argtab_cap) grow_argtab(c, 2 * hostargs.size());
     if (c->argtab_used + hostargs.size() > c->argtab_cap) {
-      // table full: wait until no kernel reads it, then start over
-      drop_graphs(c);
-      HIPCHK(hipStreamSynchronize(c->s_comp));
-      c->argtab_cache.clear();
-      c->argtab_used = 0;
+      // table full: a larger one (ring slabs cycle through several origins,
+      // each a chain of its own here) up to a limit, else wait until no
+      // kernel reads it and start over
+      if (c->argtab_cap * sizeof(KArgs) < kArgTableMaxBytes) {
+        grow_argtab(c, 2 * c->argtab_cap);
+      } else {
+        drop_graphs(c);
+        HIPCHK(hipStreamSynchronize(c->s_comp));
+        c->argtab_cache.clear();
+        c->argtab_used = 0;
+      }
     }
     abase = c->argtab_used;
     std::memcpy(c->argtab_host + abase, hostargs.data(), hostargs.size() * sizeof(KArgs));
@@ -857,9 +906,9 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
     wait_tile(c, c->s_up, c->ev_down, g - S);  // slot free again
     if (t == 0 && prev_last_tile >= 0 && !(c->flags & OOC_FLAG_PREFETCH))
       wait_tile(c, c->s_up, c->ev_comp, prev_last_tile);  // no early start of the next chain
-    // ring slabs: the first tile's rows may map onto ring positions of the
-    // previous chain's last tiles, so it starts once they are downloaded
-    if (P.ring && t == 0 && prev_last_tile >= 0) wait_tile(c, c->s_up, c->ev_down, prev_last_tile);
+    // ring slabs: the first tiles may take ring positions of the previous
+    // chain's last tiles; then they start once those are downloaded
+    if (P.ring && t < S && ring_wait[t] >= 0) wait_tile(c, c->s_up, c->ev_down, ring_wait[t]);
     if (P.ring && (c->flags & OOC_FLAG_DEBUG_POISON)) {
       // poison the rows the tile brings into its rings (before the uploads)
       for (int f : P.slot_fields) {
@@ -1091,6 +1140,14 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
   }
   for (const Run &r : P.down)
     for (int64_t q = r.lo; q < r.hi; q++) c->fields[r.f].last_down[q] = g0 + r.t;
+  if (P.ring) {
+    c->ring_prev_valid = true;
+    c->ring_prev_g0 = g0;
+    c->ring_prev_T = T;
+    c->ring_prev_resA = P.resA;
+    c->ring_prev_resB = P.resB;
+    c->ring_prev_origin = c->ring_origin;
+  }
   // host-copy bookkeeping
   const bool cyclic = (c->flags & OOC_FLAG_CYCLIC) != 0;
   for (size_t f = 0; f < c->fields.size(); f++) {

@@ -164,11 +164,59 @@ void check_plan(const Case &c, const Plan &P, uint64_t capacity, int seed) {
   }
 }
 
+// Two consecutive ring chains: with the origins choose_ring_origins picks,
+// every tile of the previous chain that may still be in flight when one of
+// the next chain's first S tiles uploads (after the tile S before it, and
+// after the chosen wait) holds ring bytes disjoint from that tile's, checked
+// element by element on a map of each ring.
+void check_ring_origins(const Case &c, const Plan &A, const Plan &B, int S, std::mt19937_64 &rng, int seed) {
+  const int nf = (int)c.fields.size();
+  std::vector<uint64_t> R(nf), rb(nf), prev_origin(nf), origin(nf);
+  for (int f = 0; f < nf; f++) {
+    R[f] = A.ring_bytes[f];
+    rb[f] = c.fields[f].row_bytes_dev();
+    const uint64_t units = R[f] / 8;
+    prev_origin[f] = units ? (std::uniform_int_distribution<uint64_t>(0, units - 1)(rng)) * 8 : 0;
+  }
+  RingChain pv, nx;
+  pv.T = A.T;
+  pv.resA = A.resA.data();
+  pv.resB = A.resB.data();
+  pv.origin = prev_origin.data();
+  nx.T = B.T;
+  nx.resA = B.resA.data();
+  nx.resB = B.resB.data();
+  std::vector<int64_t> wait(S);
+  choose_ring_origins(nf, R.data(), rb.data(), pv, nx, S, origin.data(), wait.data());
+  for (int t = 0; t < S; t++) check(wait[t] >= -1 && wait[t] < A.T, "wait names a previous tile", seed);
+  for (int f = 0; f < nf; f++) {
+    if (!R[f]) continue;
+    check(origin[f] < R[f] && origin[f] % (R[f] / kRingOrigins) == 0, "origin is one of the candidates", seed);
+    const uint64_t units = R[f] / 8, per_row = rb[f] / 8;
+    auto cell = [&](int64_t r, uint64_t k, uint64_t o) { return ((uint64_t)r * rb[f] + o) / 8 % units + k; };
+    for (int t = 0; t < S && t < B.T; t++) {
+      const int64_t nA = B.resA[(size_t)f * B.T + t], nB = B.resB[(size_t)f * B.T + t];
+      if (nB <= nA) continue;
+      std::vector<char> held(units, 0);
+      for (int64_t u = 0; u < A.T; u++) {
+        if (u <= (int64_t)A.T - S + t || u <= wait[t]) continue;  // done before tile t uploads
+        const int64_t pA = A.resA[(size_t)f * A.T + u], pB = A.resB[(size_t)f * A.T + u];
+        for (int64_t r = pA; r < pB; r++)
+          for (uint64_t k = 0; k < per_row; k++) held[cell(r, k, prev_origin[f]) % units] = 1;
+      }
+      bool clash = false;
+      for (int64_t r = nA; r < nB && !clash; r++)
+        for (uint64_t k = 0; k < per_row && !clash; k++) clash = held[cell(r, k, origin[f]) % units] != 0;
+      check(!clash, "next chain's tile takes no ring bytes a tile in flight holds", seed);
+    }
+  }
+}
+
 }  // namespace
 
 int main(int argc, char **argv) {
   const int ncases = argc > 1 ? std::atoi(argv[1]) : 300;
-  int planned = 0, budget_refusals = 0;
+  int planned = 0, budget_refusals = 0, rings_checked = 0;
   for (int seed = 0; seed < ncases; seed++) {
     std::mt19937_64 rng(0x9e3779b97f4a7c15ull ^ (uint64_t)seed);
     Case c = random_case(rng, seed);
@@ -196,6 +244,23 @@ int main(int argc, char **argv) {
             if (rc == OOC_OK) {
               planned++;
               check_plan(c, P, capacity, seed);
+              if (P.ring && capacity == ((uint64_t)1 << 20)) {
+                // the next chain: the same plan, or one with other tile heights
+                // that fits the rings the first one sized
+                check_ring_origins(c, P, P, S, rng, seed);
+                PlanInput in2 = in;
+                in2.forced_h = h == 0 ? 3 : h + 2;
+                Plan P2;
+                std::string err2;
+                if (make_plan(in2, P2, err2) == OOC_OK) {
+                  bool fits = true;
+                  for (size_t f = 0; f < P.ring_bytes.size(); f++) fits = fits && P2.ring_bytes[f] <= P.ring_bytes[f];
+                  if (fits) {
+                    rings_checked++;
+                    check_ring_origins(c, P, P2, S, rng, seed);
+                  }
+                }
+              }
             } else {
               budget_refusals++;
               check(!err.empty(), "a refusal says why", seed);
@@ -203,6 +268,7 @@ int main(int argc, char **argv) {
           }
         }
   }
-  std::printf("planned %d, refused %d, failures %d\n", planned, budget_refusals, failures);
+  std::printf("planned %d, refused %d, ring chain pairs %d, failures %d\n", planned, budget_refusals, rings_checked,
+              failures);
   return failures ? 1 : 0;
 }

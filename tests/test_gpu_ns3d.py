@@ -50,6 +50,9 @@ def test_ns3d_tiled_matches_oracle():
     (2, 1, 3, ooc.FLAG_PREFETCH), (3, 2, 2, ooc.FLAG_PREFETCH), (5, 2, 4, 0), (7, 3, 3, ooc.FLAG_PREFETCH),
     (0, 1, 3, 0), (4, 1, 3, ooc.FLAG_FUSE), (6, 2, 3, ooc.FLAG_KERNEL_COPY | ooc.FLAG_PREFETCH),
     (6, 2, 2, ooc.FLAG_RING | ooc.FLAG_PREFETCH), (3, 3, 3, ooc.FLAG_RING | ooc.FLAG_DEBUG_POISON),
+    # one step per chain on rings with Prefetch: each chain's first tiles
+    # start before the previous chain's last downloads (rotated ring origins)
+    (4, 1, 2, ooc.FLAG_RING | ooc.FLAG_PREFETCH | ooc.FLAG_DEBUG_POISON), (2, 1, 3, ooc.FLAG_RING | ooc.FLAG_PREFETCH),
     pytest.param(4, 1, 3, ooc.FLAG_FUSE | ooc.FLAG_GRAPH, marks=GRAPH_OFF)])
 def test_ns3d_tiled_equals_incore(tile_rows, chain_steps, slots, flags):
     n, steps = 20, 3

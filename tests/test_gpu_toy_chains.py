@@ -75,7 +75,8 @@ def test_prefetch_across_different_consecutive_chains(seed):
     rows = ny + 2 * H + 1
     for tile_rows, slots, flags in [(2, 2, ooc.FLAG_PREFETCH), (5, 3, ooc.FLAG_PREFETCH),
                                     (rows // 3 + 1, 4, ooc.FLAG_PREFETCH | ooc.FLAG_DEBUG_POISON),
-                                    (3, 3, 0), (4, 2, ooc.FLAG_PREFETCH | ooc.FLAG_RING | ooc.FLAG_DEBUG_POISON)]:
+                                    (3, 3, 0), (4, 2, ooc.FLAG_PREFETCH | ooc.FLAG_RING | ooc.FLAG_DEBUG_POISON),
+                                    (2, 3, ooc.FLAG_PREFETCH | ooc.FLAG_RING)]:
         say("case: toy prefetch seed", seed, "tile_rows", tile_rows, "slots", slots, "flags", flags)
         c, host, shapes2 = make_ctx_bound(nx, ny, nf, 100 + seed, flags)
         assert shapes2 == shapes
