@@ -200,18 +200,29 @@ class NS3DWork(Workload):
 
     def variants(self):
         from paper_1709_02125_amd import ooc
-        pf = ooc.FLAG_PREFETCH
+        dl = ooc.FLAG_DMA_DOWNLOAD if self.args.download == "dma" else 0
+        pf = ooc.FLAG_PREFETCH | dl
         ring = 0 if self.args.slots_mode else ooc.FLAG_RING
         # the paper's slots with edge copies, with Prefetch and Cyclic, then
-        # its two ablations; the ring-slab headline's other chain lengths;
-        # float32 streaming of the same schedule
+        # its two ablations; the ring-slab headline's other chain lengths and
+        # its downloads by copy kernel; float32 streaming of the same schedule
         k3 = {"chain_steps": 3}  # the longest chain whose skew slots can hold at this budget
-        return [("slots_edge_copies_chains_of_3", pf, k3), ("slots_no_prefetch_cyclic_chains_of_3", 0, k3),
-                ("slots_no_prefetch_no_cyclic_chains_of_3", 0, {"cyclic": False, **k3}),
+        return [("slots_edge_copies_chains_of_3", pf, k3), ("slots_no_prefetch_cyclic_chains_of_3", dl, k3),
+                ("slots_no_prefetch_no_cyclic_chains_of_3", dl, {"cyclic": False, **k3}),
                 ("chains_of_1_step", pf | ring, {"chain_steps": 1}),
                 ("chains_of_2_steps", pf | ring, {"chain_steps": 2}),
                 ("chains_of_3_steps", pf | ring, k3),
+                ("copy_kernel_downloads", (pf & ~dl) | ring, {}) if dl else
+                ("runtime_copy_downloads", pf | ring | ooc.FLAG_DMA_DOWNLOAD, {}),
                 ("fp32_stream", pf | ring | ooc.FLAG_FP32_STREAM, {})]
+
+    def warmup_steps(self, warmup, steps):
+        """Untimed steps before the timed ones: at least one whole chain, and
+        then the trailing partial chain the timed steps end with, so that
+        every chain shape the timed region runs has been planned and its
+        rings sized before it."""
+        k = self.args.chain_steps
+        return -(-max(warmup, k) // k) * k + steps % k
 
     def describe(self):
         form = ("15 fields (gradients evaluated in the residual kernel), 42 loops per step" if self.fused else
@@ -566,12 +577,14 @@ def c5_main(args):
         ring = 0 if args.slots_mode else ooc.FLAG_RING
         budget = int(args.budget) if args.budget else N.footprint_bytes(n, fused) // 3
         cands = tune.grid([8, 16, 24, 32, 48, 0], [1, 2, 3, 4], [2, 3, 4])
-        workload = lambda fl: tune.ns3d_workload(n, budget, fl | ring, fused=fused)
+        dl = ooc.FLAG_DMA_DOWNLOAD  # the chain is bound by its kernels
+        workload = lambda fl: tune.ns3d_workload(n, budget, fl | ring | dl, fused=fused)
         cells = n ** 3
         names = N.Q
 
         def fresh(h, k, S):
-            app = N.NS3D(n, tgv_initial_state(n), budget=budget, flags=ooc.FLAG_PREFETCH | f32 | ring, fused=fused)
+            app = N.NS3D(n, tgv_initial_state(n), budget=budget, flags=ooc.FLAG_PREFETCH | f32 | ring | dl,
+                         fused=fused)
             app.ctx.set_schedule(tile_rows=h, chain_steps=k, slots=S)
             return app
 
@@ -716,7 +729,8 @@ def c5_main(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; 10 for the 3D workloads)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 20 for hydro2d, 10 for hydro3d, two chains for ns3d)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--repeats", type=int, default=3,
                     help="timed runs of --steps steps each for the headline and in-core rates (median reported)")
@@ -729,6 +743,9 @@ def main():
     ap.add_argument("--fp32", action="store_true", help="store and stream fields as float32 on the host")
     ap.add_argument("--no-prefetch", action="store_true")
     ap.add_argument("--kernel-copy", action="store_true", help="host-link transfers by copy kernel")
+    ap.add_argument("--download", choices=["kernel", "dma"], default=None,
+                    help="downloads by copy kernel or by runtime copies (copy engines); default: runtime "
+                         "copies for ns3d (kernel-bound chains), copy kernel for the hydro proxies")
     ap.add_argument("--fuse", action="store_true", help="fuse independent strip loops per tile")
     ap.add_argument("--no-cyclic", action="store_true")
     ap.add_argument("--no-incore", action="store_true")
@@ -765,8 +782,8 @@ def main():
             print("configuration 5 covers hydro2d and ns3d", file=sys.stderr)
             sys.exit(2)
         return c5_main(args)
-    if args.steps is None:
-        args.steps = 20 if args.workload == "hydro2d" else 10
+    if args.steps is None:  # ns3d: two whole chains
+        args.steps = {"hydro2d": 20, "hydro3d": 10, "ns3d": 2 * args.chain_steps}[args.workload]
     # ns3d runs on ring slabs with chains of 4 steps, the largest tile that
     # fits and 2 slots: the fastest of the exhaustive sweep of this grid and
     # budget (tile heights 8 .. largest, chains of 1 .. 4 steps, 2 .. 4 slots;
@@ -792,6 +809,10 @@ def main():
         flags |= ooc.FLAG_FP32_STREAM
     if args.kernel_copy:
         flags |= ooc.FLAG_KERNEL_COPY
+    if args.download is None:  # runtime copies where the stencils bound the chain
+        args.download = "dma" if ns else "kernel"
+    if args.download == "dma":
+        flags |= ooc.FLAG_DMA_DOWNLOAD
     if args.fuse:
         flags |= ooc.FLAG_FUSE
     t = time.perf_counter()
@@ -800,6 +821,7 @@ def main():
         app.ctx.set_schedule(tile_rows=args.tile_rows, slots=args.slots)
     app.initialise()
     log("out-of-core setup %.1f s" % (time.perf_counter() - t))
+    args.warmup = w.warmup_steps(args.warmup, args.steps) if hasattr(w, "warmup_steps") else args.warmup
     ooc_r = timed_run(app, args.steps, args.warmup, w.knames, w.dominant, repeats=args.repeats)
     tile_stages = tile_stage_summary(app, args.chain_steps if args.workload == "ns3d" else 1, args.tile_log)
     app.close()
@@ -909,7 +931,8 @@ def main():
               "prefetch": not args.no_prefetch, "cyclic": not args.no_cyclic,
               "resident_geometry": args.resident_geometry, "resident_state": args.resident_state,
               "fp32_stream": args.fp32,
-              "kernel_copy": args.kernel_copy, "fuse": args.fuse, "tiles": ooc_r["ntiles"],
+              "kernel_copy": args.kernel_copy, "downloads": args.download, "fuse": args.fuse,
+              "tiles": ooc_r["ntiles"],
               "tile_rows": ooc_r["tile_rows"], "slots": args.slots or 3}
     if args.workload == "ns3d":
         config["chain_steps"] = args.chain_steps

@@ -81,18 +81,28 @@ enum {
   OOC_FLAG_PLAN_ONLY = 256,   /* no host or device storage: for ooc_debug_plan only (schedule search) */
   OOC_FLAG_KERNEL_COPY = 512, /* uploads too by a copy kernel on the pinned arrays' device mapping
                                  (one launch per tile; FP32 converted in flight) instead of runtime
-                                 memcpy calls.  Downloads always go by copy kernel when the host
-                                 arrays are device-mapped (pinned by ooc_bind_device) */
-  OOC_FLAG_RING = 1024        /* ring slabs instead of slots: each streamed field lives in one ring
+                                 memcpy calls.  Downloads go by copy kernel when the host arrays
+                                 are device-mapped (pinned by ooc_bind_device), unless
+                                 OOC_FLAG_DMA_DOWNLOAD is set */
+  OOC_FLAG_RING = 1024,       /* ring slabs instead of slots: each streamed field lives in one ring
                                  of device memory mapped twice at consecutive virtual addresses
                                  (HIP virtual memory API), so the rows two tiles share stay in
                                  place -- no edge copy -- and a ring only holds the rows of the S
                                  tiles in flight.  The rings are allocated by the library within
                                  the budget (the arena given to ooc_bind_device then only needs
                                  the reductions and resident fields, or may be NULL with 0 bytes:
-                                 the library allocates that too).  A chain's first tile waits for
-                                 the previous chain's last download.  Fixed at creation;
-                                 OOC_E_ARG at the first flush if the device lacks the API. */
+                                 the library allocates that too).  Each chain places its rows at
+                                 a ring origin of its own, chosen so that its first tiles wait
+                                 only for the downloads of the previous chain's tiles whose ring
+                                 positions they take.  Fixed at creation; OOC_E_ARG at the first
+                                 flush if the device lacks the API. */
+  OOC_FLAG_DMA_DOWNLOAD = 2048 /* downloads by runtime memcpy calls (the copy engines; FP32 rounded
+                                 into a staging area first) instead of the copy kernel, also when
+                                 the host arrays are device-mapped: for chains bound by their
+                                 kernels, which the copy kernel's host stores slow down (ns3d
+                                 512^3 on rings: 60 against 73 ms per step); the copy kernel
+                                 stays faster for chains bound by the link (hydro2d 15360^2).
+                                 Ignored with OOC_FLAG_KERNEL_COPY. */
 };
 
 /* per-field flags for ooc_decl_field */

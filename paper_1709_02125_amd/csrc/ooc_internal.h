@@ -196,11 +196,11 @@ int make_plan(const PlanInput &in, Plan &plan, std::string &err);
 // Ring slabs across consecutive chains.  Rows do not stay in the rings from
 // one chain to the next, so each chain may place its rows anywhere: row r of
 // field f sits at byte (r * row bytes + origin[f]) mod ring bytes.  For the
-// next chain the origin of every ring is chosen among kRingOrigins evenly
-// spaced ones so that its first tiles take ring positions that the previous
-// chain's last tiles no longer hold; that lets the next chain's first
-// uploads start while the previous chain still computes (Prefetch, paper
-// Section 4.1), instead of after its last download.
+// next chain the origins are chosen -- the same fraction q / kRingOrigins of
+// every ring -- so that its first tiles take ring positions that the
+// previous chain's last tiles no longer hold; that lets the next chain's
+// first uploads start while the previous chain still computes (Prefetch,
+// paper Section 4.1), instead of after its last download.
 constexpr int kRingOrigins = 8;
 
 // The rows each tile of one chain holds, and where they sit in the rings.

@@ -468,26 +468,26 @@ bool ring_ranges_meet(uint64_t a, uint64_t la, uint64_t b, uint64_t lb, uint64_t
 
 void choose_ring_origins(int nf, const uint64_t *ring_bytes, const uint64_t *row_bytes, const RingChain &prev,
                          const RingChain &next, int S, uint64_t *origin_out, int64_t *wait_out) {
-  for (int t = 0; t < S; t++) wait_out[t] = -1;
+  // One origin index q for every ring (origin q/kRingOrigins of the ring):
+  // then the chains' origins repeat within kRingOrigins chains, and so do the
+  // launch-argument tables that depend on them.  For each q and each of the
+  // next chain's first S tiles t, the last previous-chain tile still in
+  // flight (after the tile S before t) whose rows meet tile t's ring
+  // positions in any ring; the lexicographically smallest list of those
+  // waits wins, the smaller q on ties.
   std::vector<int64_t> w(S), best(S);
-  for (int f = 0; f < nf; f++) {
-    origin_out[f] = 0;
-    const uint64_t R = ring_bytes[f], rb = row_bytes[f];
-    if (!R) continue;
-    // Tile t of the next chain is issued after the download of the tile S
-    // before it; the previous chain's tiles after that one may still be in
-    // flight.  For each candidate origin, the last of those whose rows meet
-    // tile t's ring positions (lexicographically smallest over t wins).
-    bool have = false;
-    for (int q = 0; q < kRingOrigins; q++) {
+  int best_q = -1;
+  for (int q = 0; q < kRingOrigins; q++) {
+    std::fill(w.begin(), w.end(), -1);
+    for (int f = 0; f < nf; f++) {
+      const uint64_t R = ring_bytes[f], rb = row_bytes[f];
+      if (!R) continue;
       const uint64_t O = (uint64_t)q * (R / kRingOrigins);
-      for (int t = 0; t < S; t++) {
-        w[t] = -1;
-        if (t >= next.T) continue;
+      for (int t = 0; t < S && t < next.T; t++) {
         const int64_t A = next.resA[(size_t)f * next.T + t], B = next.resB[(size_t)f * next.T + t];
         if (B <= A) continue;
         const uint64_t a = ((uint64_t)A * rb + O) % R, la = (uint64_t)(B - A) * rb;
-        for (int64_t u = prev.T - 1; u >= 0 && u > (int64_t)prev.T - S + t; u--) {
+        for (int64_t u = prev.T - 1; u >= 0 && u > (int64_t)prev.T - S + t && u > w[t]; u--) {
           const int64_t pA = prev.resA[(size_t)f * prev.T + u], pB = prev.resB[(size_t)f * prev.T + u];
           if (pB <= pA) continue;
           const uint64_t b = ((uint64_t)pA * rb + prev.origin[f]) % R, lb = (uint64_t)(pB - pA) * rb;
@@ -497,14 +497,14 @@ void choose_ring_origins(int nf, const uint64_t *ring_bytes, const uint64_t *row
           }
         }
       }
-      if (!have || std::lexicographical_compare(w.begin(), w.end(), best.begin(), best.end())) {
-        best = w;
-        origin_out[f] = O;
-        have = true;
-      }
     }
-    for (int t = 0; t < S; t++) wait_out[t] = std::max(wait_out[t], best[t]);
+    if (best_q < 0 || std::lexicographical_compare(w.begin(), w.end(), best.begin(), best.end())) {
+      best = w;
+      best_q = q;
+    }
   }
+  for (int f = 0; f < nf; f++) origin_out[f] = ring_bytes[f] ? (uint64_t)best_q * (ring_bytes[f] / kRingOrigins) : 0;
+  for (int t = 0; t < S; t++) wait_out[t] = best[t];
 }
 
 }  // namespace ooc

@@ -122,7 +122,8 @@ struct ooc_ctx {
   int device = 0;
   // tiles and events
   int64_t gtile = 0, gbase = 0, gsynced = -1;
-  int64_t prev_last_tile = -1;  // last tile of the previously issued chain
+  int64_t prev_last_tile = -1;   // last tile of the previously issued chain
+  int64_t prev2_last_tile = -1;  // last tile of the chain issued before that one
   std::vector<hipEvent_t> ev_up, ev_comp, ev_down;  // indexed by g - gbase
   std::map<std::string, Plan> plans;
   Plan dbg;
@@ -406,7 +407,7 @@ int64_t sum_partials(const ooc_ctx *c) {
 }
 
 // Device bytes taken ahead of the slots: reduction buffers and resident fields.
-constexpr size_t kArgTableBytes = 8u << 20;      // initial size of the launch-argument table
+constexpr size_t kArgTableBytes = 32u << 20;     // initial size of the launch-argument table
 constexpr size_t kArgTableMaxBytes = 256u << 20;  // it grows while full up to this size
 
 uint64_t reserved_bytes(const ooc_ctx *c) {
@@ -1045,12 +1046,13 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       const char *src = row_ptr(c, P, r->f, t, slot, r->lo);
       const size_t nb = (size_t)(r->hi - r->lo) * f.row_bytes_host();
       char *dst = (char *)f.host + r->lo * f.row_bytes_host();
-      // Downloads go by copy kernel into the device-mapped host rows.  DMA
-      // downloads (runtime memcpy) ran faster in short runs, but once many
-      // tiles were queued the runtime blocked the host inside launches and
-      // both link directions fell to about half rate; the copy kernel holds
-      // its rate however far ahead the host issues.
-      if (kcopy || f.host_dev) {
+      // Downloads go by copy kernel into the device-mapped host rows unless
+      // the context asks for the copy engines.  On link-bound chains the
+      // kernel keeps the higher rate (hydro2d 15360^2: 240 against 261 ms
+      // per step in FP64, 100 against 173 ms in FP32); on kernel-bound ones
+      // its host stores slow the stencils beside them and the copy engines
+      // win (ns3d 512^3 on rings: 60 against 73 ms per step).
+      if (kcopy || (f.host_dev && !(c->flags & OOC_FLAG_DMA_DOWNLOAD))) {
         if (!f.host_dev) throw DeviceError("kernel copy needs device-mapped pinned host arrays");
         char *hdst = (char *)f.host_dev + r->lo * f.row_bytes_host();
         const int64_t elems = (r->hi - r->lo) * f.row_elems;
@@ -1259,7 +1261,15 @@ int flush(ooc_ctx *c, bool wait = true) {
     }
   }
   for (auto &ch : chains) {
+    // The host runs at most one chain ahead of the device: a chain is issued
+    // once the one two before it has finished.  (With many chains of
+    // runtime-copy downloads queued, the runtime blocked the host inside
+    // launches for up to 0.4 s and both link directions slowed: hydro2d
+    // 15360^2, 559 against 237 ms per step.)
+    if (c->prev2_last_tile > c->gsynced && c->prev2_last_tile >= c->gbase)
+      timed_call(c, [&] { HIPCHK(hipEventSynchronize(evref(c->ev_down, c, c->prev2_last_tile))); }, kCallWait);
     run_chain(c, c->queue.data() + ch.first, ch.second - ch.first, c->prev_last_tile);
+    c->prev2_last_tile = c->prev_last_tile;
     c->prev_last_tile = c->gtile - 1;
   }
   c->queue.erase(c->queue.begin(), c->queue.begin() + chains.back().second);

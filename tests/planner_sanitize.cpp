@@ -189,9 +189,13 @@ void check_ring_origins(const Case &c, const Plan &A, const Plan &B, int S, std:
   std::vector<int64_t> wait(S);
   choose_ring_origins(nf, R.data(), rb.data(), pv, nx, S, origin.data(), wait.data());
   for (int t = 0; t < S; t++) check(wait[t] >= -1 && wait[t] < A.T, "wait names a previous tile", seed);
+  int q = -1;  // every ring at the same fraction q / kRingOrigins
   for (int f = 0; f < nf; f++) {
     if (!R[f]) continue;
     check(origin[f] < R[f] && origin[f] % (R[f] / kRingOrigins) == 0, "origin is one of the candidates", seed);
+    const int qf = (int)(origin[f] / (R[f] / kRingOrigins));
+    check(q < 0 || qf == q, "one origin fraction for every ring", seed);
+    q = qf;
     const uint64_t units = R[f] / 8, per_row = rb[f] / 8;
     auto cell = [&](int64_t r, uint64_t k, uint64_t o) { return ((uint64_t)r * rb[f] + o) / 8 % units + k; };
     for (int t = 0; t < S && t < B.T; t++) {

@@ -53,6 +53,9 @@ def test_ns3d_tiled_matches_oracle():
     # one step per chain on rings with Prefetch: each chain's first tiles
     # start before the previous chain's last downloads (rotated ring origins)
     (4, 1, 2, ooc.FLAG_RING | ooc.FLAG_PREFETCH | ooc.FLAG_DEBUG_POISON), (2, 1, 3, ooc.FLAG_RING | ooc.FLAG_PREFETCH),
+    # downloads by runtime copies (copy engines) instead of the copy kernel
+    (6, 2, 2, ooc.FLAG_RING | ooc.FLAG_PREFETCH | ooc.FLAG_DMA_DOWNLOAD),
+    (5, 3, 3, ooc.FLAG_PREFETCH | ooc.FLAG_DMA_DOWNLOAD),
     pytest.param(4, 1, 3, ooc.FLAG_FUSE | ooc.FLAG_GRAPH, marks=GRAPH_OFF)])
 def test_ns3d_tiled_equals_incore(tile_rows, chain_steps, slots, flags):
     n, steps = 20, 3
@@ -135,8 +138,9 @@ def test_ns3d_fused_two_block_columns_match_oracle():
         assert np.array_equal(got[q], ref[q]), q
 
 
-@pytest.mark.parametrize("k,ring", [(6, False), (2, False), (2, True)])
-def test_ns3d_fp32_streaming_matches_oracle_with_the_same_roundings(k, ring):
+@pytest.mark.parametrize("k,ring,dl", [(6, False, 0), (2, False, 0), (2, True, 0), (2, True, ooc.FLAG_DMA_DOWNLOAD),
+                                       (6, False, ooc.FLAG_DMA_DOWNLOAD)])
+def test_ns3d_fp32_streaming_matches_oracle_with_the_same_roundings(k, ring, dl):
     # Extension: the streamed fields are stored on the host and moved as
     # float32; compute stays float64 on the device.  The initial primitives
     # are rounded once on the way in, and every chain of k steps rounds the
@@ -144,11 +148,12 @@ def test_ns3d_fp32_streaming_matches_oracle_with_the_same_roundings(k, ring):
     # float64 oracle doing the same roundings gives the same values.  With
     # k = 6 the chain's kernels move more than 60x its link bytes and the
     # download kernel keeps 8-byte host stores; with k = 2 it uses 16-byte
-    # stores.
+    # stores; with runtime-copy downloads the rows are rounded into a staging
+    # area first.
     n, steps = 24, 6
-    say("case: ns3d fp32 streaming, chains of", k)
+    say("case: ns3d fp32 streaming, chains of", k, "ring", ring, "runtime-copy downloads", bool(dl))
     prims = tgv_initial_state(n)
-    flags = ooc.FLAG_FP32_STREAM | ooc.FLAG_PREFETCH | (ooc.FLAG_RING if ring else 0)
+    flags = ooc.FLAG_FP32_STREAM | ooc.FLAG_PREFETCH | (ooc.FLAG_RING if ring else 0) | dl
     got, st = gpu_ns(n, steps, tile_rows=6, chain_steps=k, slots=2, flags=flags, prims=prims)
     assert st["ntiles_last"] >= 3
     if k == 6:

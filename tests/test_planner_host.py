@@ -239,6 +239,18 @@ def test_library_exports_every_declared_symbol():
     assert set(ooc.EXPORTS) == names
 
 
+def test_binding_constants_match_the_header():
+    # every OOC_FLAG_ / OOC_E_ constant the header defines has the same value
+    # in the Python binding
+    import re
+    import os
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "ooc.h")).read()
+    consts = dict((n, int(v)) for n, v in re.findall(r"\bOOC_((?:FLAG|E)_\w+)\s*=\s*(-?\d+)", hdr))
+    assert len([n for n in consts if n.startswith("FLAG_")]) >= 12
+    for n, v in consts.items():
+        assert getattr(ooc, n) == v, n
+
+
 def test_single_hip_runtime_in_process():
     import re
     ooc.load_library()
