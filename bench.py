@@ -200,20 +200,21 @@ class NS3DWork(Workload):
 
     def variants(self):
         from paper_1709_02125_amd import ooc
-        dl = ooc.FLAG_DMA_DOWNLOAD if self.args.download == "dma" else 0
+        dl = ooc.FLAG_MEMCPY_DOWNLOAD if self.args.download == "memcpy" else 0
         pf = ooc.FLAG_PREFETCH | dl
         ring = 0 if self.args.slots_mode else ooc.FLAG_RING
         # the paper's slots with edge copies, with Prefetch and Cyclic, then
         # its two ablations; the ring-slab headline's other chain lengths and
         # its downloads by copy kernel; float32 streaming of the same schedule
-        k3 = {"chain_steps": 3}  # the longest chain whose skew slots can hold at this budget
-        return [("slots_edge_copies_chains_of_3", pf, k3), ("slots_no_prefetch_cyclic_chains_of_3", dl, k3),
-                ("slots_no_prefetch_no_cyclic_chains_of_3", dl, {"cyclic": False, **k3}),
+        k3 = {"chain_steps": 3}
+        s2k3 = {"slots": 2, **k3}  # the longest chain whose skew slots can hold at this budget
+        return [("slots_edge_copies_chains_of_3", pf, s2k3), ("slots_no_prefetch_cyclic_chains_of_3", dl, s2k3),
+                ("slots_no_prefetch_no_cyclic_chains_of_3", dl, {"cyclic": False, **s2k3}),
                 ("chains_of_1_step", pf | ring, {"chain_steps": 1}),
                 ("chains_of_2_steps", pf | ring, {"chain_steps": 2}),
                 ("chains_of_3_steps", pf | ring, k3),
                 ("copy_kernel_downloads", (pf & ~dl) | ring, {}) if dl else
-                ("runtime_copy_downloads", pf | ring | ooc.FLAG_DMA_DOWNLOAD, {}),
+                ("runtime_copy_downloads", pf | ring | ooc.FLAG_MEMCPY_DOWNLOAD, {}),
                 ("fp32_stream", pf | ring | ooc.FLAG_FP32_STREAM, {})]
 
     def warmup_steps(self, warmup, steps):
@@ -577,7 +578,7 @@ def c5_main(args):
         ring = 0 if args.slots_mode else ooc.FLAG_RING
         budget = int(args.budget) if args.budget else N.footprint_bytes(n, fused) // 3
         cands = tune.grid([8, 16, 24, 32, 48, 0], [1, 2, 3, 4], [2, 3, 4])
-        dl = ooc.FLAG_DMA_DOWNLOAD  # the chain is bound by its kernels
+        dl = ooc.FLAG_MEMCPY_DOWNLOAD  # the chain is bound by its kernels
         workload = lambda fl: tune.ns3d_workload(n, budget, fl | ring | dl, fused=fused)
         cells = n ** 3
         names = N.Q
@@ -743,14 +744,14 @@ def main():
     ap.add_argument("--fp32", action="store_true", help="store and stream fields as float32 on the host")
     ap.add_argument("--no-prefetch", action="store_true")
     ap.add_argument("--kernel-copy", action="store_true", help="host-link transfers by copy kernel")
-    ap.add_argument("--download", choices=["kernel", "dma"], default=None,
-                    help="downloads by copy kernel or by runtime copies (copy engines); default: runtime "
-                         "copies for ns3d (kernel-bound chains), copy kernel for the hydro proxies")
+    ap.add_argument("--download", choices=["kernel", "memcpy"], default=None,
+                    help="downloads by the library's copy kernel or by runtime memcpy calls; default: memcpy "
+                         "for ns3d (kernel-bound chains), the copy kernel for the hydro proxies")
     ap.add_argument("--fuse", action="store_true", help="fuse independent strip loops per tile")
     ap.add_argument("--no-cyclic", action="store_true")
     ap.add_argument("--no-incore", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--slots", type=int, default=None, help="slot count (default 3; ns3d: 2)")
+    ap.add_argument("--slots", type=int, default=None, help="slot count (default 3; ns3d with stored gradients: 2)")
     ap.add_argument("--tile-rows", type=int, default=None, help="tile height (default: largest that fits; ns3d: 24)")
     ap.add_argument("--chain-steps", type=int, default=4, help="ns3d: time steps per chain")
     ap.add_argument("--slots-mode", action="store_true",
@@ -785,14 +786,15 @@ def main():
     if args.steps is None:  # ns3d: two whole chains
         args.steps = {"hydro2d": 20, "hydro3d": 10, "ns3d": 2 * args.chain_steps}[args.workload]
     # ns3d runs on ring slabs with chains of 4 steps, the largest tile that
-    # fits and 2 slots: the fastest of the exhaustive sweep of this grid and
-    # budget (tile heights 8 .. largest, chains of 1 .. 4 steps, 2 .. 4 slots;
-    # chains of 3 steps 10 % slower).  With stored gradients and slots the
-    # round-one sweep found 24-plane tiles, chains of 3 steps, 2 slots.  The
-    # hydro proxies default to the largest tile and 3 slots.
+    # fits and 3 slots: within 1 % of the fastest of the exhaustive sweep of
+    # this grid and budget (tile heights 8 .. largest, chains of 1 .. 4
+    # steps, 2 .. 4 slots; 2 slots 4 % slower, chains of 3 steps 2-5 %
+    # slower).  With stored gradients on slots, 24-plane tiles, chains of 3
+    # steps and 2 slots were the fastest.  The hydro proxies default to the
+    # largest tile and 3 slots.
     ns = args.workload == "ns3d"
     if args.slots is None:
-        args.slots = 2 if ns else 0
+        args.slots = 3 if ns and not args.stored_gradients else (2 if ns else 0)
     if args.tile_rows is None:
         args.tile_rows = 24 if ns and args.stored_gradients else 0
 
@@ -810,9 +812,9 @@ def main():
     if args.kernel_copy:
         flags |= ooc.FLAG_KERNEL_COPY
     if args.download is None:  # runtime copies where the stencils bound the chain
-        args.download = "dma" if ns else "kernel"
-    if args.download == "dma":
-        flags |= ooc.FLAG_DMA_DOWNLOAD
+        args.download = "memcpy" if ns else "kernel"
+    if args.download == "memcpy":
+        flags |= ooc.FLAG_MEMCPY_DOWNLOAD
     if args.fuse:
         flags |= ooc.FLAG_FUSE
     t = time.perf_counter()

@@ -83,7 +83,7 @@ enum {
                                  (one launch per tile; FP32 converted in flight) instead of runtime
                                  memcpy calls.  Downloads go by copy kernel when the host arrays
                                  are device-mapped (pinned by ooc_bind_device), unless
-                                 OOC_FLAG_DMA_DOWNLOAD is set */
+                                 OOC_FLAG_MEMCPY_DOWNLOAD is set */
   OOC_FLAG_RING = 1024,       /* ring slabs instead of slots: each streamed field lives in one ring
                                  of device memory mapped twice at consecutive virtual addresses
                                  (HIP virtual memory API), so the rows two tiles share stay in
@@ -96,13 +96,13 @@ enum {
                                  only for the downloads of the previous chain's tiles whose ring
                                  positions they take.  Fixed at creation; OOC_E_ARG at the first
                                  flush if the device lacks the API. */
-  OOC_FLAG_DMA_DOWNLOAD = 2048 /* downloads by runtime memcpy calls (the copy engines; FP32 rounded
-                                 into a staging area first) instead of the copy kernel, also when
-                                 the host arrays are device-mapped: for chains bound by their
-                                 kernels, which the copy kernel's host stores slow down (ns3d
-                                 512^3 on rings: 60 against 73 ms per step); the copy kernel
-                                 stays faster for chains bound by the link (hydro2d 15360^2).
-                                 Ignored with OOC_FLAG_KERNEL_COPY. */
+  OOC_FLAG_MEMCPY_DOWNLOAD = 2048 /* downloads by runtime memcpy calls (FP32 rounded into a staging
+                                 area first) instead of the copy kernel, also when the host arrays
+                                 are device-mapped: for chains bound by their kernels, which the
+                                 copy kernel's host stores slow down more than the runtime's
+                                 copies do (ns3d 512^3 on rings: 59 against 73 ms per step); the
+                                 copy kernel stays faster for chains bound by the link (hydro2d
+                                 15360^2, hydro3d 640^3).  Ignored with OOC_FLAG_KERNEL_COPY. */
 };
 
 /* per-field flags for ooc_decl_field */

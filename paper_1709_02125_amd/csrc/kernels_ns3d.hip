@@ -303,8 +303,12 @@ __global__ void __launch_bounds__(64 * PH) k_ns_rhs(const KArgs *__restrict__ ap
 // values as in k_ns_grads and k_ns_rhs, so the results are bit-identical to
 // the stored-gradient chain.
 constexpr int kFusedRows = 4;
-// planes of a fused z-segment at least (each re-reads 8 planes of primitives)
-constexpr int kFusedMinSegPlanes = 16;
+// planes of a fused z-segment at least: each segment re-reads 8 planes of
+// primitives, so a tile's short z-range (36 planes at ns3d 512^3 with
+// 4-step chains) runs as one segment (45.7 against 46.8 ms per step for
+// the in-core chain cut into such tiles), while a whole 512-plane grid still
+// splits in two for parallelism
+constexpr int kFusedMinSegPlanes = 64;
 
 // fused-residual argument slots
 enum { FPR = 0, FQR = 5, FDR = 10 };

@@ -1047,12 +1047,13 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
       const size_t nb = (size_t)(r->hi - r->lo) * f.row_bytes_host();
       char *dst = (char *)f.host + r->lo * f.row_bytes_host();
       // Downloads go by copy kernel into the device-mapped host rows unless
-      // the context asks for the copy engines.  On link-bound chains the
+      // the context asks for runtime memcpy calls.  On link-bound chains the
       // kernel keeps the higher rate (hydro2d 15360^2: 240 against 261 ms
-      // per step in FP64, 100 against 173 ms in FP32); on kernel-bound ones
-      // its host stores slow the stencils beside them and the copy engines
-      // win (ns3d 512^3 on rings: 60 against 73 ms per step).
-      if (kcopy || (f.host_dev && !(c->flags & OOC_FLAG_DMA_DOWNLOAD))) {
+      // per step in FP64, 100 against 173 ms in FP32; hydro3d 640^3 FP32:
+      // 172 against 248 ms); on kernel-bound ones its host stores slow the
+      // stencils beside them more than the runtime's copies do (ns3d 512^3
+      // on rings: 59 against 73 ms per step).
+      if (kcopy || (f.host_dev && !(c->flags & OOC_FLAG_MEMCPY_DOWNLOAD))) {
         if (!f.host_dev) throw DeviceError("kernel copy needs device-mapped pinned host arrays");
         char *hdst = (char *)f.host_dev + r->lo * f.row_bytes_host();
         const int64_t elems = (r->hi - r->lo) * f.row_elems;

@@ -21,7 +21,7 @@ FLAG_CYCLIC, FLAG_PREFETCH, FLAG_FP32_STREAM, FLAG_INCORE = 1, 2, 4, 8
 FLAG_GRAPH, FLAG_FUSE, FLAG_DEBUG_POISON, FLAG_DEBUG_SYNC, FLAG_PLAN_ONLY = 16, 32, 64, 128, 256
 FLAG_KERNEL_COPY = 512
 FLAG_RING = 1024
-FLAG_DMA_DOWNLOAD = 2048
+FLAG_MEMCPY_DOWNLOAD = 2048
 FIELD_RESIDENT = 1
 SCRATCH_DOUBLES = 524288  # OOC_MLP_SCRATCH_DOUBLES: static device scratch of ooc_mlp_predict_noalloc
 

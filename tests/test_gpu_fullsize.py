@@ -166,8 +166,9 @@ def ns3d_oracle():
 
 NS_CONFIGS = [
     # the benchmark's headline: 15-field chain (gradients inside the residual)
-    # on ring slabs, largest tiles, chains of 4 steps, 2 slots
-    ("fused residual, ring slabs, largest tiles, 4-step chains, 2 slots", True, ooc.FLAG_RING, (0, 4, 2)),
+    # on ring slabs, memcpy downloads, largest tiles, chains of 4 steps, 3 slots
+    ("fused residual, ring slabs, memcpy downloads, largest tiles, 4-step chains, 3 slots", True,
+     ooc.FLAG_RING | ooc.FLAG_MEMCPY_DOWNLOAD, (0, 4, 3)),
     # its variant with stored gradients on slots with edge copies
     ("stored gradients, slots with edge copies, 24-plane tiles, 3-step chains, 2 slots", False, 0, (24, 3, 2)),
 ]
@@ -209,7 +210,7 @@ def test_ns3d_512_fp32_stream_20_steps_error(ns3d_oracle):
     say("case: ns3d 512^3 FP32 streaming, third-of-footprint budget, ring slabs, 16-plane tiles, 4-step chains, "
         "20 steps")
     app = N.NS3D(n, tgv_initial_state(n), budget=N.footprint_bytes(n, True) // 3,
-                 flags=ooc.FLAG_PREFETCH | ooc.FLAG_FP32_STREAM | ooc.FLAG_RING, fused=True)
+                 flags=ooc.FLAG_PREFETCH | ooc.FLAG_FP32_STREAM | ooc.FLAG_RING | ooc.FLAG_MEMCPY_DOWNLOAD, fused=True)
     app.ctx.set_schedule(tile_rows=16, chain_steps=4, slots=2)
     app.initialise()
     app.run(steps)

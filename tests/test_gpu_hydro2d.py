@@ -47,7 +47,7 @@ def test_hydro2d_c1_config_matches_oracle():
     # ring slabs (no edge copy)
     (5, 2, ooc.FLAG_RING, True), (7, 3, ooc.FLAG_RING | ooc.FLAG_DEBUG_POISON | ooc.FLAG_PREFETCH, True),
     (9, 2, ooc.FLAG_RING | ooc.FLAG_KERNEL_COPY, False), (3, 4, ooc.FLAG_RING | ooc.FLAG_DEBUG_SYNC, True),
-    (7, 3, ooc.FLAG_PREFETCH | ooc.FLAG_DMA_DOWNLOAD, True), (5, 2, ooc.FLAG_RING | ooc.FLAG_DMA_DOWNLOAD, True)])
+    (7, 3, ooc.FLAG_PREFETCH | ooc.FLAG_MEMCPY_DOWNLOAD, True), (5, 2, ooc.FLAG_RING | ooc.FLAG_MEMCPY_DOWNLOAD, True)])
 def test_hydro2d_tiled_equals_untiled_bit_exact(tile_rows, slots, flags, cyclic):
     nx, ny, steps = 40, 51, 5  # several chains: graph mode replays its capture
     say("case: tiled vs in-core", tile_rows, slots, flags, cyclic)
@@ -180,9 +180,9 @@ def test_hydro2d_fp32_streaming_error_is_stated_and_tiling_independent():
                         tile_rows=7, budget=h2.device_footprint_bytes(nx, ny))
     for n in STATE:   # conversion in the copy kernel == staging + convert kernels
         assert np.array_equal(a[n], c[n]), n
-    g, _, _ = gpu_hydro(nx, ny, steps, flags=flags | ooc.FLAG_DMA_DOWNLOAD, resident_geometry=True,
+    g, _, _ = gpu_hydro(nx, ny, steps, flags=flags | ooc.FLAG_MEMCPY_DOWNLOAD, resident_geometry=True,
                         tile_rows=6, budget=h2.device_footprint_bytes(nx, ny))
-    for n in STATE:   # downloads rounded in staging and sent by the copy engines
+    for n in STATE:   # downloads rounded in staging and sent by runtime memcpy calls
         assert np.array_equal(a[n], g[n]), n
     ref, odts = oracle_hydro(nx, ny, steps)
     errs = {n: rel_err(a[n], ref[n]) for n in STATE}

@@ -53,9 +53,9 @@ def test_ns3d_tiled_matches_oracle():
     # one step per chain on rings with Prefetch: each chain's first tiles
     # start before the previous chain's last downloads (rotated ring origins)
     (4, 1, 2, ooc.FLAG_RING | ooc.FLAG_PREFETCH | ooc.FLAG_DEBUG_POISON), (2, 1, 3, ooc.FLAG_RING | ooc.FLAG_PREFETCH),
-    # downloads by runtime copies (copy engines) instead of the copy kernel
-    (6, 2, 2, ooc.FLAG_RING | ooc.FLAG_PREFETCH | ooc.FLAG_DMA_DOWNLOAD),
-    (5, 3, 3, ooc.FLAG_PREFETCH | ooc.FLAG_DMA_DOWNLOAD),
+    # downloads by runtime memcpy calls instead of the copy kernel
+    (6, 2, 2, ooc.FLAG_RING | ooc.FLAG_PREFETCH | ooc.FLAG_MEMCPY_DOWNLOAD),
+    (5, 3, 3, ooc.FLAG_PREFETCH | ooc.FLAG_MEMCPY_DOWNLOAD),
     pytest.param(4, 1, 3, ooc.FLAG_FUSE | ooc.FLAG_GRAPH, marks=GRAPH_OFF)])
 def test_ns3d_tiled_equals_incore(tile_rows, chain_steps, slots, flags):
     n, steps = 20, 3
@@ -138,8 +138,8 @@ def test_ns3d_fused_two_block_columns_match_oracle():
         assert np.array_equal(got[q], ref[q]), q
 
 
-@pytest.mark.parametrize("k,ring,dl", [(6, False, 0), (2, False, 0), (2, True, 0), (2, True, ooc.FLAG_DMA_DOWNLOAD),
-                                       (6, False, ooc.FLAG_DMA_DOWNLOAD)])
+@pytest.mark.parametrize("k,ring,dl", [(6, False, 0), (2, False, 0), (2, True, 0), (2, True, ooc.FLAG_MEMCPY_DOWNLOAD),
+                                       (6, False, ooc.FLAG_MEMCPY_DOWNLOAD)])
 def test_ns3d_fp32_streaming_matches_oracle_with_the_same_roundings(k, ring, dl):
     # Extension: the streamed fields are stored on the host and moved as
     # float32; compute stays float64 on the device.  The initial primitives
