@@ -35,7 +35,8 @@ H2D_NAMES = ["h2d_eos", "h2d_eos_p", "h2d_visc", "h2d_pdv_pred", "h2d_pdv_corr",
 H3D_NAMES = ["h3d_visc", "h3d_pdv_pred", "h3d_pdv_corr", "h3d_accel"] + \
             ["h3d_%s_%s" % (k, a) for k in ("flux", "adv_vol", "adv_flux", "adv_cell", "nflux", "nmass",
                                             "mflux", "vel") for a in "xyz"] + ["h3d_dt"]
-NS_NAMES = ["ns_init", "ns_prims", "ns_grads", "ns_rhs_first", "ns_rhs", "ns_rhs_fused_first", "ns_rhs_fused"]
+NS_NAMES = ["ns_init", "ns_prims", "ns_grads", "ns_rhs_first", "ns_rhs", "ns_rhs_fused_first", "ns_rhs_fused",
+            "ns_rhs_fusedq_first", "ns_rhs_fusedq"]
 COMMON = {1: "mirror", 2: "fill", 3: "sum_prod"}
 
 
@@ -176,7 +177,7 @@ class NS3DWork(Workload):
         from paper_1709_02125_amd import ns3d as N
         from paper_1709_02125_amd.inputs import tgv_initial_state
         self.mod = N
-        self.fused = not args.stored_gradients
+        self.fused = "q" if args.prims_in_residual else not args.stored_gradients
         self.n = args.n or 512
         self.cells = self.n ** 3
         self.footprint = N.footprint_bytes(self.n, self.fused)
@@ -184,7 +185,8 @@ class NS3DWork(Workload):
         log("generating input %d^3" % self.n)
         self.prims = tgv_initial_state(self.n)
         self.knames = {**COMMON, **{200 + i: s for i, s in enumerate(NS_NAMES)}}
-        self.dominant = 200 + NS_NAMES.index("ns_rhs_fused" if self.fused else "ns_rhs")
+        self.dominant = 200 + NS_NAMES.index({"q": "ns_rhs_fusedq", True: "ns_rhs_fused",
+                                              False: "ns_rhs"}[self.fused])
 
     def make(self, budget, flags, incore=False, **opts):
         N = self.mod
@@ -226,8 +228,10 @@ class NS3DWork(Workload):
         return -(-max(warmup, k) // k) * k + steps % k
 
     def describe(self):
-        form = ("15 fields (gradients evaluated in the residual kernel), 42 loops per step" if self.fused else
-                "27 fields (12 stored gradients), 45 loops per step")
+        form = {"q": "15 fields (two copies of the conserved variables; primitives and gradients evaluated in "
+                     "the residual kernel), 39 loops per step",
+                True: "15 fields (gradients evaluated in the residual kernel), 42 loops per step",
+                False: "27 fields (12 stored gradients), 45 loops per step"}[self.fused]
         return ("ns3d proxy %d^3 FP64 (Taylor-Green, Mach 0.1), %s, chains of %d "
                 "steps, device budget %.3g B (footprint %.3g B, %.2fx oversubscribed), tiles along z" %
                 (self.n, form, self.args.chain_steps, self.budget, self.footprint, self.footprint / self.budget))
@@ -574,10 +578,12 @@ def c5_main(args):
         from paper_1709_02125_amd import ns3d as N
         from paper_1709_02125_amd.inputs import tgv_initial_state
         n = args.n or 512
-        fused = not args.stored_gradients
+        fused = "q" if args.prims_in_residual else not args.stored_gradients
         ring = 0 if args.slots_mode else ooc.FLAG_RING
         budget = int(args.budget) if args.budget else N.footprint_bytes(n, fused) // 3
-        cands = tune.grid([8, 16, 24, 32, 48, 0], [1, 2, 3, 4], [2, 3, 4])
+        # with two copies of the conserved variables a chain spans an even
+        # number of steps (the state returns to the copy it started in)
+        cands = tune.grid([8, 16, 24, 32, 48, 0], [2, 4] if fused == "q" else [1, 2, 3, 4], [2, 3, 4])
         dl = ooc.FLAG_MEMCPY_DOWNLOAD  # the chain is bound by its kernels
         workload = lambda fl: tune.ns3d_workload(n, budget, fl | ring | dl, fused=fused)
         cells = n ** 3
@@ -760,6 +766,9 @@ def main():
     ap.add_argument("--ring", action="store_true", help="hydro proxies: ring slabs instead of slots")
     ap.add_argument("--cache-tiling", type=int, nargs="*", default=None,
                     help="also time the in-core run cut into tiles of these heights (cache blocking, no transfers)")
+    ap.add_argument("--prims-in-residual", action="store_true",
+                    help="ns3d: the residual kernel evaluates the primitives too (two copies of the conserved "
+                         "variables instead of the primitive fields; chains of an even number of steps)")
     ap.add_argument("--stored-gradients", action="store_true",
                     help="ns3d: the 27-field chain with a gradient loop and stored gradients (default: the "
                          "15-field chain whose residual evaluates the gradients itself)")

@@ -98,6 +98,13 @@ enum {
    * the 5-point stencils, each from the 5-point stencils of the primitives). */
   OOC_K_NS_RHS_FUSED_FIRST = 205,
   OOC_K_NS_RHS_FUSED = 206,
+  /* The same with the primitives evaluated from the conserved variables
+   * inside the kernel too (no primitives loop, no primitive fields), reading
+   * one copy of the conserved variables and writing the other:
+   * R q x5 G, W q' x5, W dq x5 (first stage) or RW dq x5; the same CONSTs:
+   * dq = A_s dq + dt R(q); q' = q + B_s dq. */
+  OOC_K_NS_RHS_FUSEDQ_FIRST = 207,
+  OOC_K_NS_RHS_FUSEDQ = 208,
 
   /* ---- 3D hydro proxy (tiled along z).  "8n" = the 8 nodes of a cell
    * {0,1}^3; "8c" = the 8 cells of a node {-1,0}^3; "F4x" = the 4 nodes of a

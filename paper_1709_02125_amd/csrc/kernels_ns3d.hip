@@ -310,15 +310,46 @@ constexpr int kFusedRows = 4;
 // splits in two for parallelism
 constexpr int kFusedMinSegPlanes = 64;
 
-// fused-residual argument slots
+// fused-residual argument slots: the stencil input (primitives, or with kQ
+// the conserved variables), the conserved variables updated (with kQ: the
+// other copy, written), the Runge-Kutta increments
 enum { FPR = 0, FQR = 5, FDR = 10 };
 
+// rho, u, v, w, p at storage offset o: the primitive fields, or (kQ) the
+// same expressions of the conserved variables as k_ns_prims
+template <bool kQ>
+__device__ __forceinline__ void ns_prim5(const KArgs &a, int64_t o, double v[5]) {
+  if (kQ) {
+    const double r = gp(a.p[FPR])[o], ru = gp(a.p[FPR + 1])[o], rv = gp(a.p[FPR + 2])[o];
+    const double rw = gp(a.p[FPR + 3])[o], e = gp(a.p[FPR + 4])[o];
+    const double u = ru / r, vv = rv / r, w = rw / r;
+    v[0] = r;
+    v[1] = u;
+    v[2] = vv;
+    v[3] = w;
+    v[4] = kGm1 * (e - 0.5 * ((ru * u + rv * vv) + rw * w));
+  } else {
+#pragma unroll
+    for (int f = 0; f < 5; f++) v[f] = gp(a.p[FPR + f])[o];
+  }
+}
+
 // u, v, w, T of the primitives at storage offset o
+template <bool kQ>
 __device__ __forceinline__ void ns_uvwt(const KArgs &a, int64_t o, double gm2, double out[4]) {
-  out[0] = gp(a.p[FPR + 1])[o];
-  out[1] = gp(a.p[FPR + 2])[o];
-  out[2] = gp(a.p[FPR + 3])[o];
-  out[3] = (gm2 * gp(a.p[FPR + 4])[o]) / gp(a.p[FPR])[o];
+  if (kQ) {
+    double v[5];
+    ns_prim5<true>(a, o, v);
+    out[0] = v[1];
+    out[1] = v[2];
+    out[2] = v[3];
+    out[3] = (gm2 * v[4]) / v[0];
+  } else {
+    out[0] = gp(a.p[FPR + 1])[o];
+    out[1] = gp(a.p[FPR + 2])[o];
+    out[2] = gp(a.p[FPR + 3])[o];
+    out[3] = (gm2 * gp(a.p[FPR + 4])[o]) / gp(a.p[FPR])[o];
+  }
 }
 
 // the 17 flux inputs at one point from its rho, p, the staged plane (row
@@ -342,7 +373,7 @@ __device__ __forceinline__ void ns_inputs(const double (&sv)[4][R][C], int sy, i
   v[GTX + 2] = deriv(zc[0][3], zc[1][3], zc[3][3], zc[4][3], inv);
 }
 
-template <bool kFirst, int PH>
+template <bool kFirst, int PH, bool kQ>
 __global__ void __launch_bounds__(64 * PH) k_ns_rhs_fused(const KArgs *__restrict__ ap) {
   ARGS
   // u, v, w, T at plane c: rows y = j0-4 .. j0+PH+3, columns x = i0-4 .. i0+67
@@ -383,6 +414,9 @@ __global__ void __launch_bounds__(64 * PH) k_ns_rhs_fused(const KArgs *__restric
   const int64_t col_ld = own_ld ? col : (int64_t)(j < yh ? j : yh - 1) * a.pitch + (i < xl ? xl : (i < xh ? i : xh - 1));
   const int hyc = hy < yl ? yl : (hy < yh ? hy : yh - 1);
   const int64_t ycol_ld = yh_ld ? ycol : (int64_t)hyc * a.pitch + (i < xl ? xl : (i < xh ? i : xh - 1));
+  // raw loads: u, v, w into z[0..2], rho, p into r[0..1] (kQ: rho u, rho v,
+  // rho w and rho, E); form_t then completes the point after the loads have
+  // arrived (kQ: the primitives first, as k_ns_prims evaluates them)
   auto load_raw = [&](int64_t o, double z[4], double r[2]) {
     z[0] = gp(a.p[FPR + 1])[o];
     z[1] = gp(a.p[FPR + 2])[o];
@@ -390,7 +424,16 @@ __global__ void __launch_bounds__(64 * PH) k_ns_rhs_fused(const KArgs *__restric
     r[0] = gp(a.p[FPR])[o];
     r[1] = gp(a.p[FPR + 4])[o];
   };
-  auto form_t = [&](double z[4], const double r[2]) { z[3] = (gm2 * r[1]) / r[0]; };
+  auto form_t = [&](double z[4], double r[2]) {
+    if (kQ) {
+      const double ru = z[0], rv = z[1], rw = z[2];
+      z[0] = ru / r[0];
+      z[1] = rv / r[0];
+      z[2] = rw / r[0];
+      r[1] = kGm1 * (r[1] - 0.5 * ((ru * z[0] + rv * z[1]) + rw * z[2]));
+    }
+    z[3] = (gm2 * r[1]) / r[0];
+  };
 #pragma unroll
   for (int q = 0; q < 4; q++) {  // planes kb-4 .. kb-1
     const int64_t pq = (int64_t)(kb - 4 + q) * a.plane;
@@ -415,16 +458,9 @@ __global__ void __launch_bounds__(64 * PH) k_ns_rhs_fused(const KArgs *__restric
     // the staging waits only for the former, the rings' loads complete
     // behind it and are used after the barrier
     double ov[4], hxv[4], hv[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, zc[5][4];
-    if (oy_ld) ns_uvwt(a, pc + ocol, gm2, ov);
-    if (hxy_ld) ns_uvwt(a, pc + hcol, gm2, hxv);
-    if (ox_ld) {
-      const int64_t o = pc + xcol;
-      hv[0] = gp(a.p[FPR])[o];
-      hv[1] = gp(a.p[FPR + 1])[o];
-      hv[2] = gp(a.p[FPR + 2])[o];
-      hv[3] = gp(a.p[FPR + 3])[o];
-      hv[4] = gp(a.p[FPR + 4])[o];
-    }
+    if (oy_ld) ns_uvwt<kQ>(a, pc + ocol, gm2, ov);
+    if (hxy_ld) ns_uvwt<kQ>(a, pc + hcol, gm2, hxv);
+    if (ox_ld) ns_prim5<kQ>(a, pc + xcol, hv);
     load_raw(pc + 2 * a.plane + col_ld, za[4], ra[2]);
     load_raw(pc + 2 * a.plane + ycol_ld, zb[4], rb[2]);
     // ---- stage plane c
@@ -473,7 +509,7 @@ __global__ void __launch_bounds__(64 * PH) k_ns_rhs_fused(const KArgs *__restric
       if (xh_flux) {
 #pragma unroll
         for (int q = 0; q < 5; q++)
-          if (q != 2) ns_uvwt(a, pc + (int64_t)(q - 2) * a.plane + xcol, gm2, zc[q]);
+          if (q != 2) ns_uvwt<kQ>(a, pc + (int64_t)(q - 2) * a.plane + xcol, gm2, zc[q]);
         zc[2][0] = hv[1];
         zc[2][1] = hv[2];
         zc[2][2] = hv[3];
@@ -503,7 +539,7 @@ __global__ void __launch_bounds__(64 * PH) k_ns_rhs_fused(const KArgs *__restric
         const double res = rxy[0][q] - deriv(fz[0][q], fz[1][q], fz[3][q], fz[4][q], inv);
         const double d = kFirst ? dt * res : A * gp(a.p[FDR + q])[o] + dt * res;
         gp(a.p[FDR + q])[o] = d;
-        gp(a.p[FQR + q])[o] = gp(a.p[FQR + q])[o] + B * d;
+        gp(a.p[FQR + q])[o] = gp(a.p[kQ ? FPR + q : FQR + q])[o] + B * d;
       }
     }
 #pragma unroll
@@ -556,10 +592,16 @@ void l_rhs(const KArgs &a, const KArgs *d, int nd, void *s) {
   launch_zmarch<kRhsRows>(k_ns_rhs<false, kRhsRows>, a, d, nd, s);
 }
 void l_rhs_fused_first(const KArgs &a, const KArgs *d, int nd, void *s) {
-  launch_zmarch_seg<kFusedRows, kFusedMinSegPlanes>(k_ns_rhs_fused<true, kFusedRows>, a, d, nd, s);
+  launch_zmarch_seg<kFusedRows, kFusedMinSegPlanes>(k_ns_rhs_fused<true, kFusedRows, false>, a, d, nd, s);
 }
 void l_rhs_fused(const KArgs &a, const KArgs *d, int nd, void *s) {
-  launch_zmarch_seg<kFusedRows, kFusedMinSegPlanes>(k_ns_rhs_fused<false, kFusedRows>, a, d, nd, s);
+  launch_zmarch_seg<kFusedRows, kFusedMinSegPlanes>(k_ns_rhs_fused<false, kFusedRows, false>, a, d, nd, s);
+}
+void l_rhs_fusedq_first(const KArgs &a, const KArgs *d, int nd, void *s) {
+  launch_zmarch_seg<kFusedRows, kFusedMinSegPlanes>(k_ns_rhs_fused<true, kFusedRows, true>, a, d, nd, s);
+}
+void l_rhs_fusedq(const KArgs &a, const KArgs *d, int nd, void *s) {
+  launch_zmarch_seg<kFusedRows, kFusedMinSegPlanes>(k_ns_rhs_fused<false, kFusedRows, true>, a, d, nd, s);
 }
 #undef L
 
@@ -573,6 +615,8 @@ void register_ns3d_kernels(KernelInfo *t) {
   t[OOC_K_NS_RHS] = {"ns_rhs", 27, 27, 6, 0, 0, kPointGrid, l_rhs};
   t[OOC_K_NS_RHS_FUSED_FIRST] = {"ns_rhs_fused_first", 15, 15, 7, 0, 0, kPointGrid, l_rhs_fused_first};
   t[OOC_K_NS_RHS_FUSED] = {"ns_rhs_fused", 15, 15, 7, 0, 0, kPointGrid, l_rhs_fused};
+  t[OOC_K_NS_RHS_FUSEDQ_FIRST] = {"ns_rhs_fusedq_first", 15, 15, 7, 0, 0, kPointGrid, l_rhs_fusedq_first};
+  t[OOC_K_NS_RHS_FUSEDQ] = {"ns_rhs_fusedq", 15, 15, 7, 0, 0, kPointGrid, l_rhs_fusedq};
 }
 
 }  // namespace ooc

@@ -19,7 +19,8 @@ def test_more_than_one_gpu_is_refused():
 @pytest.mark.parametrize("name,n", [("hydro2d", 64), ("hydro3d", 16), ("ns3d", 16)])
 def test_workloads_build_on_host(name, n):
     args = types.SimpleNamespace(n=n, budget=0, resident_geometry=False, resident_state=False, no_cyclic=False, chain_steps=3,
-                                 tile_rows=0, slots=0, stored_gradients=False)
+                                 tile_rows=0, slots=0, stored_gradients=False,
+                                 prims_in_residual=False)
     w = bench.WORKLOADS[name](args)
     assert w.cells > 0 and w.footprint > 0 and w.budget > 0
     assert name in w.describe()

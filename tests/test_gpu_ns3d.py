@@ -118,6 +118,62 @@ def test_ns3d_fused_residual_equals_stored_gradients(tile_rows, chain_steps, slo
         assert np.array_equal(got[q], ref[q]), q
 
 
+@pytest.mark.parametrize("tile_rows,chain_steps,slots,flags", [
+    (4, 2, 3, 0), (3, 2, 2, ooc.FLAG_PREFETCH), (7, 2, 4, ooc.FLAG_FUSE),
+    (5, 4, 3, ooc.FLAG_RING | ooc.FLAG_PREFETCH | ooc.FLAG_MEMCPY_DOWNLOAD),
+    (4, 2, 2, ooc.FLAG_RING | ooc.FLAG_DEBUG_POISON), (6, 4, 3, ooc.FLAG_RING | ooc.FLAG_PREFETCH)])
+def test_ns3d_conserved_input_residual_equals_fused(tile_rows, chain_steps, slots, flags):
+    # The residual that evaluates the primitives as well (one copy of the
+    # conserved variables in, the other out; no primitive fields or loop in
+    # the chain) against the fused form with stored primitives: bit for bit,
+    # in core (also after an odd number of steps, the state then in the other
+    # copy) and tiled over several schedules with chains of even length
+    n = 20
+    say("case: ns3d conserved-input residual vs fused", tile_rows, chain_steps, slots, flags)
+    for steps in (3, 4):
+        ref, _ = gpu_ns(n, steps, incore=True, fused=True)
+        inc, _ = gpu_ns(n, steps, incore=True, fused="q")
+        for q in N.Q:
+            assert np.array_equal(inc[q], ref[q]), (steps, q)
+    got, st = gpu_ns(n, 4, tile_rows=tile_rows, chain_steps=chain_steps, slots=slots, flags=flags,
+                     budget=16 * N.device_footprint_bytes(n, "q"), fused="q")
+    assert st["ntiles_last"] >= 3
+    for q in N.Q:
+        assert np.array_equal(got[q], ref[q]), q
+
+
+def test_ns3d_conserved_input_odd_chains_under_cyclic_are_refused():
+    # With Cyclic, a chain of an odd number of steps leaves the state in the
+    # copy its first stage writes, which Cyclic takes for a temporary and does
+    # not download: the library refuses to read that field afterwards
+    say("case: ns3d conserved-input residual, odd chain under Cyclic")
+    n = 20
+    app = N.NS3D(n, tgv_initial_state(n), budget=8 * N.device_footprint_bytes(n, "q"), fused="q")
+    try:
+        app.ctx.set_schedule(tile_rows=5, chain_steps=1)
+        app.initialise()
+        with pytest.raises(ooc.OocError) as e:
+            app.run(3)
+        assert e.value.code == ooc.E_STALE
+    finally:
+        app.close()
+
+
+def test_ns3d_conserved_input_two_block_columns_match_oracle():
+    n, steps = 72, 2
+    say("case: ns3d 72^3 conserved-input residual, tiled vs oracle")
+    got, st = gpu_ns(n, steps, tile_rows=9, chain_steps=2, fused="q", flags=ooc.FLAG_RING | ooc.FLAG_PREFETCH)
+    assert st["ntiles_last"] >= 4
+    o = on.NS3D(n)
+    o.set_primitives(*tgv_initial_state(n))
+    for _ in range(steps):
+        o.step(on.stable_dt(n))
+    for q in N.Q:
+        e = rel_err(got[q], o.interior(q))
+        say(q, e)
+        assert e <= TOL, q
+
+
 def test_ns3d_fused_two_block_columns_match_oracle():
     # x over two 64-wide block columns with a ragged tail, tiled with 2-step
     # chains: the fused residual against the oracle and, bit for bit, against
