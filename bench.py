@@ -171,13 +171,23 @@ class Hydro3DWork(Workload):
         return cpu_hydro3d(self.n, target_s, one_thread)
 
 
+def ns_form(args):
+    """The ns3d chain form: "q" (the default: two copies of the conserved
+    variables, primitives and gradients evaluated in the residual kernel),
+    True (stored primitives, gradients in the residual) or False (stored
+    primitives and gradients)."""
+    if getattr(args, "stored_gradients", False):
+        return False
+    return True if getattr(args, "stored_primitives", False) else "q"
+
+
 class NS3DWork(Workload):
     def __init__(self, args):
         super().__init__(args)
         from paper_1709_02125_amd import ns3d as N
         from paper_1709_02125_amd.inputs import tgv_initial_state
         self.mod = N
-        self.fused = "q" if args.prims_in_residual else not args.stored_gradients
+        self.fused = ns_form(args)
         self.n = args.n or 512
         self.cells = self.n ** 3
         self.footprint = N.footprint_bytes(self.n, self.fused)
@@ -190,10 +200,11 @@ class NS3DWork(Workload):
 
     def make(self, budget, flags, incore=False, **opts):
         N = self.mod
+        fused = opts.get("fused", self.fused)
         if incore:
-            return N.NS3D(self.n, self.prims, budget=N.device_footprint_bytes(self.n, self.fused), flags=flags,
-                          fused=self.fused)
-        app = N.NS3D(self.n, self.prims, budget=budget, flags=flags, fused=self.fused,
+            return N.NS3D(self.n, self.prims, budget=N.device_footprint_bytes(self.n, fused), flags=flags,
+                          fused=fused)
+        app = N.NS3D(self.n, self.prims, budget=budget, flags=flags, fused=fused,
                      cyclic_after_init=opts.get("cyclic", not self.args.no_cyclic))
         app.ctx.set_schedule(tile_rows=opts.get("tile_rows", self.args.tile_rows),
                              chain_steps=opts.get("chain_steps", self.args.chain_steps),
@@ -207,17 +218,26 @@ class NS3DWork(Workload):
         ring = 0 if self.args.slots_mode else ooc.FLAG_RING
         # the paper's slots with edge copies, with Prefetch and Cyclic, then
         # its two ablations; the ring-slab headline's other chain lengths and
-        # its downloads by copy kernel; float32 streaming of the same schedule
-        k3 = {"chain_steps": 3}
-        s2k3 = {"slots": 2, **k3}  # the longest chain whose skew slots can hold at this budget
-        return [("slots_edge_copies_chains_of_3", pf, s2k3), ("slots_no_prefetch_cyclic_chains_of_3", dl, s2k3),
-                ("slots_no_prefetch_no_cyclic_chains_of_3", dl, {"cyclic": False, **s2k3}),
-                ("chains_of_1_step", pf | ring, {"chain_steps": 1}),
-                ("chains_of_2_steps", pf | ring, {"chain_steps": 2}),
-                ("chains_of_3_steps", pf | ring, k3),
-                ("copy_kernel_downloads", (pf & ~dl) | ring, {}) if dl else
+        # its downloads by copy kernel; float32 streaming of the same
+        # schedule; the forms with stored primitives and stored gradients.
+        # (The default form keeps two copies of the conserved variables, so
+        # its chains span an even number of steps.)
+        q = self.fused == "q"
+        kk = {"chain_steps": 2 if q else 3}
+        s2 = {"slots": 2, **kk}  # slots hold the skew of chains this long at this budget
+        nm = "_chains_of_%d" % kk["chain_steps"]
+        out = [("slots_edge_copies" + nm, pf, s2), ("slots_no_prefetch_cyclic" + nm, dl, s2),
+               ("slots_no_prefetch_no_cyclic" + nm, dl, {"cyclic": False, **s2})]
+        out += [("chains_of_%d_steps" % k, pf | ring, {"chain_steps": k})
+                for k in ((2,) if q else (1, 2, 3)) if k != self.args.chain_steps]
+        out += [("copy_kernel_downloads", (pf & ~dl) | ring, {}) if dl else
                 ("runtime_copy_downloads", pf | ring | ooc.FLAG_MEMCPY_DOWNLOAD, {}),
                 ("fp32_stream", pf | ring | ooc.FLAG_FP32_STREAM, {})]
+        if q:
+            out += [("stored_primitives_form", pf | ring, {"fused": True}),
+                    ("stored_gradients_form_slots_24_planes_chains_of_3", pf,
+                     {"fused": False, "slots": 2, "chain_steps": 3, "tile_rows": 24})]
+        return out
 
     def warmup_steps(self, warmup, steps):
         """Untimed steps before the timed ones: at least one whole chain, and
@@ -578,7 +598,7 @@ def c5_main(args):
         from paper_1709_02125_amd import ns3d as N
         from paper_1709_02125_amd.inputs import tgv_initial_state
         n = args.n or 512
-        fused = "q" if args.prims_in_residual else not args.stored_gradients
+        fused = ns_form(args)
         ring = 0 if args.slots_mode else ooc.FLAG_RING
         budget = int(args.budget) if args.budget else N.footprint_bytes(n, fused) // 3
         # with two copies of the conserved variables a chain spans an even
@@ -766,9 +786,10 @@ def main():
     ap.add_argument("--ring", action="store_true", help="hydro proxies: ring slabs instead of slots")
     ap.add_argument("--cache-tiling", type=int, nargs="*", default=None,
                     help="also time the in-core run cut into tiles of these heights (cache blocking, no transfers)")
-    ap.add_argument("--prims-in-residual", action="store_true",
-                    help="ns3d: the residual kernel evaluates the primitives too (two copies of the conserved "
-                         "variables instead of the primitive fields; chains of an even number of steps)")
+    ap.add_argument("--stored-primitives", action="store_true",
+                    help="ns3d: the 15-field chain with a primitives loop and stored primitives (the default "
+                         "form evaluates them in the residual kernel from two copies of the conserved variables, "
+                         "which needs chains of an even number of steps)")
     ap.add_argument("--stored-gradients", action="store_true",
                     help="ns3d: the 27-field chain with a gradient loop and stored gradients (default: the "
                          "15-field chain whose residual evaluates the gradients itself)")
@@ -794,14 +815,19 @@ def main():
         return c5_main(args)
     if args.steps is None:  # ns3d: two whole chains
         args.steps = {"hydro2d": 20, "hydro3d": 10, "ns3d": 2 * args.chain_steps}[args.workload]
-    # ns3d runs on ring slabs with chains of 4 steps, the largest tile that
-    # fits and 3 slots: within 1 % of the fastest of the exhaustive sweep of
-    # this grid and budget (tile heights 8 .. largest, chains of 1 .. 4
-    # steps, 2 .. 4 slots; 2 slots 4 % slower, chains of 3 steps 2-5 %
-    # slower).  With stored gradients on slots, 24-plane tiles, chains of 3
-    # steps and 2 slots were the fastest.  The hydro proxies default to the
-    # largest tile and 3 slots.
+    # ns3d runs the form with the primitives and gradients evaluated in the
+    # residual kernel, on ring slabs with chains of 4 steps, the largest tile
+    # that fits and 3 slots (45 ms per step; 52 ms with 2 slots).  With stored
+    # primitives the same schedule was within 1 % of the fastest of the
+    # exhaustive sweep (tile heights 8 .. largest, chains of 1 .. 4 steps,
+    # 2 .. 4 slots); with stored gradients on slots, 24-plane tiles, chains
+    # of 3 steps and 2 slots were the fastest.  The hydro proxies default to
+    # the largest tile and 3 slots.
     ns = args.workload == "ns3d"
+    if ns and ns_form(args) == "q" and args.chain_steps % 2 and not args.no_cyclic:
+        print("the default ns3d form keeps two copies of the conserved variables: under Cyclic its chains "
+              "span an even number of steps (--chain-steps 2 or 4), or use --stored-primitives", file=sys.stderr)
+        sys.exit(2)
     if args.slots is None:
         args.slots = 3 if ns and not args.stored_gradients else (2 if ns else 0)
     if args.tile_rows is None:

@@ -91,8 +91,7 @@ enum {
                                  tiles in flight.  The rings are allocated by the library within
                                  the budget (the arena given to ooc_bind_device then only needs
                                  the reductions and resident fields, or may be NULL with 0 bytes:
-                                 the library allocates that too).  Each chain places its rows at
-                                 a ring origin of its own, chosen so that its first tiles wait
+                                 the library allocates that too).  A chain's first tiles wait
                                  only for the downloads of the previous chain's tiles whose ring
                                  positions they take.  Fixed at creation; OOC_E_ARG at the first
                                  flush if the device lacks the API. */

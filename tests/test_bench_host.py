@@ -20,7 +20,7 @@ def test_more_than_one_gpu_is_refused():
 def test_workloads_build_on_host(name, n):
     args = types.SimpleNamespace(n=n, budget=0, resident_geometry=False, resident_state=False, no_cyclic=False, chain_steps=3,
                                  tile_rows=0, slots=0, stored_gradients=False,
-                                 prims_in_residual=False)
+                                 stored_primitives=False)
     w = bench.WORKLOADS[name](args)
     assert w.cells > 0 and w.footprint > 0 and w.budget > 0
     assert name in w.describe()

@@ -165,8 +165,12 @@ def ns3d_oracle():
 
 
 NS_CONFIGS = [
-    # the benchmark's headline: 15-field chain (gradients inside the residual)
-    # on ring slabs, memcpy downloads, largest tiles, chains of 4 steps, 3 slots
+    # the benchmark's headline: 15-field chain (two copies of the conserved
+    # variables; primitives and gradients inside the residual) on ring slabs,
+    # memcpy downloads, largest tiles, chains of 4 steps, 3 slots
+    ("conserved-input residual, ring slabs, memcpy downloads, largest tiles, 4-step chains, 3 slots", "q",
+     ooc.FLAG_RING | ooc.FLAG_MEMCPY_DOWNLOAD, (0, 4, 3)),
+    # the same schedule with stored primitives
     ("fused residual, ring slabs, memcpy downloads, largest tiles, 4-step chains, 3 slots", True,
      ooc.FLAG_RING | ooc.FLAG_MEMCPY_DOWNLOAD, (0, 4, 3)),
     # its variant with stored gradients on slots with edge copies
@@ -174,7 +178,8 @@ NS_CONFIGS = [
 ]
 
 
-@pytest.mark.parametrize("what,fused,extra,sched", NS_CONFIGS, ids=["fused_ring", "stored_slots"])
+@pytest.mark.parametrize("what,fused,extra,sched", NS_CONFIGS, ids=["conserved_input_ring", "fused_ring",
+                                                                   "stored_slots"])
 def test_ns3d_512_10_steps_equals_oracle_and_in_core(ns3d_oracle, what, fused, extra, sched):
     n, steps = 512, 10
     ref = ns3d_oracle[10]
@@ -201,17 +206,17 @@ def test_ns3d_512_10_steps_equals_oracle_and_in_core(ns3d_oracle, what, fused, e
 
 
 def test_ns3d_512_fp32_stream_20_steps_error(ns3d_oracle):
-    # FP32 storage and transfer of the streamed fields on the schedule the
-    # cost model picks for the FP32 form (15-field chain on ring slabs,
-    # 16-plane tiles, chains of 4 steps, 2 slots): stated error per field
-    # against the FP64 oracle after 20 steps
+    # FP32 storage and transfer of the streamed fields in the benchmark's
+    # form and schedule (conserved-input residual on ring slabs, largest
+    # tiles, chains of 4 steps, 3 slots): stated error per field against the
+    # FP64 oracle after 20 steps
     n, steps = 512, 20
     ref = ns3d_oracle[20]
-    say("case: ns3d 512^3 FP32 streaming, third-of-footprint budget, ring slabs, 16-plane tiles, 4-step chains, "
+    say("case: ns3d 512^3 FP32 streaming, third-of-footprint budget, ring slabs, largest tiles, 4-step chains, "
         "20 steps")
-    app = N.NS3D(n, tgv_initial_state(n), budget=N.footprint_bytes(n, True) // 3,
-                 flags=ooc.FLAG_PREFETCH | ooc.FLAG_FP32_STREAM | ooc.FLAG_RING | ooc.FLAG_MEMCPY_DOWNLOAD, fused=True)
-    app.ctx.set_schedule(tile_rows=16, chain_steps=4, slots=2)
+    app = N.NS3D(n, tgv_initial_state(n), budget=N.footprint_bytes(n, "q") // 3,
+                 flags=ooc.FLAG_PREFETCH | ooc.FLAG_FP32_STREAM | ooc.FLAG_RING | ooc.FLAG_MEMCPY_DOWNLOAD, fused="q")
+    app.ctx.set_schedule(tile_rows=0, chain_steps=4, slots=3)
     app.initialise()
     app.run(steps)
     got = {q: app.interior(q) for q in N.Q}
