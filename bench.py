@@ -240,12 +240,13 @@ class NS3DWork(Workload):
         return out
 
     def warmup_steps(self, warmup, steps):
-        """Untimed steps before the timed ones: at least one whole chain, and
-        then the trailing partial chain the timed steps end with, so that
-        every chain shape the timed region runs has been planned and its
-        rings sized before it."""
+        """Untimed steps before the timed ones: at least two whole chains
+        (the first after another chain shape sizes the rings; the second
+        runs behind a chain of its own shape), and then the trailing partial
+        chain the timed steps end with, so that every chain shape the timed
+        region runs has been planned and its rings sized before it."""
         k = self.args.chain_steps
-        return -(-max(warmup, k) // k) * k + steps % k
+        return -(-max(warmup, 2 * k) // k) * k + steps % k
 
     def describe(self):
         form = {"q": "15 fields (two copies of the conserved variables; primitives and gradients evaluated in "
@@ -680,7 +681,7 @@ def c5_main(args):
     def run_sweep(fl, what, wl=workload, bud=budget):
         t = time.perf_counter()
         app, plan_ctx, q, cl, rb = wl(fl)
-        recs = tune.sweep(app, plan_ctx, q, cl, rb, bud, cands, chains=2,
+        recs = tune.sweep(app, plan_ctx, q, cl, rb, bud, cands, chains=3,
                           log=lambda m: log("%s sweep: %s" % (what, m)))
         app.close()
         del app

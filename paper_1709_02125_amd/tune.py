@@ -156,10 +156,13 @@ def transfer_regret(train_records, target_records, n_hidden=32, seed=1709, epoch
 
 def default_schedule(records):
     """The schedule the library uses without guidance: largest tile height
-    that fits (h = 0), one step per chain, 3 slots."""
-    for r in records:
-        if (r["h"], r["k"], r["S"]) == (0, 1, 3):
-            return r
+    that fits (h = 0), one step per chain, 3 slots -- or, where chains must
+    span an even number of steps (the Navier-Stokes form with two copies of
+    the conserved variables), two steps per chain."""
+    for key in ((0, 1, 3), (0, 2, 3)):
+        for r in records:
+            if (r["h"], r["k"], r["S"]) == key:
+                return r
     return None
 
 
