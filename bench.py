@@ -204,6 +204,8 @@ class NS3DWork(Workload):
         if incore:
             return N.NS3D(self.n, self.prims, budget=N.device_footprint_bytes(self.n, fused), flags=flags,
                           fused=fused)
+        if fused != self.fused and not self.args.budget:  # the other form's own third of its footprint
+            budget = N.footprint_bytes(self.n, fused) // 3
         app = N.NS3D(self.n, self.prims, budget=budget, flags=flags, fused=fused,
                      cyclic_after_init=opts.get("cyclic", not self.args.no_cyclic))
         app.ctx.set_schedule(tile_rows=opts.get("tile_rows", self.args.tile_rows),
@@ -581,11 +583,12 @@ def c5_main(args):
     of an exhaustive sweep of the FP64 form of the same grid (the schedule
     sweep configuration 4 records) and picks among the float32 form's
     schedules from their planned features alone; the exhaustive float32 sweep
-    that follows is its yardstick (regret) and fallback.  For hydro2d the
-    training set also holds a float32 sweep of a smaller grid (10240^2 at the
-    same oversubscription): the FP64 form is bound by its uploads whatever
-    the slot count, so its timings carry nothing of the float32 form's
-    download-to-upload slot dependence.  The picked schedule
+    that follows is its yardstick (regret) and fallback.  The training set
+    also holds a float32 sweep of a smaller grid at the same oversubscription
+    (hydro2d 10240^2, ns3d 384^3): the FP64 hydro2d form is bound by its
+    uploads whatever the slot count, and the FP64 ns3d form does not show
+    the float32 form's penalty for short tiles, so FP64 timings alone do not
+    carry what matters in float32.  The picked schedule
     then runs `--steps` steps from the initial state (the error of every state
     field against the FP64 oracle after those steps is stated) and, warmed,
     `--steps` more timed ones (the throughput)."""
@@ -632,7 +635,10 @@ def c5_main(args):
             return out
 
         got_state = lambda app: {x: app.interior(x) for x in names}
-        small = None
+        n_small = n * 3 // 4 // 32 * 32
+        small = (n_small, lambda fl: tune.ns3d_workload(n_small, N.footprint_bytes(n_small, fused) // 3, fl | ring | dl,
+                                                         fused=fused),
+                 N.footprint_bytes(n_small, fused) // 3)
         form = ("ns3d proxy %d^3 (Taylor-Green, Mach 0.1), %d fields, conserved fields stored and streamed as "
                 "float32, compute in FP64, %s, device budget %.3g B (1/3 of the FP64 fields)" %
                 (n, 15 if fused else 27, "ring slabs" if ring else "slots with edge copies", budget))
@@ -681,7 +687,7 @@ def c5_main(args):
     def run_sweep(fl, what, wl=workload, bud=budget):
         t = time.perf_counter()
         app, plan_ctx, q, cl, rb = wl(fl)
-        recs = tune.sweep(app, plan_ctx, q, cl, rb, bud, cands, chains=3,
+        recs = tune.sweep(app, plan_ctx, q, cl, rb, bud, cands, chains=3, repeats=2,
                           log=lambda m: log("%s sweep: %s" % (what, m)))
         app.close()
         del app
@@ -690,7 +696,7 @@ def c5_main(args):
         return recs
 
     train_fp64 = run_sweep(0, "FP64 (training)")
-    train_small = run_sweep(f32, "FP32 %d^2 (training)" % small[0], small[1], small[2]) if small else []
+    train_small = run_sweep(f32, "FP32 %d (training)" % small[0], small[1], small[2]) if small else []
     train = train_fp64 + train_small
     target = run_sweep(f32, "FP32 (yardstick)")
     picks = [tune.transfer_regret(train, target, seed=seed) for seed in (1709, 1, 2)]
@@ -740,7 +746,7 @@ def c5_main(args):
            "config": {"workload": form, "cells": cells, "schedule": {"tile_rows": h, "chain_steps": k, "slots": S},
                       "tiles": st["ntiles_last"],
                       "picked_by": "cost model trained on the FP64 sweep" +
-                                   (" and the FP32 sweep of %d^2" % small[0] if small else "")},
+                                   (" and the FP32 sweep at %d cells per axis" % small[0] if small else "")},
            "incore_value": inc_rate, "pct_of_incore": round(100.0 * rate / inc_rate, 2),
            "incore_ms_per_step": round(inc_sec / steps * 1e3, 3),
            "cost_model": {"picks": picks, "train_schedules": len(train), "target_schedules": len(target)},

@@ -69,16 +69,17 @@ def measure(app, cells, h, k, S, chains=2):
     return (time.perf_counter() - t0) / (cells * chains * k)
 
 
-def sweep(app, plan_ctx, queue_steps, cells, row_bytes, budget, candidates, chains=2, log=None):
+def sweep(app, plan_ctx, queue_steps, cells, row_bytes, budget, candidates, chains=2, log=None, repeats=1):
     """Exhaustive autotuner: features and measured time of every feasible
-    candidate.  Returns a list of records."""
+    candidate (the fastest of `repeats` measurements, which filters the
+    occasional chain whose downloads ran slow).  Returns a list of records."""
     recs = []
     for (h, k, S) in candidates:
         f = plan_features(plan_ctx, queue_steps, cells, row_bytes, budget, h, k, S)
         if f is None:
             continue
         try:
-            t = measure(app, cells, h, k, S, chains)
+            t = min(measure(app, cells, h, k, S, chains) for _ in range(repeats))
         except ooc.OocError as e:
             if e.code == ooc.E_BUDGET:
                 continue
@@ -215,7 +216,7 @@ def hydro2d_workload(n: int, budget: int, flags: int = 0, resident_geometry: boo
     return app, planner.ctx, queue_steps, n * n, row_bytes
 
 
-def ns3d_workload(n: int, budget: int, flags: int = 0, fused: bool = False):
+def ns3d_workload(n: int, budget: int, flags: int = 0, fused=False):
     """(live app, plan-only context, queue_steps, cells, row_bytes) for the
     Navier-Stokes proxy at n^3 (Taylor-Green input); fused: the 15-field
     chain whose residual evaluates the gradients itself."""
