@@ -840,9 +840,9 @@ void run_chain(ooc_ctx *c, const LoopRec *L, int n, int64_t prev_last_tile) {
   } else {
     if (hostargs.size() > c->argtab_cap) grow_argtab(c, 2 * hostargs.size());
     if (c->argtab_used + hostargs.size() > c->argtab_cap) {
-      // table full: a larger one (ring slabs cycle through several origins,
-      // each a chain of its own here) up to a limit, else wait until no
-      // kernel reads it and start over
+      // table full: a larger one up to a limit (chains that differ only in
+      // their slot phase or ring origins each have entries of their own),
+      // else wait until no kernel reads it and start over
       if (c->argtab_cap * sizeof(KArgs) < kArgTableMaxBytes) {
         grow_argtab(c, 2 * c->argtab_cap);
       } else {
