@@ -302,7 +302,12 @@ __global__ void __launch_bounds__(64 * PH) k_ns_rhs(const KArgs *__restrict__ ap
 // T, every derivative and every flux are the same expressions of the same
 // values as in k_ns_grads and k_ns_rhs, so the results are bit-identical to
 // the stored-gradient chain.
-constexpr int kFusedRows = 4;
+// Patches of 8 rows: a block of 512 threads (8 waves, the most that 2
+// waves/SIMD at 244 VGPRs allow) and 89 KB of LDS; against 4 rows the y-halo
+// columns' loads and primitives are shared by twice the points (conserved
+// input, ns3d 512^3: in core 34.3 against 35.2 ms per step, out of core 43.3
+// against 44.1 ms).
+constexpr int kFusedRows = 8;
 // planes of a fused z-segment at least: each segment re-reads 8 planes of
 // primitives, so a tile's short z-range (36 planes at ns3d 512^3 with
 // 4-step chains) runs as one segment (45.7 against 46.8 ms per step for
