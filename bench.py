@@ -463,10 +463,12 @@ def roofline_of(r, knames, where):
             "measured_in": where}
 
 
-def committed_traffic(kernel, workload):
+def committed_traffic(kernel, workload, alg_bytes_per_launch):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
-    used only while the kernel source still hashes to what was profiled."""
+    used only while the kernel source still hashes to what was profiled and
+    the launches process the same points (algorithmic bytes per launch within
+    0.1 %: another tile shape reads other halos)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "%s_%s_traffic.txt" % (kernel, workload))
     if not os.path.exists(path):
@@ -483,6 +485,9 @@ def committed_traffic(kernel, workload):
         want = kv.get(hkey)
         if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != want:
             return None
+    alg = float(kv.get("algorithmic_bytes_per_launch", 0))
+    if not alg or abs(alg - alg_bytes_per_launch) > 1e-3 * alg:
+        return None
     return float(kv["hbm_bytes_per_launch"])
 
 
@@ -939,7 +944,7 @@ def main():
 
     roofline = roofline_of(ooc_r, w.knames, "out-of-core timed steps")
     if roofline:
-        roofline["traffic"] = committed_traffic(roofline["kernel"], args.workload)
+        roofline["traffic"] = committed_traffic(roofline["kernel"], args.workload, roofline["bytes_per_launch"])
     incore_roofline = roofline_of(inc_r, w.knames, "in-core timed steps") if inc_r else None
     probe_h2d, probe_d2h = link_probe()
     both_h2d, both_d2h = link_both_probe()

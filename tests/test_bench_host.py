@@ -79,3 +79,18 @@ def test_benchmark_configurations_plan_as_measured():
         assert (p["ntiles"], p["tile_rows"]) == (tiles, rows)
         assert p["slots"] * p["slot_bytes"] <= budget
         app.close()
+
+
+def test_committed_traffic_only_for_the_profiled_launch_shape():
+    # the committed counter summaries match the current kernel sources and the
+    # benchmark plans' bytes per launch; another tile shape gets no traffic
+    for kernel, workload in (("h2d_pdv_corr", "hydro2d"), ("h3d_pdv_corr", "hydro3d"), ("ns_rhs_fusedq", "ns3d")):
+        kv = {}
+        for line in open(bench.os.path.join(bench.ROOT, "profiles", "%s_%s_traffic.txt" % (kernel, workload))):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        alg = int(kv["algorithmic_bytes_per_launch"])
+        assert bench.committed_traffic(kernel, workload, alg) == float(kv["hbm_bytes_per_launch"])
+        assert bench.committed_traffic(kernel, workload, alg * 1.01) is None
+    assert bench.committed_traffic("no_such_kernel", "ns3d", 1) is None
