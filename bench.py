@@ -790,7 +790,8 @@ def main():
     ap.add_argument("--no-incore", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--slots", type=int, default=None, help="slot count (default 3; ns3d with stored gradients: 2)")
-    ap.add_argument("--tile-rows", type=int, default=None, help="tile height (default: largest that fits; ns3d: 24)")
+    ap.add_argument("--tile-rows", type=int, default=None, help="tile height (default: the planner's, the largest that fits, "
+                         "on ring slabs the tallest whose chain boundaries stay clear; ns3d with stored gradients: 24)")
     ap.add_argument("--chain-steps", type=int, default=4, help="ns3d: time steps per chain")
     ap.add_argument("--slots-mode", action="store_true",
                     help="ns3d: the paper's per-tile slots with edge copies instead of ring slabs (the default "
