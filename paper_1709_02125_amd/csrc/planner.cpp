@@ -255,14 +255,19 @@ int make_plan(const PlanInput &in, Plan &P, std::string &err) {
   };
 
   // ---- skewed tiling for a given tile height
+  // The ragged remainder of the range goes to the first tile, not the last:
+  // the first tile already holds the chain's whole skew, and the last S
+  // tiles are what the next chain's first uploads wait for, so a short first
+  // tile and full last ones let those uploads overlap the last computes.
   auto tile_plan = [&](int64_t h, Plan &Q) -> uint64_t {
     const int T = (int)((R - L + h - 1) / h);
+    const int64_t lead = (int64_t)T * h - (R - L);  // rows the first tile lacks, 0 <= lead < h
     Q.T = T;
     Q.h = h;
     Q.e.assign((size_t)n * T, 0);
     for (int i = 0; i < n; i++) Q.e[(size_t)i * T + T - 1] = P.hi[i];
     for (int t = 0; t + 1 < T; t++) {
-      const int64_t cut = L + (int64_t)(t + 1) * h;
+      const int64_t cut = L + (int64_t)(t + 1) * h - lead;
       for (int i = n - 1; i >= 0; i--) {
         int64_t v = cut;
         for (int j = i + 1; j < n; j++) {

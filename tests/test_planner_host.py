@@ -118,11 +118,14 @@ def test_skew_closed_form_for_jacobi_chain():
                    [dat(dst, WRITE), dat(src, READ, (0, -1), (0, 0), (0, 1)), Const(1.0), Const(0.0)])
     p = c.debug_plan()
     e = p["loop_rows"][:, :, 1]
-    for t in range(p["ntiles"] - 1):
+    T = p["ntiles"]
+    assert T == -(-(ny + 2) // 10)
+    short = T * 10 - (ny + 2)  # the ragged remainder: the first tile is this much shorter
+    for t in range(T - 1):
         lead = e[:, t]
         if lead[0] < ny + 1:  # interior tiles, before the clamp at the range end
             assert list(np.diff(lead)) == [-1] * (k - 1)
-            assert lead[-1] == -1 + (t + 1) * 10  # cut: span start + (t+1) h
+            assert lead[-1] == -1 + (t + 1) * 10 - short  # cut: span start + (t+1) h - remainder
 
 
 @pytest.mark.parametrize("seed", range(12))
