@@ -829,8 +829,8 @@ def main():
     if args.steps is None:  # ns3d: two whole chains
         args.steps = {"hydro2d": 20, "hydro3d": 10, "ns3d": 2 * args.chain_steps}[args.workload]
     # ns3d runs the form with the primitives and gradients evaluated in the
-    # residual kernel, on ring slabs with chains of 4 steps, the largest tile
-    # that fits and 3 slots (45 ms per step; 52 ms with 2 slots).  With stored
+    # residual kernel, on ring slabs with chains of 4 steps, the planner's
+    # tile and 3 slots (42.5 ms per step over two chains).  With stored
     # primitives the same schedule was within 1 % of the fastest of the
     # exhaustive sweep (tile heights 8 .. largest, chains of 1 .. 4 steps,
     # 2 .. 4 slots); with stored gradients on slots, 24-plane tiles, chains
