@@ -708,7 +708,11 @@ def c5_main(args):
     for r in picks:
         log("cost model pick %s: regret %.3f, gain over default %s" % (r["pick"], r["regret"],
                                                                        r["gain_over_default"]))
-    h, k, S = picks[0]["pick"]
+    # the schedule run below: the pick of the three models together
+    ens = tune.ensemble_transfer_regret(train, target, seeds=(1709, 1, 2))
+    log("three-model cost model pick %s: regret %.3f, gain over default %s" % (ens["pick"], ens["regret"],
+                                                                               ens["gain_over_default"]))
+    h, k, S = ens["pick"]
 
     # the picked schedule from the initial state: error after `steps` steps,
     # then warmed, `steps` timed steps
@@ -754,7 +758,8 @@ def c5_main(args):
                                    (" and the FP32 sweep at %d cells per axis" % small[0] if small else "")},
            "incore_value": inc_rate, "pct_of_incore": round(100.0 * rate / inc_rate, 2),
            "incore_ms_per_step": round(inc_sec / steps * 1e3, 3),
-           "cost_model": {"picks": picks, "train_schedules": len(train), "target_schedules": len(target)},
+           "cost_model": {"picks": picks, "ensemble": ens, "train_schedules": len(train),
+                          "target_schedules": len(target)},
            "sweep_fp64": [{k_: r[k_] for k_ in ("h", "k", "S", "sec_per_cell_step")} for r in train_fp64],
            "sweep_fp32_small": [{k_: r[k_] for k_ in ("h", "k", "S", "sec_per_cell_step")} for r in train_small],
            "sweep_fp32": [{k_: r[k_] for k_ in ("h", "k", "S", "sec_per_cell_step")} for r in target],

@@ -155,6 +155,40 @@ def transfer_regret(train_records, target_records, n_hidden=32, seed=1709, epoch
             "gain_over_default": (d["sec_per_cell_step"] / t[(h, k, S)]) if d else None}
 
 
+def ensemble_transfer_regret(train_records, target_records, seeds=(1709, 1, 2), n_hidden=32, epochs=4000,
+                             lr=3e-3):
+    """As transfer_regret, with one cost model per seed: the pick minimises
+    the mean of their predicted log times, which steadies it against the
+    one initialisation that lands in a poor minimum of so few samples."""
+    keys = [(r["h"], r["k"], r["S"]) for r in target_records]
+    feats = [r["features"] for r in target_records]
+    logs = []
+    for seed in seeds:
+        model = CostModel(n_hidden=n_hidden, seed=seed)
+        try:
+            model.fit(train_records, epochs=epochs, lr=lr)
+            logs.append(np.log(model.predict(feats)))
+        finally:
+            model.close()
+    i, mean = ensemble_pick(logs)
+    h, k, S = keys[i]
+    t = {kk: r["sec_per_cell_step"] for kk, r in zip(keys, target_records)}
+    best = min(t, key=t.get)
+    d = default_schedule(target_records)
+    return {"seeds": list(seeds), "pick": [h, k, S], "predicted_sec_per_cell_step": float(np.exp(mean[i])),
+            "measured_sec_per_cell_step": t[(h, k, S)], "best": list(best), "best_sec_per_cell_step": t[best],
+            "regret": t[(h, k, S)] / t[best] - 1.0,
+            "gain_over_default": (d["sec_per_cell_step"] / t[(h, k, S)]) if d else None}
+
+
+def ensemble_pick(log_predictions):
+    """Index of the candidate with the lowest mean predicted log time over
+    the models (rows: models, columns: candidates; first index on ties), and
+    the means."""
+    mean = np.mean(np.asarray(log_predictions, dtype=np.float64), axis=0)
+    return int(np.argmin(mean)), mean
+
+
 def default_schedule(records):
     """The schedule the library uses without guidance: largest tile height
     that fits (h = 0), one step per chain, 3 slots -- or, where chains must

@@ -94,3 +94,14 @@ def test_committed_traffic_only_for_the_profiled_launch_shape():
         assert bench.committed_traffic(kernel, workload, alg) == float(kv["hbm_bytes_per_launch"])
         assert bench.committed_traffic(kernel, workload, alg * 1.01) is None
     assert bench.committed_traffic("no_such_kernel", "ns3d", 1) is None
+
+
+def test_ensemble_pick_minimises_the_mean_log_prediction():
+    from paper_1709_02125_amd import tune
+    import numpy as np
+    # model 0 alone would pick candidate 2, model 1 candidate 0; together
+    # candidate 1 has the lowest mean log time
+    logs = np.log([[4.0, 1.5, 1.0], [1.0, 1.5, 4.0]])
+    i, mean = tune.ensemble_pick(logs)
+    assert i == 1 and np.allclose(mean, (logs[0] + logs[1]) / 2)
+    assert tune.ensemble_pick(np.log([[1.0, 1.0]]))[0] == 0  # ties: the first
