@@ -218,8 +218,10 @@ int ooc_set_field(ooc_ctx *ctx, ooc_field f, const double *src, size_t bytes);
 int ooc_set_flags(ooc_ctx *ctx, uint32_t set, uint32_t clear);
 
 /* Schedule: tile height in rows of the tiled axis (0 = largest that fits the
- * budget), chain length in step marks (0 = whole flush), slot count (0 = 3,
- * the paper's three slots; 2..8 allowed). */
+ * budget; on ring slabs the tallest, down to 3/5 of it, whose chain
+ * boundaries stay clear), chain length in step marks (0 = whole flush), slot
+ * count (0 = 3, the paper's three slots; 2..8 allowed).  When the tile height
+ * does not divide the tiled range, the first tile takes the remainder. */
 int ooc_set_schedule(ooc_ctx *ctx, int64_t tile_rows, int chain_steps, int slots);
 
 int ooc_get_stats(ooc_ctx *ctx, ooc_stats *out);

@@ -11,7 +11,7 @@ TOL = 1e-12
 
 
 def test_hydro3d_tiled_matches_oracle_step_by_step():
-    # several z-tiles per chain with a ragged last tile; dt checked every step
+    # several z-tiles per chain with a ragged first tile; dt checked every step
     n, steps = (40, 36, 160), 4
     say("case: hydro3d 40x36x160 tiled 1/3 budget, dt per step")
     got, gdts, st, mass = gpu_hydro3d(n, steps, per_step_dt=True, flags=ooc.FLAG_PREFETCH)
